@@ -1,0 +1,82 @@
+"""Quadrature meshes on the Laplace variable (oracle side).
+
+Variable.  Eqs. 5-8 integrate over alpha with the kernel exp(-alpha p^2).  The
+oracle works with the dimensionless beta = 4 alpha / L^2, so that each 1-D
+factor becomes a function of beta alone (see tables.py).  The split point
+alpha_c of Eq. 7 becomes beta_c = 4 alpha_c / L^2; the default beta_c = 1 is
+the reading of the paper's "alpha_c = 1" that reproduces Table I.
+
+Interval 1, [0, beta_c]: Gauss-Legendre in beta (Eq. 12, first sum).
+
+Tail, [beta_c, inf): the substitution t = beta^{-1/2} of Eq. 11 maps it onto
+t in (0, beta_c^{-1/2}], where the integrand is a polynomial-like function of
+t (Eq. 10 power series).  Gauss-Legendre in t; each node goes back to
+beta = 1/t^2 with weight 2 w / t^3 from d beta = -2 t^{-3} dt (the
+back-transformation of Eq. 13, whose printed weight is garbled).
+
+Mesh 1 (Sec. III, Table I left): Q points on interval 1 and Q on the tail.
+Mesh 2 (Sec. III, Table I right): interval 1 cut at beta_c * 5^{-7}, ...,
+beta_c * 5^{-1}, q points on each of the 8 pieces, plus q_tail tail points
+(the tail count is not printed; 8 is the default).
+
+Nodes come from numpy's Legendre module (Golub-Welsch eigenvalues), not from
+the Newton iteration the library uses.
+"""
+import numpy as np
+
+
+def gauss_legendre(q: int, a: float, b: float):
+    """q-point Gauss-Legendre nodes and weights on [a, b] (FP64)."""
+    if q < 1:
+        raise ValueError("q must be >= 1")
+    x, w = np.polynomial.legendre.leggauss(q)
+    half = 0.5 * (b - a)
+    mid = 0.5 * (b + a)
+    return mid + half * x, half * w
+
+
+def _tail(q_tail: int, beta_c: float):
+    """Tail nodes: GL in t on (0, beta_c^{-1/2}], beta = 1/t^2, W = 2 w / t^3."""
+    t, w = gauss_legendre(q_tail, 0.0, beta_c ** -0.5)
+    return 1.0 / (t * t), 2.0 * w / (t * t * t)
+
+
+def mesh1(q: int, beta_c: float = 1.0):
+    """Mesh 1: q GL points on [0, beta_c] and q on the t-mapped tail (2q nodes).
+
+    Returns (beta, W, n_interval1): node positions, weights, and how many of
+    the leading nodes belong to interval 1.
+    """
+    b1, w1 = gauss_legendre(q, 0.0, beta_c)
+    b2, w2 = _tail(q, beta_c)
+    return np.concatenate([b1, b2]), np.concatenate([w1, w2]), q
+
+
+def mesh2(q_sub: int, q_tail: int = 8, n_sub: int = 8, ratio: float = 5.0,
+          beta_c: float = 1.0):
+    """Mesh 2: n_sub geometric pieces of [0, beta_c] times q_sub points, plus tail.
+
+    Piece edges are 0, beta_c * ratio^{-(n_sub-1)}, ..., beta_c * ratio^{-1},
+    beta_c (for the paper's 8 pieces and ratio 5: [0,5^-7], [5^-7,5^-6], ...,
+    [5^-1, 1]).  Returns (beta, W, n_interval1).
+    """
+    edges = [0.0] + [beta_c * ratio ** (-(n_sub - 1 - k)) for k in range(n_sub)]
+    bs, ws = [], []
+    for k in range(n_sub):
+        b, w = gauss_legendre(q_sub, edges[k], edges[k + 1])
+        bs.append(b)
+        ws.append(w)
+    b2, w2 = _tail(q_tail, beta_c)
+    bs.append(b2)
+    ws.append(w2)
+    return np.concatenate(bs), np.concatenate(ws), n_sub * q_sub
+
+
+def default_mesh(n_nodes: int, beta_c: float = 1.0):
+    """The default mapping of a node count Q to Mesh 2: Q = 8 q + 8.
+
+    8 geometric pieces with q = (Q - 8)/8 points each and an 8-point tail.
+    """
+    if n_nodes < 16 or n_nodes % 8:
+        raise ValueError("default mesh needs Q >= 16 and Q % 8 == 0")
+    return mesh2((n_nodes - 8) // 8, 8, 8, 5.0, beta_c)

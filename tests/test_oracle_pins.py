@@ -1,0 +1,339 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (Table I, the shell closings), closed forms (the unit-cube
+Coulomb constant, tau(beta; 0, 0)), brute-force integration of the defining
+integrals (tests/_brute.py), high-precision arithmetic (mpmath), exactness
+properties of Gauss quadrature, and invariants of the Coulomb integrals.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import _brute
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- basis ----
+
+def test_shell_closings_match_paper():
+    g = _gold("shell_closings.json")
+    counts = oracle.shell_counts(169)
+    assert [int(counts[r2]) for r2 in g["R2"]] == g["M"]
+
+
+def test_basis_sizes_and_order():
+    # independent count: per x, count (y, z) in the disk y^2 + z^2 <= r2 - x^2
+    def count(r2):
+        r = math.isqrt(r2)
+        return sum(1 for x in range(-r, r + 1) for y in range(-r, r + 1)
+                   for z in range(-r, r + 1) if x * x + y * y + z * z <= r2)
+    for r2, n in [(2, 19), (9, 123), (40, 1045), (169, 9171)]:
+        assert count(r2) == n
+        assert len(oracle.enumerate_basis(r2)) == n
+    b = oracle.enumerate_basis(40)
+    n2 = (b * b).sum(1)
+    assert np.all(np.diff(n2) >= 0)
+    assert len({tuple(v) for v in b}) == len(b)
+    assert tuple(b[0]) == (0, 0, 0)
+    # occupied sphere is an index prefix
+    assert np.array_equal(oracle.enumerate_basis(9), b[:123])
+
+
+# ----------------------------------------------------------------- mesh ----
+
+def _mp_gauss_legendre(q, dps=40):
+    """Roots of P_q polished by Newton in mpmath, weights 2/((1-x^2) P'_q^2)."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    x0 = np.polynomial.legendre.leggauss(q)[0]
+    xs, ws = [], []
+    for g in x0:
+        x = mp.mpf(g)
+        for _ in range(6):
+            p, dp = mp.legendre(q, x), mp.diff(lambda t: mp.legendre(q, t), x)
+            x -= p / dp
+        dp = mp.diff(lambda t: mp.legendre(q, t), x)
+        xs.append(x)
+        ws.append(2 / ((1 - x * x) * dp * dp))
+    return xs, ws
+
+
+@pytest.mark.parametrize("q", [5, 8, 11, 16])
+def test_gauss_legendre_against_mpmath_and_exactness(q):
+    x, w = oracle.gauss_legendre(q, -1.0, 1.0)
+    xm, wm = _mp_gauss_legendre(q)
+    # numpy's Golub-Welsch weights carry a few ulps of rounding
+    assert np.max(np.abs(x - np.array([float(v) for v in xm]))) < 4e-16
+    wm = np.array([float(v) for v in wm])
+    assert np.max(np.abs(w - wm) / wm) < 1e-14
+    a, b = 0.3, 2.7
+    x, w = oracle.gauss_legendre(q, a, b)
+    for k in range(2 * q):
+        exact = (b ** (k + 1) - a ** (k + 1)) / (k + 1)
+        assert abs((w * x ** k).sum() - exact) <= 4e-15 * max(1.0, abs(exact))
+
+
+@pytest.mark.parametrize("beta_c", [1.0, 0.37, 2.5])
+def test_mesh2_interval_and_tail_exactness(beta_c):
+    q, qt = 6, 8
+    beta, W, n1 = oracle.mesh2(q, qt, beta_c=beta_c)
+    assert len(beta) == 8 * q + qt and n1 == 8 * q
+    b1, w1 = beta[:n1], W[:n1]
+    assert np.all((b1 > 0) & (b1 < beta_c))
+    # geometric pieces: each piece integrates polynomials of degree <= 2q-1
+    assert abs(w1.sum() - beta_c) < 1e-15
+    for k in range(1, 2 * q):
+        exact = beta_c ** (k + 1) / (k + 1)
+        assert abs((w1 * b1 ** k).sum() - exact) < 1e-14 * max(1.0, exact)
+    # tail: Int_{beta_c}^inf beta^{-(n + 3/2)} d beta = beta_c^{-(n+1/2)} / (n + 1/2)
+    b2, w2 = beta[n1:], W[n1:]
+    assert np.all(b2 > beta_c)
+    for n in range(qt):
+        exact = beta_c ** (-(n + 0.5)) / (n + 0.5)
+        assert abs((w2 * b2 ** (-(n + 1.5))).sum() - exact) < 1e-13 * exact
+
+
+def test_mesh1_and_default_mesh_shapes():
+    beta, W, n1 = oracle.mesh1(90)
+    assert len(beta) == 180 and n1 == 90
+    beta, W, n1 = oracle.default_mesh(96)
+    assert len(beta) == 96 and n1 == 88
+    with pytest.raises(ValueError):
+        oracle.default_mesh(50)
+
+
+# --------------------------------------------------------------- tables ----
+
+def test_tau00_closed_form():
+    beta = np.array([1e-8, 6e-7, 1e-4, 0.03, 1.0, 7.5, 3e3, 4e7])
+    t = oracle.tau_table(beta, 0)[:, 0, 0]
+    ref = oracle.tau00_closed_form(beta)
+    assert np.max(np.abs(t - ref) / ref) < 1e-15
+
+
+@pytest.mark.parametrize("beta", [0.08, 0.5, 1.2, 10.0, 300.0])
+def test_tau_against_bruteforce_double_integral(beta):
+    K = 4
+    tab = oracle.tau_table([beta], K)[0]
+    scale = np.abs(tab).max()
+    for m in range(-3, 4):
+        for mp in range(-3, 4):
+            ref = _brute.tau2d(beta, m, mp)
+            assert abs(ref.imag) < 1e-15 * scale
+            assert abs(tab[m + K, mp + K] - ref.real) < 2e-15 * scale, (m, mp)
+
+
+def test_tau_against_mpmath_small_and_large_beta():
+    import mpmath as mp
+    mp.mp.dps = 40
+
+    def mp_tau(beta, m, mp_):
+        beta = mp.mpf(beta)
+        b = min(mp.mpf(1), 30 * mp.sqrt(beta))
+        pts = mp.linspace(0, b, 4 * (abs(m) + abs(mp_)) + 4)
+        s = m + mp_
+        if s == 0:
+            d = mp.quad(lambda u: (1 - u) * mp.exp(-u * u / beta) * mp.cos(2 * mp.pi * m * u), pts)
+            return 2 * d / mp.sqrt(beta)
+        S = lambda k: mp.quad(lambda u: mp.exp(-u * u / beta) * mp.sin(2 * mp.pi * k * u), pts)
+        return -(S(m) + S(mp_)) / (mp.pi * s * mp.sqrt(beta))
+
+    K = 26
+    for beta in (2e-7, 1e-3, 1e4):
+        tab = oracle.tau_table([beta], K)[0]
+        scale = np.abs(tab).max()
+        for m, mp_ in [(0, 0), (13, -13), (26, -26), (1, 2), (-7, 20), (25, 26), (-26, 3)]:
+            ref = float(mp_tau(beta, m, mp_))
+            assert abs(tab[m + K, mp_ + K] - ref) < 1e-15 * scale, (beta, m, mp_)
+
+
+def test_tau_limits():
+    K = 3
+    small = oracle.tau_table([1e-9], K)[0]
+    for m in range(-K, K + 1):
+        assert abs(small[m + K, -m + K] - math.sqrt(math.pi)) < 1e-3
+    off = small.copy()
+    for m in range(-K, K + 1):
+        off[m + K, -m + K] = 0.0
+    assert np.abs(off).max() < 1e-3
+    big = 1e8
+    large = oracle.tau_table([big], K)[0] * math.sqrt(big)
+    assert abs(large[K, K] - 1.0) < 1e-8
+    large[K, K] = 0.0
+    assert np.abs(large).max() < 1e-8
+
+
+def test_tau_symmetries():
+    K = 6
+    tab = oracle.tau_table([0.02, 1.0, 50.0], K)
+    assert np.allclose(tab, tab.transpose(0, 2, 1), rtol=0, atol=1e-16)
+    assert np.allclose(tab, tab[:, ::-1, ::-1], rtol=0, atol=1e-16)
+    # but not under (m, m') -> (-m, m')
+    assert np.abs(tab - tab[:, ::-1, :]).max() > 1e-3
+
+
+# --------------------------------------------------------- integrals --------
+
+@pytest.fixture(scope="module")
+def fine():
+    """Basis |n|^2 <= 2 (19 PW) with a fine Mesh 2 (8 x 14 + 16 nodes)."""
+    b = oracle.enumerate_basis(2)
+    beta, W, _ = oracle.mesh2(14, 16)
+    tau = oracle.tau_table(beta, 2)
+    return b, beta, W, tau
+
+
+def test_unit_cube_coulomb_constant(fine):
+    b, beta, W, tau = fine
+    c = oracle.reconstruct(tau, W, b, np.array([[0, 0, 0, 0], [3, 5, 3, 5]]))
+    assert abs(c[0] - oracle.k_cube()) < 2e-11 * oracle.k_cube()
+    assert c[0] == c[1]
+    # 1/L scaling with the beta-mesh (tables do not depend on L)
+    c2 = oracle.reconstruct(tau, W, b, np.array([[0, 0, 0, 0]]), L=2.5)
+    assert abs(c2[0] * 2.5 - c[0]) < 1e-15 * c[0]
+
+
+@pytest.mark.slow
+def test_integrals_against_bruteforce_6d(fine):
+    b, beta, W, tau = fine
+    quads = [(0, 0, 0, 0), (1, 2, 3, 4), (5, 1, 0, 7), (3, 3, 12, 18), (0, 6, 1, 2),
+             (7, 9, 11, 13), (18, 2, 4, 16)]
+    got = oracle.reconstruct(tau, W, b, np.array(quads))
+    for q, c in zip(quads, got):
+        ref = _brute.coulomb6d(*[b[x] for x in q], n=40)
+        assert abs(ref.imag) < 1e-14
+        assert abs(c - ref.real) < 1e-10 * max(abs(ref.real), 1e-3), (q, c, ref)
+
+
+def test_split_point_independence():
+    """The exact integral does not depend on where the Laplace range is split."""
+    b = oracle.enumerate_basis(2)
+    quads = np.array([[0, 0, 0, 0], [1, 2, 3, 4], [5, 1, 0, 7]])
+    vals = []
+    for bc in (0.5, 1.0, 2.0):
+        beta, W, _ = oracle.mesh2(14, 16, beta_c=bc)
+        vals.append(oracle.reconstruct(oracle.tau_table(beta, 2), W, b, quads))
+    vals = np.array(vals)
+    assert np.max(np.abs(vals - vals[1])) < 1e-10
+
+
+def test_convergence_in_node_count():
+    b = oracle.enumerate_basis(2)
+    quads = np.array([[0, 0, 0, 0], [1, 2, 3, 4], [5, 1, 0, 7], [7, 9, 11, 13]])
+    beta, W, _ = oracle.default_mesh(176)
+    ref = oracle.reconstruct(oracle.tau_table(beta, 2), W, b, quads)
+    errs = []
+    for Q in (32, 48, 64, 96, 128):
+        beta, W, _ = oracle.default_mesh(Q)
+        errs.append(np.abs(oracle.reconstruct(oracle.tau_table(beta, 2), W, b, quads) - ref).max())
+    assert all(errs[k + 1] < errs[k] for k in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-10
+
+
+def test_integral_symmetries_and_schwarz():
+    b = oracle.enumerate_basis(9)
+    N = len(b)
+    beta, W, _ = oracle.default_mesh(48)
+    tau = oracle.tau_table(beta, 6)
+    qs = workloads.uniform_quads(N, 400, seed=11)
+    i, j, k, l = qs.T
+    f = lambda a, b_, c, d: oracle.reconstruct(tau, W, b, np.stack([a, b_, c, d], 1))
+    v = f(i, j, k, l)
+    assert np.array_equal(v, f(j, i, l, k))
+    assert np.array_equal(v, f(k, l, i, j))
+    assert np.array_equal(v, f(l, k, j, i))
+    # i <-> k alone is not a symmetry
+    assert np.abs(v - f(k, j, i, l)).max() > 1e-4
+    # Schwarz: |<ij|kl>| <= sqrt(<ik|ki> <lj|jl>), exchange integrals positive
+    a, c = f(i, k, k, i), f(l, j, j, l)
+    assert np.all(a > 0) and np.all(c > 0)
+    assert np.all(np.abs(v) <= np.sqrt(a * c) * (1 + 1e-14))
+    # axis permutation and axis reflection of all four wavevectors
+    index = {tuple(x): n for n, x in enumerate(b)}
+    for tr in (lambda x: x[[1, 2, 0]], lambda x: x * np.array([1, -1, 1])):
+        mapped = np.array([[index[tuple(tr(b[x]))] for x in row] for row in qs[:100]])
+        w2 = oracle.reconstruct(tau, W, b, mapped)
+        assert np.max(np.abs(w2 - v[:100])) < 1e-15 * np.abs(v).max()
+
+
+def test_out_of_range_index_raises():
+    b = oracle.enumerate_basis(2)
+    beta, W, _ = oracle.default_mesh(16)
+    tau = oracle.tau_table(beta, 2)
+    with pytest.raises(IndexError):
+        oracle.reconstruct(tau, W, b, np.array([[0, 0, 0, 19]]))
+
+
+# -------------------------------------------------------------- energies ----
+
+def test_exchange_direct_equals_histogram_and_hartree_closed_form():
+    b = oracle.enumerate_basis(9)
+    occ = np.arange(123, dtype=np.int32)
+    beta, W, _ = oracle.default_mesh(48)
+    K = 6
+    tau = oracle.tau_table(beta, K)
+    diag = oracle.tau_diag(beta, K)
+    assert np.array_equal(diag, np.array([[tau[q, m + K, -m + K] for m in range(-K, K + 1)]
+                                           for q in range(len(beta))]))
+    for f in (None, workloads.occupations(123, seed=3)):
+        eh, ex = oracle.energies(tau, W, b, occ, f)
+        h, R = oracle.diff_histogram(b[occ], f)
+        ex2 = oracle.exchange_from_histogram(h, R, diag, W)
+        assert abs(ex - ex2) < 1e-13 * abs(ex)
+        fs = 123.0 if f is None else f.sum()
+        c0 = oracle.reconstruct(tau, W, b, np.array([[0, 0, 0, 0]]))[0]
+        assert abs(eh - 0.5 * fs * fs * c0) < 1e-13 * eh
+        assert ex < 0 and eh > 0
+    # dropping the i = j terms changes the energy visibly (they are included)
+    eh, ex = oracle.energies(tau, W, b, occ)
+    c0 = oracle.reconstruct(tau, W, b, np.array([[0, 0, 0, 0]]))[0]
+    assert abs((ex + 0.5 * 123 * c0) - ex) / abs(ex) > 0.02
+
+
+@pytest.mark.slow
+def test_table_one_reproduced():
+    """Sec. III, Table I: E_x / E_KS at M = 9171 for Mesh 1 and Mesh 2."""
+    g = _gold("table1.json")
+    b = oracle.enumerate_basis(g["n2occ"])
+    assert len(b) == g["M"]
+    h, R = oracle.diff_histogram(b)
+    eks = oracle.e_ks(g["M"])
+    tol = 1.5e-6
+    for q, (i1, tot) in g["mesh2"].items():
+        beta, W, n1 = oracle.mesh2(int(q), 8)
+        c = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W, per_node=True)
+        assert abs(c[:n1].sum() / eks - i1) < tol and abs(c.sum() / eks - tot) < tol
+    for Q, (i1, tot) in g["mesh1"].items():
+        beta, W, n1 = oracle.mesh1(int(Q))
+        c = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W, per_node=True)
+        assert abs(c[:n1].sum() / eks - i1) < tol and abs(c.sum() / eks - tot) < tol
+
+
+@pytest.mark.slow
+def test_exchange_ratio_tends_to_one_with_shell_size():
+    """Fig. 1 / Sec. III: E_x/E_KS rises with M and extrapolates linearly toward 1."""
+    g = _gold("shell_closings.json")
+    b = oracle.enumerate_basis(169)
+    beta, W, _ = oracle.mesh2(10, 8)
+    diag = oracle.tau_diag(beta, 26)
+    ratios = []
+    for M in g["M"]:
+        h, R = oracle.diff_histogram(b[:M])
+        ratios.append(oracle.exchange_from_histogram(h, R, diag, W) / oracle.e_ks(M))
+    ratios = np.array(ratios)
+    assert np.all(np.diff(ratios) > 0)
+    x = np.array(g["M"], dtype=float) ** (-1.0 / 3.0)
+    slope, icpt = np.polyfit(x[-5:], ratios[-5:], 1)
+    assert 0.99 < icpt < 1.0 and slope < 0
