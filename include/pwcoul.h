@@ -1,0 +1,206 @@
+/*
+ * pwcoul.h -- C ABI of libpwcoul, the MI355X (gfx950) library for two-electron
+ * Coulomb integrals over box planewaves reconstructed from O(N^{2/3})
+ * per-direction tables.
+ *
+ * Method (Pederson, arxiv 1502.08043):
+ *   basis       phi_n(r) = L^{-3/2} exp(2 pi i n.r / L), r in [0, L]^3, all
+ *               n in Z^3 with |n|^2 <= n2max (Sec. II, the cutoff on |I|).
+ *   integral    <ij|kl> = Int Int phi_i*(r) phi_j*(r') phi_k(r) phi_l(r')
+ *               / |r - r'| d^3r d^3r'   (Eq. 2; free-space Coulomb between
+ *               densities confined to the box; bra conjugated, i and k share r).
+ *   quadrature  Laplace transform of the Coulomb kernel, split at alpha_c,
+ *               t = alpha^{-1/2} on the tail, Gauss quadrature on both pieces
+ *               (Eqs. 5-13), giving Q nodes (beta_q, W_q) with
+ *               beta = 4 alpha / L^2 and
+ *                 <ij|kl> = (1/(sqrt(pi) L)) sum_q W_q
+ *                           tau_q(m_x, m'_x) tau_q(m_y, m'_y) tau_q(m_z, m'_z)
+ *               (Eq. 14), m = n_k - n_i, m' = n_l - n_j per direction.
+ *   table       tau_q(m, m') = beta_q^{-1/2} Int_0^1 Int_0^1
+ *               exp(-(xi - xi')^2 / beta_q) exp(2 pi i (m xi + m' xi')) dxi dxi'
+ *               (Eq. 8 after the p integral, reduced coordinates), one real
+ *               table of (4 nmax + 1)^2 entries per node serving all three
+ *               directions of the cube (Sec. III: planewave products are
+ *               planewaves, so only index differences matter).
+ *   energies    uniform electron gas, one spin channel (Sec. III):
+ *               E_H =  1/2 sum_{i,j} f_i f_j <ij|ij>,
+ *               E_x = -1/2 sum_{i,j} f_i f_j <ij|ji>  (i = j included).
+ *
+ * Conventions for every call:
+ *   - Units are atomic units, L in bohr.  Results scale as 1/L.
+ *   - Basis indices are 0-based in the canonical order: ascending
+ *     (|n|^2, n_x, n_y, n_z), so a Fermi sphere |n|^2 <= r2 is an index prefix.
+ *   - "d_" pointers are device (HBM) pointers on the current HIP device and
+ *     stay owned by the caller; "h_" pointers are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked async only enqueue work on it.
+ *   - No exception crosses the ABI.  Argument errors are returned at once and
+ *     nothing is enqueued.  Errors found by kernels (an index out of range)
+ *     set an error word in the table that pwc_sync() reports and clears; the
+ *     affected outputs are NaN and the others are valid.
+ *   - A table is immutable after creation and may be read from several
+ *     streams at once; pwc_table_destroy() must not race with its use.
+ */
+#ifndef PWCOUL_H
+#define PWCOUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Every entry point is exported; the library is built with hidden visibility. */
+#if defined(__GNUC__)
+#define PWC_API __attribute__((visibility("default")))
+#else
+#define PWC_API
+#endif
+
+typedef enum {
+    PWC_OK = 0,
+    PWC_ERR_ARG = 1,     /* invalid argument (null pointer, bad size, bad mesh) */
+    PWC_ERR_RANGE = 2,   /* a basis index outside [0, N) was seen by a kernel */
+    PWC_ERR_NOMEM = 3,   /* device or host allocation failed */
+    PWC_ERR_DEVICE = 4,  /* HIP runtime error */
+    PWC_ERR_BUSY = 5,    /* server: queue full or shutting down */
+    PWC_ERR_STATE = 6    /* server: unknown ticket, or object in the wrong state */
+} pwc_status;
+
+typedef enum {
+    PWC_FP64 = 0,   /* FP64 tables, FP64 node products and accumulation */
+    PWC_MIXED = 1   /* FP32 hi/lo split tables; node products and sums in
+                       float-float (error-free FP32 transformations), final
+                       scaling and energy reductions in FP64 */
+} pwc_precision;
+
+typedef enum {
+    PWC_MESH_GEOMETRIC = 0,    /* "Mesh 2" of Sec. III / Table I */
+    PWC_MESH_TWO_INTERVAL = 1  /* "Mesh 1" of Sec. III / Table I */
+} pwc_mesh_kind;
+
+/*
+ * Quadrature mesh on the Laplace variable (Eqs. 11-14, Sec. III).
+ * Interval 1 is [0, beta_c] with beta_c = 4 alpha_c / L^2; the tail
+ * [beta_c, inf) is integrated in t = beta^{-1/2} on (0, beta_c^{-1/2}] and
+ * each tail node maps back to beta = 1/t^2 with weight 2 w / t^3.
+ *   GEOMETRIC:    interval 1 is cut at beta_c * ratio^{-k}, k = n_sub-1 .. 1,
+ *                 into n_sub pieces with q_sub Gauss-Legendre points each;
+ *                 plus q_tail tail points.  Q = n_sub * q_sub + q_tail.
+ *                 Table I's Mesh 2 is n_sub = 8, ratio = 5.
+ *   TWO_INTERVAL: q_sub points on interval 1 and q_tail on the tail
+ *                 (Table I's Mesh 1 has q_sub = q_tail = Q).
+ * alpha_c <= 0 selects alpha_c = L^2 / 4, i.e. beta_c = 1 for every box: the
+ * tables are then independent of L and <ij|kl>(L) = <ij|kl>(1) / L exactly.
+ * This is the reading of the paper's "alpha_c = 1" that reproduces Table I.
+ * alpha_c > 0 is taken literally (fixed alpha_c in bohr^2).
+ */
+typedef struct {
+    int kind;        /* pwc_mesh_kind */
+    int n_sub;       /* GEOMETRIC: number of pieces of interval 1, 1..32 */
+    double ratio;    /* GEOMETRIC: ratio of successive piece edges, > 1 */
+    int q_sub;       /* Gauss-Legendre points per piece of interval 1, 1..256 */
+    int q_tail;      /* Gauss-Legendre points on the tail, 1..256 */
+    double alpha_c;  /* split point (bohr^2); <= 0 selects beta_c = 1 */
+} pwc_mesh;
+
+/* Maximum sizes accepted by pwc_table_create. */
+#define PWC_MAX_N2MAX 625    /* nmax <= 25, table dimension 4 nmax + 1 <= 101 */
+#define PWC_MAX_NODES 512
+
+typedef struct pwc_table pwc_table;
+
+/* Library version string (static storage). */
+PWC_API const char *pwc_version(void);
+
+/* Human-readable name of a status code (static storage, never NULL). */
+PWC_API const char *pwc_status_str(pwc_status s);
+
+/*
+ * Default mesh for a node count: GEOMETRIC with n_sub = 8, ratio = 5,
+ * q_tail = 8 and q_sub = (n_nodes - 8) / 8.  Requires n_nodes >= 16 and
+ * n_nodes % 8 == 0, else PWC_ERR_ARG.  Writes *out (host).
+ */
+PWC_API pwc_status pwc_mesh_default(int n_nodes, pwc_mesh *out);
+
+/* Number of nodes Q of a mesh; PWC_ERR_ARG if the mesh is invalid. */
+PWC_API pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes);
+
+/*
+ * Build the tables for a cube of side L > 0 and the basis |n|^2 <= n2max
+ * (1 <= n2max <= PWC_MAX_N2MAX) on the mesh `mesh` (NULL: the default mesh
+ * for n_nodes).  If mesh is given, n_nodes must be 0 or equal its node count.
+ * Basis, mesh and index maps are formed on the host in FP64; the 1-D
+ * primitives and every table layout are computed by HIP kernels on `stream`
+ * (FP64).  The call returns after the tables are complete.  The handle owns
+ * all of its device memory (see pwc_table_info) and must be released with
+ * pwc_table_destroy.  *out is NULL on failure.
+ */
+PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *mesh,
+                            void *stream, pwc_table **out);
+
+/* Free a table and its device memory.  NULL is accepted. */
+PWC_API pwc_status pwc_table_destroy(pwc_table *t);
+
+/*
+ * Sizes of a table: basis size N, nmax = floor(sqrt(n2max)), node count Q and
+ * the device bytes it holds.  Any output pointer may be NULL.
+ */
+PWC_API pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_nodes,
+                          size_t *device_bytes);
+
+/* Canonical basis vectors: h_n[3 * i + d] = n_d of basis function i (host). */
+PWC_API pwc_status pwc_basis(const pwc_table *t, int32_t *h_n);
+
+/* Mesh nodes beta_q and weights W_q, q = 0..Q-1 (host, FP64). */
+PWC_API pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_W);
+
+/*
+ * Copy the FP64 tables into the caller's device buffer, layout
+ * d_dst[(q * nd + (m + 2 nmax)) * nd + (m' + 2 nmax)] = tau_q(m, m'),
+ * nd = 4 nmax + 1, m, m' in [-2 nmax, 2 nmax].  Async on `stream`.
+ */
+PWC_API pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream);
+
+/*
+ * Reconstruct <ij|kl> (Eq. 14) for n quadruples.  d_quads is int32 [n][4]
+ * holding (i, j, k, l) per row, 16-byte aligned; d_out is double [n], 8-byte
+ * aligned.  Async on `stream`.  n = 0 is a no-op.  An index outside [0, N)
+ * makes that output NaN and sets the table's error word (see pwc_sync).
+ * p = PWC_FP64 or PWC_MIXED.
+ */
+PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n,
+                           double *d_out, pwc_precision p, void *stream);
+
+/*
+ * Uniform-electron-gas energies of one spin channel (Sec. III) for the M
+ * occupied orbitals d_occ (int32 basis indices [M]) with occupations d_f
+ * (double [M], NULL = all ones):
+ *   d_out[0] = E_H =  1/2 sum_{i,j} f_i f_j <ij|ij>
+ *   d_out[1] = E_x = -1/2 sum_{i,j} f_i f_j <ij|ji>
+ * Exchange integrals read only the diagonal entries tau_q(m, -m).  The pair
+ * sum visits each unordered pair once (the summand is symmetric in i, j) and
+ * reduces block partials in a fixed order, so results are bitwise
+ * reproducible.  Async on `stream`; d_out is double [2] on the device.
+ * M = 0 writes zeros.
+ */
+PWC_API pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                              int64_t M, pwc_precision p, double *d_out, void *stream);
+
+/* Same as pwc_energies_async, then waits and writes h_out[2] = {E_H, E_x}. */
+PWC_API pwc_status pwc_energies(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                        int64_t M, pwc_precision p, double *h_out, void *stream);
+
+/*
+ * Wait for `stream`, then report and clear the table's kernel error word:
+ * PWC_ERR_RANGE if any index seen since the last pwc_sync was out of range,
+ * PWC_ERR_DEVICE on a runtime error, else PWC_OK.
+ */
+PWC_API pwc_status pwc_sync(const pwc_table *t, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWCOUL_H */

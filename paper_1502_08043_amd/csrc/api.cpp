@@ -1,0 +1,327 @@
+// C ABI of libpwcoul: argument checks, table set-up and ownership, launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pwc_internal.h"
+
+using pwc::Table;
+
+namespace {
+
+pwc_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return PWC_OK;
+    if (e == hipErrorOutOfMemory) return PWC_ERR_NOMEM;
+    return PWC_ERR_DEVICE;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Choose the node chunking of a table whose entries take `row_bytes` bytes per
+// node in LDS (plus 8 bytes of weight per node): the fewest padded nodes
+// nchunk * c, c even, with the chunk inside the LDS budget.
+bool plan_chunks(int Q, size_t row_bytes, int *c_out, int *nchunk_out) {
+    int best_c = 0, best_n = 0;
+    long best_total = -1;
+    for (int n = 1; n <= Q; ++n) {
+        int c = (Q + n - 1) / n;
+        c += c & 1;
+        if (static_cast<size_t>(c) * (row_bytes + 8) > static_cast<size_t>(pwc::kLdsBudget)) continue;
+        const long total = static_cast<long>(c) * n;
+        if (best_total < 0 || total < best_total) {
+            best_total = total;
+            best_c = c;
+            best_n = n;
+        }
+        if (total == Q) break;
+    }
+    if (best_total < 0) return false;
+    *c_out = best_c;
+    *nchunk_out = best_n;
+    return true;
+}
+
+float2 split_hilo(double v) {
+    const float hi = static_cast<float>(v);
+    return make_float2(hi, static_cast<float>(v - static_cast<double>(hi)));
+}
+
+void free_table(Table &t) {
+    if (t.d_block) (void)hipFree(t.d_block);
+    t.d_block = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pwc_version(void) { return "pwcoul 0.1.0 (gfx950)"; }
+
+const char *pwc_status_str(pwc_status s) {
+    switch (s) {
+        case PWC_OK: return "ok";
+        case PWC_ERR_ARG: return "invalid argument";
+        case PWC_ERR_RANGE: return "index out of range";
+        case PWC_ERR_NOMEM: return "out of memory";
+        case PWC_ERR_DEVICE: return "HIP device error";
+        case PWC_ERR_BUSY: return "busy";
+        case PWC_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+pwc_status pwc_mesh_default(int n_nodes, pwc_mesh *out) {
+    if (!out || n_nodes < 16 || n_nodes % 8 != 0 || n_nodes > PWC_MAX_NODES) return PWC_ERR_ARG;
+    out->kind = PWC_MESH_GEOMETRIC;
+    out->n_sub = 8;
+    out->ratio = 5.0;
+    out->q_sub = (n_nodes - 8) / 8;
+    out->q_tail = 8;
+    out->alpha_c = 0.0;
+    return PWC_OK;
+}
+
+pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes) {
+    if (!mesh || !n_nodes) return PWC_ERR_ARG;
+    return pwc::mesh_valid(*mesh, n_nodes) ? PWC_OK : PWC_ERR_ARG;
+}
+
+pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *mesh, void *stream,
+                            pwc_table **out) {
+    if (!out) return PWC_ERR_ARG;
+    *out = nullptr;
+    if (!(L > 0.0) || !std::isfinite(L) || n2max < 1 || n2max > PWC_MAX_N2MAX) return PWC_ERR_ARG;
+    pwc_mesh m{};
+    if (mesh) {
+        int q = 0;
+        if (!pwc::mesh_valid(*mesh, &q)) return PWC_ERR_ARG;
+        if (n_nodes != 0 && n_nodes != q) return PWC_ERR_ARG;
+        m = *mesh;
+    } else if (pwc_mesh_default(n_nodes, &m) != PWC_OK) {
+        return PWC_ERR_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    pwc_table *h = new (std::nothrow) pwc_table;
+    if (!h) return PWC_ERR_NOMEM;
+    Table &t = h->t;
+    t.L = L;
+    t.n2max = n2max;
+    t.nmax = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
+    t.K = 2 * t.nmax;
+    t.nd = 2 * t.K + 1;
+    t.mesh = m;
+    t.h_basis = pwc::enumerate_basis(n2max);
+    t.N = static_cast<int64_t>(t.h_basis.size() / 3);
+    if (!pwc::build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) {
+        delete h;
+        return PWC_ERR_ARG;
+    }
+    t.Q = static_cast<int>(t.h_beta.size());
+    std::vector<int32_t> fold, reps;
+    pwc::build_fold(t.K, fold, reps);
+    t.fl.E = static_cast<int>(reps.size() / 2);
+    if (!plan_chunks(t.Q, static_cast<size_t>(t.fl.E) * 8, &t.fl.c, &t.fl.nchunk) ||
+        !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk)) {
+        delete h;
+        return PWC_ERR_ARG;
+    }
+    (void)hipGetDevice(&t.device);
+
+    const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E;
+    const size_t Qp = static_cast<size_t>(t.fl.c) * t.fl.nchunk;
+    const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
+    // Carve one allocation.
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const size_t o_basis = take(sizeof(int32_t) * t.N);
+    const size_t o_fold = take(sizeof(int32_t) * nd * nd);
+    const size_t o_reps = take(sizeof(int32_t) * reps.size());
+    const size_t o_beta = take(sizeof(double) * Q);
+    const size_t o_W = take(sizeof(double) * Q);
+    const size_t o_gl = take(sizeof(double) * 2 * pwc::kGlPanelPoints);
+    const size_t o_prim = take(sizeof(double) * Q * 2 * (K + 1));
+    const size_t o_tau = take(sizeof(double) * Q * nd * nd);
+    const size_t o_tauF = take(sizeof(double) * Qp * E);
+    const size_t o_tauHL = take(sizeof(float2) * Qp * E);
+    const size_t o_Wpad = take(sizeof(double) * Qp);
+    const size_t o_WHL = take(sizeof(float2) * Qp);
+    const size_t o_diag = take(sizeof(double) * Qd * (K + 1));
+    const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
+    const size_t o_Wdiag = take(sizeof(double) * Qd);
+    const size_t o_WdiagHL = take(sizeof(float2) * Qd);
+    const size_t o_err = take(sizeof(int) * 64);
+    t.bytes = off;
+    hipError_t e = hipMalloc(&t.d_block, t.bytes);
+    if (e != hipSuccess) {
+        delete h;
+        return from_hip(e);
+    }
+    char *base = static_cast<char *>(t.d_block);
+    t.d_basis = reinterpret_cast<int32_t *>(base + o_basis);
+    t.d_fold = reinterpret_cast<int32_t *>(base + o_fold);
+    t.d_reps = reinterpret_cast<int32_t *>(base + o_reps);
+    t.d_beta = reinterpret_cast<double *>(base + o_beta);
+    t.d_W = reinterpret_cast<double *>(base + o_W);
+    t.d_gl = reinterpret_cast<double *>(base + o_gl);
+    t.d_prim = reinterpret_cast<double *>(base + o_prim);
+    t.d_tau = reinterpret_cast<double *>(base + o_tau);
+    t.d_tauF = reinterpret_cast<double *>(base + o_tauF);
+    t.d_tauHL = reinterpret_cast<float2 *>(base + o_tauHL);
+    t.d_Wpad = reinterpret_cast<double *>(base + o_Wpad);
+    t.d_WHL = reinterpret_cast<float2 *>(base + o_WHL);
+    t.d_diag = reinterpret_cast<double *>(base + o_diag);
+    t.d_diagHL = reinterpret_cast<float2 *>(base + o_diagHL);
+    t.d_Wdiag = reinterpret_cast<double *>(base + o_Wdiag);
+    t.d_WdiagHL = reinterpret_cast<float2 *>(base + o_WdiagHL);
+    t.d_err = reinterpret_cast<int *>(base + o_err);
+
+    // Host-side inputs of the table kernels.
+    std::vector<int32_t> packed(t.N);
+    for (int64_t i = 0; i < t.N; ++i) {
+        const int x = t.h_basis[3 * i], y = t.h_basis[3 * i + 1], z = t.h_basis[3 * i + 2];
+        packed[i] = static_cast<int32_t>((static_cast<uint32_t>(x) & 0xffu) |
+                                         ((static_cast<uint32_t>(y) & 0xffu) << 8) |
+                                         ((static_cast<uint32_t>(z) & 0xffu) << 16));
+    }
+    std::vector<double> glx, glw, gl;
+    pwc::gauss_legendre(pwc::kGlPanelPoints, 0.0, 1.0, glx, glw);
+    gl = glx;
+    gl.insert(gl.end(), glw.begin(), glw.end());
+    std::vector<double> Wpad(Qp, 0.0), Wdiag(Qd, 0.0);
+    std::vector<float2> WHL(Qp, make_float2(0.f, 0.f)), WdiagHL(Qd, make_float2(0.f, 0.f));
+    // Chunk-local node order equals global node order: node q sits at
+    // chunk q / c, slot q % c; padded slots carry zero weight.
+    for (int q = 0; q < Q; ++q) {
+        Wpad[q] = t.h_W[q];
+        WHL[q] = split_hilo(t.h_W[q]);
+        Wdiag[q] = t.h_W[q];
+        WdiagHL[q] = split_hilo(t.h_W[q]);
+    }
+
+    pwc_status st = PWC_OK;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (st == PWC_OK && bytes)
+            st = from_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    };
+    // Padding slots of the node-chunked layouts must read as zero.
+    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_tauF, 0, o_Wdiag - o_tauF, s));
+    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_err, 0, sizeof(int) * 64, s));
+    up(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
+    up(t.d_fold, fold.data(), sizeof(int32_t) * fold.size());
+    up(t.d_reps, reps.data(), sizeof(int32_t) * reps.size());
+    up(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
+    up(t.d_W, t.h_W.data(), sizeof(double) * Q);
+    up(t.d_gl, gl.data(), sizeof(double) * gl.size());
+    up(t.d_Wpad, Wpad.data(), sizeof(double) * Qp);
+    up(t.d_WHL, WHL.data(), sizeof(float2) * Qp);
+    up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
+    up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
+    if (st == PWC_OK) st = from_hip(pwc::launch_table_build(t, s));
+    // The host staging vectors die with this frame: wait for the stream.
+    const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
+    if (st == PWC_OK) st = st_sync;
+    if (st != PWC_OK) {
+        free_table(t);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_destroy(pwc_table *t) {
+    if (!t) return PWC_OK;
+    free_table(t->t);
+    delete t;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_nodes,
+                          size_t *device_bytes) {
+    if (!t) return PWC_ERR_ARG;
+    if (N) *N = t->t.N;
+    if (nmax) *nmax = t->t.nmax;
+    if (n_nodes) *n_nodes = t->t.Q;
+    if (device_bytes) *device_bytes = t->t.bytes;
+    return PWC_OK;
+}
+
+pwc_status pwc_basis(const pwc_table *t, int32_t *h_n) {
+    if (!t || !h_n) return PWC_ERR_ARG;
+    std::memcpy(h_n, t->t.h_basis.data(), sizeof(int32_t) * t->t.h_basis.size());
+    return PWC_OK;
+}
+
+pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_W) {
+    if (!t || !h_beta || !h_W) return PWC_ERR_ARG;
+    std::memcpy(h_beta, t->t.h_beta.data(), sizeof(double) * t->t.Q);
+    std::memcpy(h_W, t->t.h_W.data(), sizeof(double) * t->t.Q);
+    return PWC_OK;
+}
+
+pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
+    if (!t || !d_dst) return PWC_ERR_ARG;
+    const size_t bytes = sizeof(double) * t->t.Q * t->t.nd * t->t.nd;
+    return from_hip(hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n, double *d_out,
+                           pwc_precision p, void *stream) {
+    if (!t || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (n == 0) return PWC_OK;
+    if (!d_quads || !d_out) return PWC_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
+        return PWC_ERR_ARG;
+    return from_hip(pwc::launch_reconstruct(t->t, d_quads, n, d_out, p,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                              int64_t M, pwc_precision p, double *d_out, void *stream) {
+    if (!t || !d_out || M < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (M > 0 && !d_occ) return PWC_ERR_ARG;
+    if (M > (1 << 17)) return PWC_ERR_ARG;   // pair-tile grid (M/32)^2 workgroups
+    if ((reinterpret_cast<uintptr_t>(d_out) & 7) || (d_f && (reinterpret_cast<uintptr_t>(d_f) & 7)))
+        return PWC_ERR_ARG;
+    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, d_out,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+pwc_status pwc_energies(const pwc_table *t, const int32_t *d_occ, const double *d_f, int64_t M,
+                        pwc_precision p, double *h_out, void *stream) {
+    if (!t || !h_out) return PWC_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *d_out = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&d_out), 2 * sizeof(double), s);
+    if (e != hipSuccess) return from_hip(e);
+    pwc_status st = pwc_energies_async(t, d_occ, d_f, M, p, d_out, stream);
+    if (st == PWC_OK) st = from_hip(hipMemcpyAsync(h_out, d_out, 2 * sizeof(double),
+                                                   hipMemcpyDeviceToHost, s));
+    (void)hipFreeAsync(d_out, s);
+    const pwc_status st2 = from_hip(hipStreamSynchronize(s));
+    if (st != PWC_OK) return st;
+    if (st2 != PWC_OK) return st2;
+    return pwc_sync(t, stream);
+}
+
+pwc_status pwc_sync(const pwc_table *t, void *stream) {
+    if (!t) return PWC_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, t->t.d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return from_hip(e);
+    if (flag) {
+        const int zero = 0;
+        e = hipMemcpyAsync(t->t.d_err, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return from_hip(e);
+        return PWC_ERR_RANGE;
+    }
+    return PWC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host API and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "pwcoul.h"
+
+namespace pwc {
+
+// ---------------------------------------------------------------- host ----
+
+// Canonical planewave basis |n|^2 <= n2max, ascending (|n|^2, nx, ny, nz).
+std::vector<int32_t> enumerate_basis(int n2max);
+
+// q-point Gauss-Legendre rule on [a, b] (Newton iteration on the Legendre
+// three-term recurrence), nodes ascending.
+void gauss_legendre(int q, double a, double b, std::vector<double> &x, std::vector<double> &w);
+
+// Quadrature nodes and weights in beta = 4 alpha / L^2 for a mesh; also
+// returns how many leading nodes lie in interval 1.  false if invalid.
+bool build_mesh(const pwc_mesh &m, double L, std::vector<double> &beta,
+                std::vector<double> &W, int *n_interval1);
+
+bool mesh_valid(const pwc_mesh &m, int *n_nodes);
+
+// Symmetry fold of the (m, m') plane: tau(m, m') = tau(m', m) = tau(-m, -m').
+// fold[(m + K) * nd + (m' + K)] = index of the orbit representative, and
+// reps[2 * e], reps[2 * e + 1] = (m, m') of representative e.
+void build_fold(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps);
+
+// ------------------------------------------------------------- kernels ----
+
+// LDS budget of one table-streaming workgroup: two workgroups share a CU.
+constexpr int kLdsBudget = 80 * 1024;
+constexpr int kGlPanelPoints = 16;    // Gauss-Legendre points per panel
+constexpr int kGlPanels = 128;        // panels over the Gaussian's support
+
+struct FoldLayout {
+    int E = 0;        // folded entries per node
+    int c = 0;        // nodes per LDS chunk (even)
+    int nchunk = 0;   // chunks; nodes padded to nchunk * c with zero weight
+};
+
+struct DiagLayout {
+    int c = 0;        // nodes per LDS chunk of the diagonal table
+    int nchunk = 0;
+};
+
+struct Table {
+    double L = 0.0;
+    int n2max = 0, nmax = 0, K = 0, nd = 0, Q = 0;
+    int64_t N = 0;
+    int n_interval1 = 0;
+    pwc_mesh mesh{};
+    std::vector<int32_t> h_basis;   // [N][3]
+    std::vector<double> h_beta, h_W;
+    FoldLayout fl;
+    DiagLayout dl;
+    int device = 0;
+
+    // device memory (one allocation, carved)
+    void *d_block = nullptr;
+    size_t bytes = 0;
+    int32_t *d_basis = nullptr;     // [N] packed (x, y, z) as int8 lanes of an int32
+    int32_t *d_fold = nullptr;      // [nd * nd]
+    int32_t *d_reps = nullptr;      // [E][2]
+    double *d_beta = nullptr;       // [Q]
+    double *d_W = nullptr;          // [Q]
+    double *d_gl = nullptr;         // [2][kGlPanelPoints] panel rule on [0, 1]
+    double *d_prim = nullptr;       // [Q][2][K + 1]  (S, D)
+    double *d_tau = nullptr;        // [Q][nd][nd]
+    double *d_tauF = nullptr;       // [nchunk][E][c]         folded FP64
+    float2 *d_tauHL = nullptr;      // [nchunk][E][c]         folded (hi, lo)
+    double *d_Wpad = nullptr;       // [nchunk * c]
+    float2 *d_WHL = nullptr;        // [nchunk * c]
+    double *d_diag = nullptr;       // [dl.nchunk][K + 1][dl.c]  tau_q(m, -m), m >= 0
+    float2 *d_diagHL = nullptr;     // same, (hi, lo)
+    double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]
+    float2 *d_WdiagHL = nullptr;
+    int *d_err = nullptr;           // kernel error word
+};
+
+// table_kernels.hip
+hipError_t launch_table_build(Table &t, hipStream_t s);
+// reconstruct_kernels.hip
+hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
+                              double *d_out, pwc_precision p, hipStream_t s);
+// pairsum_kernels.hip
+hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,
+                           int64_t M, pwc_precision p, double *d_out, hipStream_t s);
+
+}  // namespace pwc
+
+struct pwc_table {
+    pwc::Table t;
+};

@@ -1,0 +1,141 @@
+// Table construction on the GPU (FP64): the 1-D integrals of Eq. 8 for
+// planewave factors at every quadrature node, and the layouts the hot
+// kernels read.
+//
+// For one direction, with m = n_k - n_i, m' = n_l - n_j and s = m + m',
+//   tau_q(m, m') = 2 beta^{-1/2} D(m)                          if s = 0,
+//                = -(S(m) + S(m')) / (pi s beta^{1/2})          otherwise,
+//   S(m) = Int_0^1 exp(-u^2/beta) sin(2 pi m u) du   (odd in m),
+//   D(m) = Int_0^1 (1 - u) exp(-u^2/beta) cos(2 pi m u) du   (even in m),
+// which follows from substituting u = xi - xi' in the double integral
+// beta^{-1/2} Int Int exp(-(xi-xi')^2/beta) exp(2 pi i (m xi + m' xi')).
+// S and D are integrated by composite Gauss-Legendre (kGlPanels panels of
+// kGlPanelPoints points) over [0, min(1, 8 beta^{1/2})]; past that point the
+// Gaussian is below e^{-64}.  D is integrated directly: the integration-by-
+// parts shortcut through S cancels catastrophically at large beta.
+#include <cmath>
+
+#include "pwc_internal.h"
+
+namespace pwc {
+namespace {
+
+constexpr int kThreads = 256;
+
+// sin(2 pi m u) and cos(2 pi m u) with the product 2 m u carried to double
+// the working precision, so the phase is exact to rounding at large m.
+__device__ inline void sincos_2pi_mu(int m, double u, double *s, double *c) {
+    const double a = 2.0 * m * u;
+    const double da = fma(2.0 * m, u, -a);   // exact remainder of the product
+    double sa, ca;
+    sincospi(a, &sa, &ca);
+    const double pda = M_PI * da;
+    *s = fma(pda, ca, sa);
+    *c = fma(-pda, sa, ca);
+}
+
+__global__ __launch_bounds__(kThreads) void k_prim(const double *__restrict__ beta,
+                                                  const double *__restrict__ gl, int K,
+                                                  double *__restrict__ prim) {
+    const int m = blockIdx.x;
+    const int q = blockIdx.y;
+    const double b = beta[q];
+    const double up = fmin(1.0, 8.0 * sqrt(b));
+    const double h = up / kGlPanels;
+    double s = 0.0, d = 0.0;
+    for (int p = threadIdx.x; p < kGlPanels * kGlPanelPoints; p += kThreads) {
+        const int panel = p / kGlPanelPoints, k = p % kGlPanelPoints;
+        const double u = (panel + gl[k]) * h;
+        const double wt = gl[kGlPanelPoints + k] * h;
+        const double g = exp(-(u * u) / b);
+        double sn, cs;
+        sincos_2pi_mu(m, u, &sn, &cs);
+        s = fma(wt * g, sn, s);
+        d = fma(wt * (1.0 - u) * g, cs, d);
+    }
+    // Fixed-order tree reduction over the block.
+    __shared__ double rs[kThreads], rd[kThreads];
+    rs[threadIdx.x] = s;
+    rd[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+            rd[threadIdx.x] += rd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        prim[(static_cast<size_t>(q) * 2 + 0) * (K + 1) + m] = (m == 0) ? 0.0 : rs[0];
+        prim[(static_cast<size_t>(q) * 2 + 1) * (K + 1) + m] = rd[0];
+    }
+}
+
+__device__ inline float2 split_hilo(double v) {
+    const float hi = static_cast<float>(v);
+    const float lo = static_cast<float>(v - static_cast<double>(hi));
+    return make_float2(hi, lo);
+}
+
+struct AsmArgs {
+    const double *beta;
+    const double *prim;
+    const int32_t *fold;
+    const int32_t *reps;
+    int K, nd, E, c, dc;
+    double *tau;
+    double *tauF;
+    float2 *tauHL;
+    double *diag;
+    float2 *diagHL;
+};
+
+__global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    const int q = blockIdx.y;
+    if (e >= a.nd * a.nd) return;
+    const int row = e / a.nd, col = e % a.nd;
+    const int m = row - a.K, mp = col - a.K;
+    const double *S = a.prim + static_cast<size_t>(q) * 2 * (a.K + 1);
+    const double *D = S + (a.K + 1);
+    const double rb = sqrt(a.beta[q]);
+    const int s = m + mp;
+    double v;
+    if (s == 0) {
+        v = 2.0 / rb * D[m < 0 ? -m : m];
+    } else {
+        const double sm = m < 0 ? -S[-m] : S[m];
+        const double smp = mp < 0 ? -S[-mp] : S[mp];
+        v = -(sm + smp) / (M_PI * s * rb);
+    }
+    a.tau[(static_cast<size_t>(q) * a.nd + row) * a.nd + col] = v;
+    // Folded layout: only the orbit representative writes its slot.
+    const int f = a.fold[e];
+    if (a.reps[2 * f] == m && a.reps[2 * f + 1] == mp) {
+        const size_t idx = (static_cast<size_t>(q / a.c) * a.E + f) * a.c + (q % a.c);
+        a.tauF[idx] = v;
+        a.tauHL[idx] = split_hilo(v);
+    }
+    // Diagonal tau(m, -m) for m >= 0 (the exchange entries; even in m).
+    if (s == 0 && m >= 0) {
+        const size_t idx = (static_cast<size_t>(q / a.dc) * (a.K + 1) + m) * a.dc + (q % a.dc);
+        a.diag[idx] = v;
+        a.diagHL[idx] = split_hilo(v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_table_build(Table &t, hipStream_t s) {
+    dim3 gp(t.K + 1, t.Q);
+    hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    AsmArgs a{t.d_beta, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.c, t.dl.c,
+              t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
+    dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q);
+    hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pwc

@@ -1,0 +1,94 @@
+"""The C ABI library loads and exports every entry point declared in include/*.h.
+
+CPU only: nothing here launches a kernel.  Argument checks that return before
+any device work are exercised too.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+LIB = os.path.join(ROOT, "paper_1502_08043_amd", "libpwcoul.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1502_08043_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(pwc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_api():
+    names = declared_symbols()
+    for n in ("pwc_table_create", "pwc_reconstruct", "pwc_energies", "pwc_sync"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls(lib):
+    lib.pwc_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.pwc_version()
+    lib.pwc_status_str.restype = ctypes.c_char_p
+    assert lib.pwc_status_str(2) == b"index out of range"
+    assert lib.pwc_status_str(99) == b"unknown status"
+
+    class Mesh(ctypes.Structure):
+        _fields_ = [("kind", ctypes.c_int), ("n_sub", ctypes.c_int), ("ratio", ctypes.c_double),
+                    ("q_sub", ctypes.c_int), ("q_tail", ctypes.c_int), ("alpha_c", ctypes.c_double)]
+
+    m = Mesh()
+    assert lib.pwc_mesh_default(96, ctypes.byref(m)) == 0
+    assert (m.kind, m.n_sub, m.ratio, m.q_sub, m.q_tail) == (0, 8, 5.0, 11, 8)
+    q = ctypes.c_int()
+    assert lib.pwc_mesh_count(ctypes.byref(m), ctypes.byref(q)) == 0 and q.value == 96
+    assert lib.pwc_mesh_default(50, ctypes.byref(m)) == 1
+    bad = Mesh(0, 8, 1.0, 5, 8, 0.0)           # ratio must exceed 1
+    assert lib.pwc_mesh_count(ctypes.byref(bad), ctypes.byref(q)) == 1
+    mesh1 = Mesh(1, 1, 5.0, 90, 90, 0.0)
+    assert lib.pwc_mesh_count(ctypes.byref(mesh1), ctypes.byref(q)) == 0 and q.value == 180
+
+
+def test_create_rejects_bad_arguments_before_device_work(lib):
+    lib.pwc_table_create.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    assert lib.pwc_table_create(0.0, 9, 48, None, None, ctypes.byref(h)) == 1      # L <= 0
+    assert lib.pwc_table_create(-1.0, 9, 48, None, None, ctypes.byref(h)) == 1
+    assert lib.pwc_table_create(1.0, 0, 48, None, None, ctypes.byref(h)) == 1      # n2max < 1
+    assert lib.pwc_table_create(1.0, 626, 48, None, None, ctypes.byref(h)) == 1    # too large
+    assert lib.pwc_table_create(1.0, 9, 50, None, None, ctypes.byref(h)) == 1      # Q % 8
+    assert lib.pwc_table_create(1.0, 9, 48, None, None, None) == 1
+    assert h.value is None
+    lib.pwc_reconstruct.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p,
+                                                            ctypes.c_int, ctypes.c_void_p]
+    assert lib.pwc_reconstruct(None, None, 0, None, 0, None) == 1
+    lib.pwc_sync.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.pwc_sync(None, None) == 1
+    lib.pwc_table_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.pwc_table_destroy(None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_1502_08043_amd as pw
+    monkeypatch.setattr(pw, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pw, "_lib", None)
+    with pytest.raises(ImportError):
+        pw.lib()

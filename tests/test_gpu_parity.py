@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pw():
+    import torch
+    import paper_1502_08043_amd as pw
+    assert torch.cuda.is_available()
+    pw.lib()
+    return pw
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.fixture(scope="module")
+def tables(pw):
+    made = {}
+
+    def get(n2max, n_nodes, L=1.0):
+        key = (n2max, n_nodes, L)
+        if key not in made:
+            say(f"[parity] table n2max={n2max} Q={n_nodes} L={L}")
+            made[key] = pw.Table(L, n2max, n_nodes)
+        return made[key]
+    yield get
+    for t in made.values():
+        t.close()
+
+
+# ---------------------------------------------------------------- tables ----
+
+@pytest.mark.parametrize("n2max,Q", [(2, 16), (9, 48), (40, 64), (169, 96), (400, 128)])
+def test_tables_basis_mesh_match_oracle(pw, tables, n2max, Q):
+    t = tables(n2max, Q)
+    o = P.setup(n2max, Q)
+    assert np.array_equal(t.basis(), o["basis"])
+    beta, W = t.mesh_nodes()
+    assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 1e-14
+    assert np.max(np.abs(W - o["W"]) / o["W"]) < 1e-13   # oracle weights: numpy leggauss
+    tau = t.copy_tables().cpu().numpy()
+    assert tau.shape == o["tau"].shape
+    scale = np.abs(o["tau"]).max(axis=(1, 2))
+    err = (np.abs(tau - o["tau"]).max(axis=(1, 2)) / scale).max()
+    say(f"[parity] tables n2max={n2max} Q={Q}: worst err / node max = {err:.2e}")
+    assert err < P.TOL_TABLE
+
+
+@pytest.mark.parametrize("kind", ["two_interval", "fixed_alpha"])
+def test_tables_other_meshes(pw, kind):
+    if kind == "two_interval":
+        m = pw.Mesh.two_interval(20)
+        o = P.setup(9, mesh=("two_interval", 20))
+        L = 1.0
+    else:
+        L = 2.0
+        m = pw.Mesh.geometric(5, 8, alpha_c=0.25)       # beta_c = 4 alpha_c / L^2 = 0.25
+        o = P.setup(9, mesh=("geometric", 5, 8), beta_c=0.25)
+    with pw.Table(L, 9, 0, mesh=m) as t:
+        beta, W = t.mesh_nodes()
+        assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 1e-14
+        tau = t.copy_tables().cpu().numpy()
+        scale = np.abs(o["tau"]).max(axis=(1, 2))
+        assert (np.abs(tau - o["tau"]).max(axis=(1, 2)) / scale).max() < P.TOL_TABLE
+
+
+# ------------------------------------------------------------ integrals ----
+
+def _check_reconstruct(pw, t, o, quads, L=1.0, label=""):
+    import torch
+    dq = _dev(quads, torch.int32)
+    ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads, L=L)
+    scale = P.cond_scale(o["tau"], o["W"], o["basis"], quads, L=L)
+    errs = {}
+    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED)):
+        out = t.reconstruct(dq, precision=prec)
+        t.sync()
+        got = out.cpu().numpy()
+        errs[prec] = P.worst_cond_err(got, ref, scale)
+        assert errs[prec] < tol, (label, prec, errs[prec])
+    say(f"[parity] reconstruct {label}: n={len(quads)} fp64 {errs[pw.FP64]:.2e} "
+        f"mixed {errs[pw.MIXED]:.2e} (condition-aware)")
+    return errs
+
+
+def test_reconstruct_plain_all_occupied_quadruples(pw, tables):
+    w = workloads.C1_PLAIN
+    t = tables(w.n2max, w.n_nodes)
+    o = P.setup(w.n2max, w.n_nodes)
+    M = int((np.asarray(o["basis"]) ** 2).sum(1).__le__(w.n2occ).sum())
+    assert M == 19
+    _check_reconstruct(pw, t, o, workloads.all_quads(M), label="19^4 (123 PW, Q=48)")
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 2047, 2048, 2049, 4097, 30001])
+def test_reconstruct_ragged_sizes(pw, tables, n):
+    w = workloads.C2_SPLIT
+    t = tables(w.n2max, w.n_nodes)
+    o = P.setup(w.n2max, w.n_nodes)
+    _check_reconstruct(pw, t, o, workloads.uniform_quads(len(o["basis"]), n, seed=n),
+                       label=f"ragged n={n}")
+
+
+def test_reconstruct_empty(pw, tables):
+    import torch
+    t = tables(9, 48)
+    out = t.reconstruct(torch.empty((0, 4), dtype=torch.int32, device="cuda"))
+    t.sync()
+    assert out.numel() == 0
+
+
+def _sampled_stream_check(pw, t, o, quads_host, sample, label):
+    import torch
+    dq = _dev(quads_host, torch.int32)
+    rows = workloads.sample_rows(len(quads_host), sample, seed=99)
+    q = quads_host[rows]
+    ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], q)
+    scale = P.cond_scale(o["tau"], o["W"], o["basis"], q)
+    outs = {}
+    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED)):
+        out = t.reconstruct(dq, precision=prec)
+        t.sync()
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        err = P.worst_cond_err(got, ref, scale)
+        say(f"[parity] {label} prec={prec}: sampled {len(rows)} worst {err:.2e}")
+        assert err < tol
+        assert bool(torch.isfinite(out).all())
+        outs[prec] = out
+    return outs
+
+
+def test_reconstruct_uniform_stream_1045pw(pw, tables):
+    w = workloads.C2_SPLIT
+    t = tables(w.n2max, w.n_nodes)
+    o = P.setup(w.n2max, w.n_nodes)
+    quads = workloads.uniform_quads(len(o["basis"]), w.n_quads, w.seed)
+    _sampled_stream_check(pw, t, o, quads, 20000, "1e7 uniform, 1045 PW, Q=64")
+
+
+def test_reconstruct_lookup_stream_full_size(pw, tables):
+    """1e8 quadruples over the 9171-PW basis at Q = 96, the launch the benchmark times."""
+    import torch
+    w = workloads.C4_STREAM
+    t = tables(w.n2max, w.n_nodes)
+    o = P.setup(w.n2max, w.n_nodes)
+    N = len(o["basis"])
+    M = int(((o["basis"] ** 2).sum(1) <= w.n2occ).sum())
+    assert (N, M) == (9171, 925)
+    quads = workloads.lookup_stream(N, M, w.n_quads, w.seed)
+    outs = _sampled_stream_check(pw, t, o, quads, 20000, "1e8 lookup stream, 9171 PW, Q=96")
+    # every output: split-FP32 against FP64, relative to the largest |value|
+    d = (outs[pw.MIXED] - outs[pw.FP64]).abs().max().item()
+    say(f"[parity] lookup stream: max |mixed - fp64| = {d:.2e}")
+    assert d < 1e-10
+
+
+# -------------------------------------------------------------- energies ----
+
+@pytest.mark.parametrize("wl", ["plain_fp64_123pw", "split_fp32_1045pw", "paper_scale_9171pw"])
+@pytest.mark.parametrize("weights", [False, True])
+def test_energies_match_oracle(pw, tables, wl, weights):
+    import torch
+    w = workloads.ALL[wl]
+    t = tables(w.n2max, w.n_nodes)
+    o = P.setup(w.n2max, w.n_nodes)
+    M = int(((o["basis"] ** 2).sum(1) <= w.n2occ).sum())
+    occ = np.arange(M, dtype=np.int32)
+    f = workloads.occupations(M, seed=5) if weights else None
+    eh_ref, ex_ref = oracle.energies(o["tau"], o["W"], o["basis"], occ, f)
+    docc = _dev(occ, torch.int32)
+    df = _dev(f, torch.float64) if weights else None
+    for prec, tol in ((pw.FP64, P.TOL_E_FP64), (pw.MIXED, P.TOL_E_MIXED)):
+        eh, ex = t.energies(docc, df, precision=prec)
+        rh, rx = abs(eh - eh_ref) / eh_ref, abs(ex - ex_ref) / abs(ex_ref)
+        say(f"[parity] energies {wl} M={M} f={weights} prec={prec}: "
+            f"E_H rel {rh:.2e}, E_x rel {rx:.2e}")
+        assert rh < tol and rx < tol
+
+
+def test_energies_permuted_occupied_list(pw, tables):
+    """Any list of basis indices may be occupied; order does not matter."""
+    import torch
+    t = tables(40, 64)
+    o = P.setup(40, 64)
+    occ = workloads.rng(4).permutation(len(o["basis"]))[:200].astype(np.int32)
+    eh_ref, ex_ref = oracle.energies(o["tau"], o["W"], o["basis"], occ)
+    eh, ex = t.energies(_dev(occ, torch.int32))
+    assert abs(ex - ex_ref) < 1e-12 * abs(ex_ref) and abs(eh - eh_ref) < 1e-12 * eh_ref
+
+
+def test_energies_empty_and_deterministic(pw, tables):
+    import torch
+    t = tables(40, 64)
+    assert t.energies(torch.empty(0, dtype=torch.int32, device="cuda")) == (0.0, 0.0)
+    occ = torch.arange(123, dtype=torch.int32, device="cuda")
+    a = t.energies(occ)
+    b = t.energies(occ)
+    assert a == b
+
+
+def test_table_one_mesh2_on_gpu(pw):
+    """Sec. III, Table I at M = 9171 (Mesh 2, 8 x 10 + 8 tail): E_x / E_KS = 0.965431."""
+    import torch
+    with pw.Table(1.0, 169, 0, mesh=pw.Mesh.geometric(10, 8)) as t:
+        occ = torch.arange(9171, dtype=torch.int32, device="cuda")
+        eh, ex = t.energies(occ)
+        ratio = ex / oracle.e_ks(9171)
+        o = P.setup(169, mesh=("geometric", 10, 8))
+        h, R = oracle.diff_histogram(o["basis"])
+        diag = o["tau"][:, np.arange(-26, 27) + 26, -np.arange(-26, 27) + 26]
+        ex_ref = oracle.exchange_from_histogram(h, R, diag, o["W"])
+        say(f"[parity] Table I on GPU: ratio {ratio:.7f}, rel err vs oracle "
+            f"{abs(ex - ex_ref) / abs(ex_ref):.2e}")
+        assert abs(ratio - 0.965431) < 1.5e-6
+        assert abs(ex - ex_ref) < 1e-12 * abs(ex_ref)
+
+
+# ------------------------------------------------------ errors, invariants ----
+
+def test_out_of_range_index_reports_and_poisons_only_its_row(pw, tables):
+    import torch
+    t = tables(9, 48)
+    o = P.setup(9, 48)
+    N = len(o["basis"])
+    quads = workloads.uniform_quads(N, 5000, seed=8)
+    bad = quads.copy()
+    bad[17, 2] = N
+    bad[4000, 0] = -3
+    for prec in (pw.FP64, pw.MIXED):
+        out = t.reconstruct(_dev(bad, torch.int32), precision=prec)
+        with pytest.raises(pw.PwcError) as ei:
+            t.sync()
+        assert ei.value.status == pw.ERR_RANGE
+        got = out.cpu().numpy()
+        assert np.isnan(got[17]) and np.isnan(got[4000])
+        keep = np.ones(len(got), bool)
+        keep[[17, 4000]] = False
+        ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads[keep])
+        scale = P.cond_scale(o["tau"], o["W"], o["basis"], quads[keep])
+        assert P.worst_cond_err(got[keep], ref, scale) < P.TOL_MIXED
+        t.sync()   # the error word was cleared
+    occ = torch.tensor([0, 1, N], dtype=torch.int32, device="cuda")
+    with pytest.raises(pw.PwcError):
+        t.energies(occ)
+
+
+def test_one_over_L_scaling(pw, tables):
+    import torch
+    q = _dev(workloads.uniform_quads(123, 3000, seed=2), torch.int32)
+    a = tables(9, 48, 1.0).reconstruct(q)
+    b = tables(9, 48, 2.5).reconstruct(q)
+    assert torch.allclose(a, b * 2.5, rtol=1e-15, atol=0)
+
+
+def test_concurrent_streams_share_one_table(pw, tables):
+    import torch
+    t = tables(40, 64)
+    q = _dev(workloads.uniform_quads(1045, 200000, seed=3), torch.int32)
+    ref = t.reconstruct(q)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        a = t.reconstruct(q, stream=s1)
+    with torch.cuda.stream(s2):
+        b = t.reconstruct(q, precision=pw.MIXED, stream=s2)
+        c = t.reconstruct(q, stream=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, ref) and torch.equal(c, ref)
+    assert (b - ref).abs().max().item() < 1e-12

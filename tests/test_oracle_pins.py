@@ -70,14 +70,15 @@ def _mp_gauss_legendre(q, dps=40):
     return xs, ws
 
 
-@pytest.mark.parametrize("q", [5, 8, 11, 16])
+@pytest.mark.parametrize("q", [5, 8, 11, 15, 16, 20])
 def test_gauss_legendre_against_mpmath_and_exactness(q):
     x, w = oracle.gauss_legendre(q, -1.0, 1.0)
     xm, wm = _mp_gauss_legendre(q)
-    # numpy's Golub-Welsch weights carry a few ulps of rounding
+    # numpy's Golub-Welsch weights carry up to ~7e-14 relative rounding error
+    # for q <= 20 (nodes are exact to an ulp); that is the oracle's mesh error.
     assert np.max(np.abs(x - np.array([float(v) for v in xm]))) < 4e-16
     wm = np.array([float(v) for v in wm])
-    assert np.max(np.abs(w - wm) / wm) < 1e-14
+    assert np.max(np.abs(w - wm) / wm) < 1e-13
     a, b = 0.3, 2.7
     x, w = oracle.gauss_legendre(q, a, b)
     for k in range(2 * q):
