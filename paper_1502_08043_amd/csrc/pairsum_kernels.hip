@@ -36,6 +36,7 @@ struct PairArgs {
     const void *w;      // [nchunk * dc]     double or float2
     int K, dc, nchunk, nT;
     double *partial;    // [nT * nT][2]
+    int *err;           // table error word
 };
 
 __device__ __forceinline__ int bx(int v) { return (v << 24) >> 24; }
@@ -66,8 +67,10 @@ __device__ __forceinline__ bool pair_setup(const PairArgs &a, int ti, int tj, in
     if (i >= a.M || j >= a.M || i > j) return true;
     const int oi = a.occ[i], oj = a.occ[j];
     if (static_cast<unsigned>(oi) >= static_cast<unsigned>(a.N) ||
-        static_cast<unsigned>(oj) >= static_cast<unsigned>(a.N))
+        static_cast<unsigned>(oj) >= static_cast<unsigned>(a.N)) {
+        atomicOr(a.err, 1);
         return false;
+    }
     const int vi = a.basis[oi], vj = a.basis[oj];
     ax = iabs(bx(vj) - bx(vi)) * a.dc;
     ay = iabs(by(vj) - by(vi)) * a.dc;
@@ -251,6 +254,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     a.dc = t.dl.c;
     a.nchunk = t.dl.nchunk;
     a.nT = static_cast<int>((M + kTile - 1) / kTile);
+    a.err = t.d_err;
     const int nblk = a.nT * a.nT;
     double *partial = nullptr;
     hipError_t err = hipMallocAsync(reinterpret_cast<void **>(&partial),
