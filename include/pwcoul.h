@@ -106,7 +106,7 @@ typedef struct {
 } pwc_mesh;
 
 /* Maximum sizes accepted by pwc_table_create. */
-#define PWC_MAX_N2MAX 625    /* nmax <= 25, table dimension 4 nmax + 1 <= 101 */
+#define PWC_MAX_N2MAX 624    /* nmax <= 24, table dimension 4 nmax + 1 <= 97 */
 #define PWC_MAX_NODES 512
 
 typedef struct pwc_table pwc_table;

@@ -42,6 +42,23 @@ bool plan_chunks(int Q, size_t row_bytes, int *c_out, int *nchunk_out) {
     return true;
 }
 
+// Node passes of the reconstruction kernels: the largest pass width c (a
+// multiple of 8 nodes) whose [E][c] slab and weights fit in LDS, the fewest
+// passes P = ceil(Q / c), and c shrunk again to spread the padding.
+bool plan_fold(int Q, int E, int n_cu, pwc::FoldLayout &fl) {
+    fl.E = E;
+    const size_t per_node = (static_cast<size_t>(E) + 1) * 8;
+    int cmax = static_cast<int>(pwc::kLdsMax / per_node) / 8 * 8;
+    if (cmax < 8) return false;
+    const int P = (Q + cmax - 1) / cmax;
+    fl.nchunk = P;
+    fl.c = ((Q + P - 1) / P + 7) / 8 * 8;
+    fl.Qp = fl.c * P;
+    const size_t lds = per_node * fl.c;
+    fl.grid_cap = n_cu * std::max(1, std::min(2, static_cast<int>(pwc::kLdsMax / lds)));
+    return true;
+}
+
 float2 split_hilo(double v) {
     const float hi = static_cast<float>(v);
     return make_float2(hi, static_cast<float>(v - static_cast<double>(hi)));
@@ -122,15 +139,18 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     std::vector<int32_t> fold, reps;
     pwc::build_fold(t.K, fold, reps);
     t.fl.E = static_cast<int>(reps.size() / 2);
-    if (!plan_chunks(t.Q, static_cast<size_t>(t.fl.E) * 8, &t.fl.c, &t.fl.nchunk) ||
+    (void)hipGetDevice(&t.device);
+    if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
+        t.n_cu <= 0)
+        t.n_cu = 256;
+    if (!plan_fold(t.Q, t.fl.E, t.n_cu, t.fl) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk)) {
         delete h;
         return PWC_ERR_ARG;
     }
-    (void)hipGetDevice(&t.device);
 
     const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E;
-    const size_t Qp = static_cast<size_t>(t.fl.c) * t.fl.nchunk;
+    const size_t Qp = static_cast<size_t>(t.fl.Qp);
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     // Carve one allocation.
     size_t off = 0;

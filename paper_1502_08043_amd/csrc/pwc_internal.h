@@ -35,16 +35,23 @@ void build_fold(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps);
 
 // ------------------------------------------------------------- kernels ----
 
-// LDS budget of one table-streaming workgroup: two workgroups share a CU.
+// LDS budget of one pair-sum workgroup (diagonal-table chunk).
 constexpr int kLdsBudget = 80 * 1024;
 constexpr int kGlPanelPoints = 16;    // Gauss-Legendre points per panel
 constexpr int kGlPanels = 128;        // panels over the Gaussian's support
 
+// Folded-table layout of the reconstruction kernels (see reconstruct_kernels.hip):
+// P node passes of c nodes each; the [E][c] slab of one pass (plus c weights)
+// must fit in one workgroup's LDS.
 struct FoldLayout {
-    int E = 0;        // folded entries per node
-    int c = 0;        // nodes per LDS chunk (even)
-    int nchunk = 0;   // chunks; nodes padded to nchunk * c with zero weight
+    int E = 0;          // folded entries per node
+    int Qp = 0;         // nodes padded to nchunk * c (zero weight, zero tau)
+    int c = 0;          // nodes per pass (multiple of 8)
+    int nchunk = 0;     // passes P
+    int grid_cap = 0;   // persistent grid size
 };
+constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
+constexpr int64_t kRecSlab = int64_t(1) << 27;   // quadruples per scratch slab
 
 struct DiagLayout {
     int c = 0;        // nodes per LDS chunk of the diagonal table
@@ -62,6 +69,7 @@ struct Table {
     FoldLayout fl;
     DiagLayout dl;
     int device = 0;
+    int n_cu = 0;
 
     // device memory (one allocation, carved)
     void *d_block = nullptr;
@@ -74,10 +82,10 @@ struct Table {
     double *d_gl = nullptr;         // [2][kGlPanelPoints] panel rule on [0, 1]
     double *d_prim = nullptr;       // [Q][2][K + 1]  (S, D)
     double *d_tau = nullptr;        // [Q][nd][nd]
-    double *d_tauF = nullptr;       // [nchunk][E][c]         folded FP64
-    float2 *d_tauHL = nullptr;      // [nchunk][E][c]         folded (hi, lo)
-    double *d_Wpad = nullptr;       // [nchunk * c]
-    float2 *d_WHL = nullptr;        // [nchunk * c]
+    double *d_tauF = nullptr;       // [E][Qp]  folded FP64
+    float2 *d_tauHL = nullptr;      // [E][Qp]  folded (hi, lo)
+    double *d_Wpad = nullptr;       // [Qp]
+    float2 *d_WHL = nullptr;        // [Qp]
     double *d_diag = nullptr;       // [dl.nchunk][K + 1][dl.c]  tau_q(m, -m), m >= 0
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
     double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]

@@ -82,7 +82,7 @@ struct AsmArgs {
     const double *prim;
     const int32_t *fold;
     const int32_t *reps;
-    int K, nd, E, c, dc;
+    int K, nd, E, Qp, dc;
     double *tau;
     double *tauF;
     float2 *tauHL;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
     // Folded layout: only the orbit representative writes its slot.
     const int f = a.fold[e];
     if (a.reps[2 * f] == m && a.reps[2 * f + 1] == mp) {
-        const size_t idx = (static_cast<size_t>(q / a.c) * a.E + f) * a.c + (q % a.c);
+        const size_t idx = static_cast<size_t>(f) * a.Qp + q;
         a.tauF[idx] = v;
         a.tauHL[idx] = split_hilo(v);
     }
@@ -131,7 +131,7 @@ hipError_t launch_table_build(Table &t, hipStream_t s) {
     hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    AsmArgs a{t.d_beta, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.c, t.dl.c,
+    AsmArgs a{t.d_beta, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.Qp, t.dl.c,
               t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
     dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q);
     hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);

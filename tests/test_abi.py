@@ -73,7 +73,7 @@ def test_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.pwc_table_create(0.0, 9, 48, None, None, ctypes.byref(h)) == 1      # L <= 0
     assert lib.pwc_table_create(-1.0, 9, 48, None, None, ctypes.byref(h)) == 1
     assert lib.pwc_table_create(1.0, 0, 48, None, None, ctypes.byref(h)) == 1      # n2max < 1
-    assert lib.pwc_table_create(1.0, 626, 48, None, None, ctypes.byref(h)) == 1    # too large
+    assert lib.pwc_table_create(1.0, 625, 48, None, None, ctypes.byref(h)) == 1    # too large
     assert lib.pwc_table_create(1.0, 9, 50, None, None, ctypes.byref(h)) == 1      # Q % 8
     assert lib.pwc_table_create(1.0, 9, 48, None, None, None) == 1
     assert h.value is None
