@@ -75,6 +75,24 @@ typedef enum {
                        scaling and energy reductions in FP64 */
 } pwc_precision;
 
+/*
+ * How the pair sums of pwc_energies* evaluate <ij|ji>.  Both give the same sum
+ * up to rounding.
+ *   NODESUM: the Q-node sum of Eq. 14 for every pair, from the diagonal
+ *            entries tau_q(m, -m) (the paper's O(M^2 Q) evaluation).
+ *   KTABLE:  <ij|ji> depends only on the sorted |n_j - n_i| per direction;
+ *            the node sums K(a, b, c) = sum_q W_q D_q(a) D_q(b) D_q(c),
+ *            a <= b <= c <= 4 nmax, are formed once at table creation and
+ *            each pair reads one entry.  Available when the C(4 nmax + 3, 3)
+ *            entries fit in LDS (nmax <= 23).
+ *   AUTO:    KTABLE when available, else NODESUM.
+ */
+typedef enum {
+    PWC_PAIR_AUTO = 0,
+    PWC_PAIR_NODESUM = 1,
+    PWC_PAIR_KTABLE = 2
+} pwc_pair_algo;
+
 typedef enum {
     PWC_MESH_GEOMETRIC = 0,    /* "Mesh 2" of Sec. III / Table I */
     PWC_MESH_TWO_INTERVAL = 1  /* "Mesh 1" of Sec. III / Table I */
@@ -187,6 +205,15 @@ PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, i
  */
 PWC_API pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
                               int64_t M, pwc_precision p, double *d_out, void *stream);
+
+/*
+ * pwc_energies_async with an explicit pair-sum algorithm (PWC_ERR_ARG if
+ * PWC_PAIR_KTABLE is asked for a table that does not keep the kernel table).
+ * pwc_energies_async is this call with PWC_PAIR_AUTO.
+ */
+PWC_API pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                                   int64_t M, pwc_precision p, pwc_pair_algo algo,
+                                   double *d_out, void *stream);
 
 /* Same as pwc_energies_async, then waits and writes h_out[2] = {E_H, E_x}. */
 PWC_API pwc_status pwc_energies(const pwc_table *t, const int32_t *d_occ, const double *d_f,

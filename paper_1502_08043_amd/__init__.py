@@ -21,6 +21,7 @@ FP64 = 0
 MIXED = 1
 MESH_GEOMETRIC = 0
 MESH_TWO_INTERVAL = 1
+PAIR_AUTO, PAIR_NODESUM, PAIR_KTABLE = 0, 1, 2
 
 OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE = range(7)
 
@@ -71,6 +72,7 @@ def lib():
             "pwc_table_copy": (i32, [vp, vp, vp]),
             "pwc_reconstruct": (i32, [vp, vp, i64, vp, i32, vp]),
             "pwc_energies_async": (i32, [vp, vp, vp, i64, i32, vp, vp]),
+            "pwc_energies_ex": (i32, [vp, vp, vp, i64, i32, i32, vp, vp]),
             "pwc_energies": (i32, [vp, vp, vp, i64, i32, vp, vp]),
             "pwc_sync": (i32, [vp, vp]),
         }
@@ -194,19 +196,25 @@ class Table:
                                      _stream(stream)), "pwc_reconstruct")
         return out
 
-    def energies_async(self, occ, f=None, precision=FP64, out=None, stream=None):
+    def energies_async(self, occ, f=None, precision=FP64, out=None, stream=None,
+                       algo=PAIR_AUTO):
         """Enqueue (E_H, E_x) into a device tensor [2]."""
         M = occ.numel()
         if out is None:
             out = torch.empty(2, dtype=torch.float64, device=occ.device)
         fp = _dev_ptr(f, torch.float64, "f") if f is not None else None
-        _check(lib().pwc_energies_async(self.handle, _dev_ptr(occ, torch.int32, "occ"), fp, M,
-                                        int(precision), _dev_ptr(out, torch.float64, "out"),
-                                        _stream(stream)), "pwc_energies_async")
+        _check(lib().pwc_energies_ex(self.handle, _dev_ptr(occ, torch.int32, "occ"), fp, M,
+                                     int(precision), int(algo),
+                                     _dev_ptr(out, torch.float64, "out"), _stream(stream)),
+               "pwc_energies_ex")
         return out
 
-    def energies(self, occ, f=None, precision=FP64, stream=None):
+    def energies(self, occ, f=None, precision=FP64, stream=None, algo=PAIR_AUTO):
         """(E_H, E_x) of one spin channel for occupied basis indices occ (int32 device)."""
+        if algo != PAIR_AUTO:
+            out = self.energies_async(occ, f, precision, stream=stream, algo=algo)
+            self.sync(stream)
+            return tuple(float(v) for v in out.cpu().numpy())
         h = np.zeros(2)
         fp = _dev_ptr(f, torch.float64, "f") if f is not None else None
         _check(lib().pwc_energies(self.handle, _dev_ptr(occ, torch.int32, "occ"), fp, occ.numel(),

@@ -171,6 +171,11 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
     const size_t o_Wdiag = take(sizeof(double) * Qd);
     const size_t o_WdiagHL = take(sizeof(float2) * Qd);
+    // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
+    const int64_t kt_n = static_cast<int64_t>(K + 1) * (K + 2) * (K + 3) / 6;
+    t.kt_n = (kt_n * 8 <= pwc::kLdsMax - 4096) ? static_cast<int>(kt_n) : 0;
+    const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
+    const size_t o_ktMX = take(sizeof(double) * static_cast<size_t>(t.kt_n));
     const size_t o_err = take(sizeof(int) * 64);
     t.bytes = off;
     hipError_t e = hipMalloc(&t.d_block, t.bytes);
@@ -196,6 +201,8 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     t.d_Wdiag = reinterpret_cast<double *>(base + o_Wdiag);
     t.d_WdiagHL = reinterpret_cast<float2 *>(base + o_WdiagHL);
     t.d_err = reinterpret_cast<int *>(base + o_err);
+    t.d_ktab64 = t.kt_n ? reinterpret_cast<double *>(base + o_kt64) : nullptr;
+    t.d_ktabMX = t.kt_n ? reinterpret_cast<double *>(base + o_ktMX) : nullptr;
 
     // Host-side inputs of the table kernels.
     std::vector<int32_t> packed(t.N);
@@ -239,6 +246,7 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
     up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
     if (st == PWC_OK) st = from_hip(pwc::launch_table_build(t, s));
+    if (st == PWC_OK) st = from_hip(pwc::launch_ktab_build(t, s));
     // The host staging vectors die with this frame: wait for the stream.
     const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
     if (st == PWC_OK) st = st_sync;
@@ -299,15 +307,24 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
                                             static_cast<hipStream_t>(stream)));
 }
 
-pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
-                              int64_t M, pwc_precision p, double *d_out, void *stream) {
+pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                           int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
+                           void *stream) {
     if (!t || !d_out || M < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (algo != PWC_PAIR_AUTO && algo != PWC_PAIR_NODESUM && algo != PWC_PAIR_KTABLE)
+        return PWC_ERR_ARG;
+    if (algo == PWC_PAIR_KTABLE && t->t.kt_n == 0) return PWC_ERR_ARG;
     if (M > 0 && !d_occ) return PWC_ERR_ARG;
     if (M > (1 << 17)) return PWC_ERR_ARG;   // pair-tile grid (M/32)^2 workgroups
     if ((reinterpret_cast<uintptr_t>(d_out) & 7) || (d_f && (reinterpret_cast<uintptr_t>(d_f) & 7)))
         return PWC_ERR_ARG;
-    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, d_out,
+    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, algo, d_out,
                                          static_cast<hipStream_t>(stream)));
+}
+
+pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
+                              int64_t M, pwc_precision p, double *d_out, void *stream) {
+    return pwc_energies_ex(t, d_occ, d_f, M, p, PWC_PAIR_AUTO, d_out, stream);
 }
 
 pwc_status pwc_energies(const pwc_table *t, const int32_t *d_occ, const double *d_f, int64_t M,

@@ -14,6 +14,7 @@
 // shuffles and LDS in a fixed order and written to a per-tile partial.  A
 // single workgroup then adds the partials in a fixed order in FP64, so the
 // energies are bitwise reproducible for a given input.
+#include <algorithm>
 #include <cmath>
 
 #include "ffloat.h"
@@ -198,11 +199,13 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(PairArgs a) {
     }
 }
 
-// Fixed-order FP64 sum of the tile partials, then the energies:
+// Fixed-order FP64 sum of the workgroup partials, then the energies:
 // E_x = -1/2 pref S_x, E_H = 1/2 pref <00|00>_raw S_h, with
-// <00|00>_raw = sum_q W_q tau_q(0,0)^3 from the FP64 diagonal table.
+// <00|00>_raw = sum_q W_q tau_q(0,0)^3 read from c0 when given, else summed
+// here from the FP64 diagonal table.
 __global__ __launch_bounds__(kThreads) void k_pair_final(const double *__restrict__ partial,
-                                                        int nblk, const double *__restrict__ diag,
+                                                        int nblk, const double *__restrict__ c0p,
+                                                        const double *__restrict__ diag,
                                                         const double *__restrict__ wd, int K,
                                                         int dc, int nchunk, double pref,
                                                         double *__restrict__ out) {
@@ -216,13 +219,145 @@ __global__ __launch_bounds__(kThreads) void k_pair_final(const double *__restric
     sh = block_sum(sh, red);
     if (threadIdx.x == 0) {
         double c0 = 0.0;
-        for (int ch = 0; ch < nchunk; ++ch)
-            for (int q = 0; q < dc; ++q) {
-                const double d0 = diag[(static_cast<size_t>(ch) * (K + 1)) * dc + q];
-                c0 = fma(d0 * d0 * d0, wd[ch * dc + q], c0);
-            }
+        if (c0p) {
+            c0 = *c0p;
+        } else {
+            for (int ch = 0; ch < nchunk; ++ch)
+                for (int q = 0; q < dc; ++q) {
+                    const double d0 = diag[(static_cast<size_t>(ch) * (K + 1)) * dc + q];
+                    c0 = fma(d0 * d0 * d0, wd[ch * dc + q], c0);
+                }
+        }
         out[0] = 0.5 * pref * c0 * sh;
         out[1] = -0.5 * pref * sx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exchange through the kernel table K(a, b, c) = sum_q W_q D_q(a) D_q(b) D_q(c),
+// a <= b <= c = the sorted |Delta_d| (the summand is symmetric in the three
+// directions and even in each Delta_d).  The same sum as the node-sum kernel,
+// reassociated: the Q node terms of each distinct Delta are added once, at
+// table creation, and each pair costs one LDS gather and one FMA.
+
+// Position of the sorted triple a <= b <= c: C(c+2,3) + C(b+1,2) + a.
+__device__ __forceinline__ int ktab_index(int a, int b, int c) {
+    return c * (c + 1) * (c + 2) / 6 + b * (b + 1) / 2 + a;
+}
+
+// One thread per (a, b, c) of the cube; sorted triples write their sum.
+__global__ __launch_bounds__(kThreads) void k_ktab_build(const double *__restrict__ diag,
+                                                        const float2 *__restrict__ diagHL,
+                                                        const double *__restrict__ wd,
+                                                        const float2 *__restrict__ wdHL, int K,
+                                                        int dc, int nchunk,
+                                                        double *__restrict__ k64,
+                                                        double *__restrict__ kmx) {
+    const int n1 = K + 1;
+    const int id = blockIdx.x * kThreads + threadIdx.x;
+    if (id >= n1 * n1 * n1) return;
+    const int c = id / (n1 * n1), b = (id / n1) % n1, a = id % n1;
+    if (a > b || b > c) return;
+    double s64 = 0.0;
+    float sh = 0.0f, sl = 0.0f;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const size_t row = static_cast<size_t>(ch) * n1;
+        for (int q = 0; q < dc; ++q) {
+            const double da = diag[(row + a) * dc + q], db = diag[(row + b) * dc + q];
+            const double dcv = diag[(row + c) * dc + q];
+            s64 = fma(da * db * dcv, wd[ch * dc + q], s64);
+            const float2 ha = diagHL[(row + a) * dc + q], hb = diagHL[(row + b) * dc + q];
+            const float2 hc = diagHL[(row + c) * dc + q], hw = wdHL[ch * dc + q];
+            ff_acc(sh, sl, ff_mul(ff_mul(ff_mul(ff{ha.x, ha.y}, ff{hb.x, hb.y}), ff{hc.x, hc.y}),
+                                  ff{hw.x, hw.y}));
+        }
+    }
+    const int idx = ktab_index(a, b, c);
+    k64[idx] = s64;
+    kmx[idx] = ff_to_double(sh, sl);
+}
+
+constexpr int kKtTile = 64;                      // 64 x 64 pairs per tile
+constexpr int kKtRows = kKtTile * kKtTile / kThreads;   // 16 pairs per lane
+
+struct KtArgs {
+    const int32_t *occ;
+    const double *f;
+    int M;
+    const int32_t *basis;
+    int N;
+    const double *ktab;
+    int kt_n;
+    int nT;
+    double *partial;   // [gridDim.x][2]
+    int *err;
+};
+
+__device__ __forceinline__ void sort3(int &a, int &b, int &c) {
+    int t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+}
+
+// Persistent workgroups walk the upper-triangle tiles of the pair matrix in
+// a fixed order; the kernel table is staged in LDS once per workgroup.
+__global__ __launch_bounds__(kThreads) void k_pair_ktab(KtArgs a) {
+    extern __shared__ uint4 lds_raw[];
+    double *lk = reinterpret_cast<double *>(lds_raw);
+    __shared__ int vi_s[kKtTile], vj_s[kKtTile];
+    __shared__ double fi_s[kKtTile], fj_s[kKtTile];
+    __shared__ double red[kThreads / 64];
+    for (int i = threadIdx.x; i < a.kt_n; i += kThreads) lk[i] = a.ktab[i];
+    double sx = 0.0, sh = 0.0;
+    const int jl = threadIdx.x % kKtTile, i0 = (threadIdx.x / kKtTile) * kKtRows;
+    const int ntile = a.nT * a.nT;
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int ti = t / a.nT, tj = t - ti * a.nT;
+        if (ti > tj) continue;                       // uniform across the workgroup
+        __syncthreads();                              // previous tile's vectors consumed
+        if (threadIdx.x < 2 * kKtTile) {
+            const bool row = threadIdx.x < kKtTile;
+            const int l = row ? threadIdx.x : threadIdx.x - kKtTile;
+            const int idx = (row ? ti : tj) * kKtTile + l;
+            int v = 0;
+            double w = 0.0;
+            if (idx < a.M) {
+                const int o = a.occ[idx];
+                if (static_cast<unsigned>(o) < static_cast<unsigned>(a.N)) {
+                    v = a.basis[o];
+                    w = a.f ? a.f[idx] : 1.0;
+                } else {
+                    atomicOr(a.err, 1);
+                    w = NAN;                          // poisons the energies
+                }
+            }
+            if (row) { vi_s[l] = v; fi_s[l] = w; } else { vj_s[l] = v; fj_s[l] = w; }
+        }
+        __syncthreads();
+        const int vj = vj_s[jl];
+        const double fj = fj_s[jl];
+        const int j = tj * kKtTile + jl;
+        const int jx = (vj << 24) >> 24, jy = (vj << 16) >> 24, jz = (vj << 8) >> 24;
+#pragma unroll 4
+        for (int k = 0; k < kKtRows; ++k) {
+            const int il = i0 + k, i = ti * kKtTile + il;
+            const int vi = vi_s[il];
+            int dx = jx - ((vi << 24) >> 24), dy = jy - ((vi << 16) >> 24), dz = jz - ((vi << 8) >> 24);
+            dx = dx < 0 ? -dx : dx;
+            dy = dy < 0 ? -dy : dy;
+            dz = dz < 0 ? -dz : dz;
+            sort3(dx, dy, dz);
+            const double wf = (i < j ? 2.0 : (i == j ? 1.0 : 0.0)) * fi_s[il] * fj;
+            sx = fma(wf, lk[ktab_index(dx, dy, dz)], sx);
+            sh += wf;
+        }
+    }
+    sx = block_sum(sx, red);
+    sh = block_sum(sh, red);
+    if (threadIdx.x == 0) {
+        a.partial[2 * blockIdx.x] = sx;
+        a.partial[2 * blockIdx.x + 1] = sh;
     }
 }
 
@@ -238,12 +373,51 @@ hipError_t set_lds(Kern k, size_t bytes) {
 
 }  // namespace
 
+hipError_t launch_ktab_build(Table &t, hipStream_t s) {
+    if (t.kt_n == 0) return hipSuccess;
+    const int n1 = t.K + 1;
+    const int blocks = (n1 * n1 * n1 + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_ktab_build, dim3(blocks), dim3(kThreads), 0, s, t.d_diag, t.d_diagHL,
+                       t.d_Wdiag, t.d_WdiagHL, t.K, t.dl.c, t.dl.nchunk, t.d_ktab64, t.d_ktabMX);
+    return hipGetLastError();
+}
+
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f, int64_t M,
-                           pwc_precision p, double *d_out, hipStream_t s) {
+                           pwc_precision p, pwc_pair_algo algo, double *d_out, hipStream_t s) {
     if (M <= 0) {
         hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, d_out);
         return hipGetLastError();
     }
+    const double pref = 1.0 / (std::sqrt(M_PI) * t.L);
+    hipError_t err;
+    if (algo != PWC_PAIR_NODESUM && t.kt_n > 0) {
+        KtArgs a{};
+        a.occ = d_occ;
+        a.f = d_f;
+        a.M = static_cast<int>(M);
+        a.basis = t.d_basis;
+        a.N = static_cast<int>(t.N);
+        a.ktab = (p == PWC_MIXED) ? t.d_ktabMX : t.d_ktab64;
+        a.kt_n = t.kt_n;
+        a.nT = static_cast<int>((M + kKtTile - 1) / kKtTile);
+        a.err = t.d_err;
+        const size_t lds = sizeof(double) * static_cast<size_t>(t.kt_n);
+        const int per_cu = std::max(1, std::min(8, static_cast<int>((kLdsMax - 4096) / std::max<size_t>(lds, 1))));
+        const int64_t upper = static_cast<int64_t>(a.nT) * (a.nT + 1) / 2;
+        const int grid = static_cast<int>(std::min<int64_t>(upper, int64_t(t.n_cu) * per_cu));
+        double *partial = nullptr;
+        err = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * 2 * grid, s);
+        if (err != hipSuccess) return err;
+        a.partial = partial;
+        if ((err = set_lds(k_pair_ktab, lds)) != hipSuccess) return err;
+        hipLaunchKernelGGL(k_pair_ktab, dim3(grid), dim3(kThreads), lds, s, a);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, grid, a.ktab,
+                           t.d_diag, t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, pref, d_out);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        return hipFreeAsync(partial, s);
+    }
+    if (algo == PWC_PAIR_KTABLE) return hipErrorInvalidValue;   // table too large for LDS
     PairArgs a{};
     a.occ = d_occ;
     a.f = d_f;
@@ -257,8 +431,8 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     a.err = t.d_err;
     const int nblk = a.nT * a.nT;
     double *partial = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void **>(&partial),
-                                    sizeof(double) * 2 * static_cast<size_t>(nblk), s);
+    err = hipMallocAsync(reinterpret_cast<void **>(&partial),
+                         sizeof(double) * 2 * static_cast<size_t>(nblk), s);
     if (err != hipSuccess) return err;
     a.partial = partial;
     const size_t lds = (static_cast<size_t>(a.K + 1) * a.dc + a.dc) * 8;
@@ -275,9 +449,9 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         hipLaunchKernelGGL(k_pair_f64, grid, dim3(kThreads), lds, s, a);
     }
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    const double pref = 1.0 / (std::sqrt(M_PI) * t.L);
-    hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, nblk, t.d_diag,
-                       t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, pref, d_out);
+    hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, nblk,
+                       static_cast<const double *>(nullptr), t.d_diag, t.d_Wdiag, t.K, t.dl.c,
+                       t.dl.nchunk, pref, d_out);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return hipFreeAsync(partial, s);
 }

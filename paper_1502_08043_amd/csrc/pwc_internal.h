@@ -90,6 +90,9 @@ struct Table {
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
     double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]
     float2 *d_WdiagHL = nullptr;
+    int kt_n = 0;                   // exchange kernel table size C(K+3, 3), 0 if not kept
+    double *d_ktab64 = nullptr;     // [kt_n] K(a<=b<=c), FP64 node sums
+    double *d_ktabMX = nullptr;     // [kt_n] same, split-FP32 node sums
     int *d_err = nullptr;           // kernel error word
 };
 
@@ -99,8 +102,10 @@ hipError_t launch_table_build(Table &t, hipStream_t s);
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               double *d_out, pwc_precision p, hipStream_t s);
 // pairsum_kernels.hip
+hipError_t launch_ktab_build(Table &t, hipStream_t s);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,
-                           int64_t M, pwc_precision p, double *d_out, hipStream_t s);
+                           int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
+                           hipStream_t s);
 
 }  // namespace pwc
 

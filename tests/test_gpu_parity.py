@@ -175,7 +175,8 @@ def test_reconstruct_lookup_stream_full_size(pw, tables):
 
 @pytest.mark.parametrize("wl", ["plain_fp64_123pw", "split_fp32_1045pw", "paper_scale_9171pw"])
 @pytest.mark.parametrize("weights", [False, True])
-def test_energies_match_oracle(pw, tables, wl, weights):
+@pytest.mark.parametrize("algo", ["nodesum", "ktable"])
+def test_energies_match_oracle(pw, tables, wl, weights, algo):
     import torch
     w = workloads.ALL[wl]
     t = tables(w.n2max, w.n_nodes)
@@ -186,12 +187,25 @@ def test_energies_match_oracle(pw, tables, wl, weights):
     eh_ref, ex_ref = oracle.energies(o["tau"], o["W"], o["basis"], occ, f)
     docc = _dev(occ, torch.int32)
     df = _dev(f, torch.float64) if weights else None
+    a = pw.PAIR_NODESUM if algo == "nodesum" else pw.PAIR_KTABLE
     for prec, tol in ((pw.FP64, P.TOL_E_FP64), (pw.MIXED, P.TOL_E_MIXED)):
-        eh, ex = t.energies(docc, df, precision=prec)
+        eh, ex = t.energies(docc, df, precision=prec, algo=a)
         rh, rx = abs(eh - eh_ref) / eh_ref, abs(ex - ex_ref) / abs(ex_ref)
-        say(f"[parity] energies {wl} M={M} f={weights} prec={prec}: "
+        say(f"[parity] energies {wl} M={M} f={weights} {algo} prec={prec}: "
             f"E_H rel {rh:.2e}, E_x rel {rx:.2e}")
         assert rh < tol and rx < tol
+
+
+def test_kernel_table_only_when_it_fits(pw):
+    import torch
+    occ = torch.arange(7, dtype=torch.int32, device="cuda")
+    with pw.Table(1.0, 600, 16) as t:            # nmax = 24: C(99, 3) entries exceed LDS
+        with pytest.raises(pw.PwcError) as ei:
+            t.energies_async(occ, algo=pw.PAIR_KTABLE)
+        assert ei.value.status == pw.ERR_ARG
+        a = t.energies(occ, algo=pw.PAIR_NODESUM)
+        b = t.energies(occ)                        # AUTO falls back to node sums
+        assert a == b
 
 
 def test_energies_permuted_occupied_list(pw, tables):
@@ -257,8 +271,12 @@ def test_out_of_range_index_reports_and_poisons_only_its_row(pw, tables):
         assert P.worst_cond_err(got[keep], ref, scale) < P.TOL_MIXED
         t.sync()   # the error word was cleared
     occ = torch.tensor([0, 1, N], dtype=torch.int32, device="cuda")
-    with pytest.raises(pw.PwcError):
-        t.energies(occ)
+    for algo in (pw.PAIR_NODESUM, pw.PAIR_KTABLE):
+        out = t.energies_async(occ, algo=algo)
+        with pytest.raises(pw.PwcError) as ei:
+            t.sync()
+        assert ei.value.status == pw.ERR_RANGE
+        assert np.isnan(out.cpu().numpy()[1])
 
 
 def test_one_over_L_scaling(pw, tables):
