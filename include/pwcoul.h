@@ -128,6 +128,7 @@ typedef struct {
 #define PWC_MAX_NODES 512
 
 typedef struct pwc_table pwc_table;
+typedef struct pwc_server pwc_server;
 
 /* Library version string (static storage). */
 PWC_API const char *pwc_version(void);
@@ -225,6 +226,85 @@ PWC_API pwc_status pwc_energies(const pwc_table *t, const int32_t *d_occ, const 
  * PWC_ERR_DEVICE on a runtime error, else PWC_OK.
  */
 PWC_API pwc_status pwc_sync(const pwc_table *t, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a persistent request loop with continuous batching.
+ *
+ * A scheduler thread owns `max_inflight` HIP streams ("slots") and a cache
+ * of resident tables keyed by (L, n2max, mesh).  Submitted requests wait in
+ * a FIFO; whenever a slot is free and the request's table plus scratch fit
+ * in the HBM budget, the request is admitted: its table is reused or built
+ * (least-recently-used tables that no queued or running request holds are
+ * evicted to make room) and its kernels are launched on the slot's stream,
+ * so work of different requests and tables overlaps on the device.  A
+ * request whose table alone exceeds the budget fails with PWC_ERR_NOMEM;
+ * otherwise requests wait for memory rather than fail.  Each request runs
+ * exactly the kernels of pwc_reconstruct / pwc_energies_ex, so its result
+ * does not depend on what else is in flight.
+ *
+ * Buffers named in a request (d_idx, d_f, d_out) are owned by the caller and
+ * must stay valid and unmodified until pwc_server_wait (or a successful
+ * pwc_server_poll) returns for its ticket.  If a kernel sees an index out of
+ * range, the request reports PWC_ERR_RANGE (concurrent requests on the same
+ * table share its error word, so such a report may also reach a request that
+ * ran at the same time on that table).
+ * ------------------------------------------------------------------------ */
+typedef enum { PWC_REQ_RECONSTRUCT = 0, PWC_REQ_ENERGIES = 1 } pwc_request_kind;
+
+typedef struct {
+    int kind;             /* pwc_request_kind */
+    double L;             /* box side */
+    int n2max;            /* basis cutoff */
+    int n_nodes;          /* default mesh for this node count, used if !has_mesh */
+    int has_mesh;
+    pwc_mesh mesh;
+    int prec;             /* pwc_precision */
+    int algo;             /* energies: pwc_pair_algo */
+    const int32_t *d_idx; /* reconstruct: quadruples [n][4]; energies: occupied [n] */
+    int64_t n;
+    const double *d_f;    /* energies: occupations [n] or NULL */
+    double *d_out;        /* reconstruct: [n]; energies: [2] = {E_H, E_x} */
+} pwc_request;
+
+typedef struct {
+    pwc_status status;
+    double e_h, e_x;      /* energies requests (also left in d_out) */
+    double queue_ms;      /* submit -> launch */
+    double latency_ms;    /* submit -> completion seen by the scheduler */
+    int table_built;      /* 1 if this request had to build its table */
+} pwc_result;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t table_builds, evictions;
+    int resident_tables;
+    size_t resident_bytes;
+    double p50_ms, p99_ms, max_ms;    /* latency over completed requests */
+    double wall_s;                    /* first submit -> last completion */
+    double integrals_per_s, pairs_per_s;
+} pwc_server_stats;
+
+/* Create a server for the current device.  hbm_budget_bytes > 0 bounds the
+ * bytes of resident tables plus per-request scratch; 1 <= max_inflight <= 64. */
+PWC_API pwc_status pwc_server_create(size_t hbm_budget_bytes, int max_inflight,
+                                     pwc_server **out);
+
+/* Queue a request (non-blocking).  Argument errors return at once. */
+PWC_API pwc_status pwc_server_submit(pwc_server *s, const pwc_request *r, uint64_t *ticket);
+
+/* PWC_OK and *res if the request has finished (its entry is then released),
+ * PWC_ERR_BUSY if not yet, PWC_ERR_STATE for an unknown ticket. */
+PWC_API pwc_status pwc_server_poll(pwc_server *s, uint64_t ticket, pwc_result *res);
+
+/* Block until the request has finished; then as pwc_server_poll. */
+PWC_API pwc_status pwc_server_wait(pwc_server *s, uint64_t ticket, pwc_result *res);
+
+/* Counters and latency percentiles since creation (or the last reset). */
+PWC_API pwc_status pwc_server_get_stats(pwc_server *s, pwc_server_stats *st);
+PWC_API pwc_status pwc_server_reset_stats(pwc_server *s);
+
+/* Drain every queued request, stop the scheduler, free every table. */
+PWC_API pwc_status pwc_server_destroy(pwc_server *s);
 
 #ifdef __cplusplus
 }

@@ -225,3 +225,140 @@ class Table:
     def sync(self, stream=None):
         """Wait for the stream and raise PwcError if a kernel saw a bad index."""
         _check(lib().pwc_sync(self.handle, _stream(stream)), "pwc_sync")
+
+
+# ---------------------------------------------------------------- serving ----
+
+REQ_RECONSTRUCT, REQ_ENERGIES = 0, 1
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("L", ctypes.c_double), ("n2max", ctypes.c_int),
+                ("n_nodes", ctypes.c_int), ("has_mesh", ctypes.c_int), ("mesh", Mesh),
+                ("prec", ctypes.c_int), ("algo", ctypes.c_int), ("d_idx", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("d_f", ctypes.c_void_p), ("d_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("e_h", ctypes.c_double), ("e_x", ctypes.c_double),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("table_built", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("table_builds", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64), ("resident_tables", ctypes.c_int),
+                ("resident_bytes", ctypes.c_size_t), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("integrals_per_s", ctypes.c_double),
+                ("pairs_per_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _server_lib():
+    L = lib()
+    if not hasattr(L, "_server_sig"):
+        vp = ctypes.c_void_p
+        L.pwc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)]
+        L.pwc_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.pwc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.pwc_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.pwc_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.pwc_server_reset_stats.argtypes = [vp]
+        L.pwc_server_destroy.argtypes = [vp]
+        for n in ("pwc_server_create", "pwc_server_submit", "pwc_server_poll", "pwc_server_wait",
+                  "pwc_server_get_stats", "pwc_server_reset_stats", "pwc_server_destroy"):
+            getattr(L, n).restype = ctypes.c_int
+        L._server_sig = True
+    return L
+
+
+class Server:
+    """Continuous-batching request loop (pwc_server_*).  Keeps the tensors of
+    every outstanding request alive until its result is collected."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight=4):
+        h = ctypes.c_void_p()
+        _check(_server_lib().pwc_server_create(int(hbm_budget_bytes), int(max_inflight),
+                                               ctypes.byref(h)), "pwc_server_create")
+        self._h = h
+        self._keep = {}
+
+    def _submit(self, req, keep):
+        t = ctypes.c_uint64()
+        _check(_server_lib().pwc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "pwc_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    @staticmethod
+    def _key(req, L, n2max, n_nodes, mesh):
+        req.L, req.n2max, req.n_nodes = float(L), int(n2max), int(n_nodes)
+        if mesh is not None:
+            req.has_mesh, req.mesh = 1, mesh
+
+    def submit_reconstruct(self, L, n2max, quads, out, precision=FP64, n_nodes=0, mesh=None):
+        req = Request()
+        req.kind = REQ_RECONSTRUCT
+        self._key(req, L, n2max, n_nodes, mesh)
+        req.prec = int(precision)
+        req.d_idx = _dev_ptr(quads, torch.int32, "quads").value
+        req.n = quads.shape[0]
+        req.d_out = _dev_ptr(out, torch.float64, "out").value
+        return self._submit(req, (quads, out))
+
+    def submit_energies(self, L, n2max, occ, out, f=None, precision=FP64, algo=PAIR_AUTO,
+                        n_nodes=0, mesh=None):
+        req = Request()
+        req.kind = REQ_ENERGIES
+        self._key(req, L, n2max, n_nodes, mesh)
+        req.prec, req.algo = int(precision), int(algo)
+        req.d_idx = _dev_ptr(occ, torch.int32, "occ").value
+        req.n = occ.numel()
+        req.d_f = _dev_ptr(f, torch.float64, "f").value if f is not None else None
+        req.d_out = _dev_ptr(out, torch.float64, "out").value
+        return self._submit(req, (occ, out, f))
+
+    def wait(self, ticket):
+        r = Result()
+        _check(_server_lib().pwc_server_wait(self._h, int(ticket), ctypes.byref(r)), "pwc_server_wait")
+        self._keep.pop(ticket, None)
+        return r
+
+    def poll(self, ticket):
+        r = Result()
+        s = _server_lib().pwc_server_poll(self._h, int(ticket), ctypes.byref(r))
+        if s == ERR_BUSY:
+            return None
+        _check(s, "pwc_server_poll")
+        self._keep.pop(ticket, None)
+        return r
+
+    def stats(self):
+        st = ServerStats()
+        _check(_server_lib().pwc_server_get_stats(self._h, ctypes.byref(st)), "pwc_server_get_stats")
+        return st.as_dict()
+
+    def reset_stats(self):
+        _check(_server_lib().pwc_server_reset_stats(self._h), "pwc_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _server_lib().pwc_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

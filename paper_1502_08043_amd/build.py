@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpwcoul.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "host_mesh.cpp", "table_kernels.hip", "reconstruct_kernels.hip",
-           "pairsum_kernels.hip"]
+SOURCES = ["api.cpp", "host_mesh.cpp", "server.cpp", "table_kernels.hip",
+           "reconstruct_kernels.hip", "pairsum_kernels.hip"]
 
 # -ffp-contract=off: the split-FP32 arithmetic relies on unfused products; FMAs
 # are written explicitly where they are wanted.  Packed FP32 instructions are
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = OUT + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -64,12 +64,157 @@ float2 split_hilo(double v) {
     return make_float2(hi, static_cast<float>(v - static_cast<double>(hi)));
 }
 
+}  // namespace
+
+namespace pwc {
+
 void free_table(Table &t) {
     if (t.d_block) (void)hipFree(t.d_block);
     t.d_block = nullptr;
 }
 
-}  // namespace
+// Carve the table's single device allocation.  With base == nullptr only the
+// size is computed (used for admission before anything is allocated).
+size_t carve(Table &t, size_t n_reps, char *base) {
+    const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E;
+    const size_t Qp = static_cast<size_t>(t.fl.Qp);
+    const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const size_t o_basis = take(sizeof(int32_t) * t.N);
+    const size_t o_fold = take(sizeof(int32_t) * nd * nd);
+    const size_t o_reps = take(sizeof(int32_t) * n_reps);
+    const size_t o_beta = take(sizeof(double) * Q);
+    const size_t o_W = take(sizeof(double) * Q);
+    const size_t o_gl = take(sizeof(double) * 2 * kGlPanelPoints);
+    const size_t o_prim = take(sizeof(double) * Q * 2 * (K + 1));
+    const size_t o_tau = take(sizeof(double) * Q * nd * nd);
+    const size_t o_tauF = take(sizeof(double) * Qp * E);
+    const size_t o_tauHL = take(sizeof(float2) * Qp * E);
+    const size_t o_Wpad = take(sizeof(double) * Qp);
+    const size_t o_WHL = take(sizeof(float2) * Qp);
+    const size_t o_diag = take(sizeof(double) * Qd * (K + 1));
+    const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
+    const size_t o_Wdiag = take(sizeof(double) * Qd);
+    const size_t o_WdiagHL = take(sizeof(float2) * Qd);
+    const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
+    const size_t o_ktMX = take(sizeof(double) * static_cast<size_t>(t.kt_n));
+    const size_t o_err = take(sizeof(int) * 64);
+    if (base) {
+        t.d_basis = reinterpret_cast<int32_t *>(base + o_basis);
+        t.d_fold = reinterpret_cast<int32_t *>(base + o_fold);
+        t.d_reps = reinterpret_cast<int32_t *>(base + o_reps);
+        t.d_beta = reinterpret_cast<double *>(base + o_beta);
+        t.d_W = reinterpret_cast<double *>(base + o_W);
+        t.d_gl = reinterpret_cast<double *>(base + o_gl);
+        t.d_prim = reinterpret_cast<double *>(base + o_prim);
+        t.d_tau = reinterpret_cast<double *>(base + o_tau);
+        t.d_tauF = reinterpret_cast<double *>(base + o_tauF);
+        t.d_tauHL = reinterpret_cast<float2 *>(base + o_tauHL);
+        t.d_Wpad = reinterpret_cast<double *>(base + o_Wpad);
+        t.d_WHL = reinterpret_cast<float2 *>(base + o_WHL);
+        t.d_diag = reinterpret_cast<double *>(base + o_diag);
+        t.d_diagHL = reinterpret_cast<float2 *>(base + o_diagHL);
+        t.d_Wdiag = reinterpret_cast<double *>(base + o_Wdiag);
+        t.d_WdiagHL = reinterpret_cast<float2 *>(base + o_WdiagHL);
+        t.d_ktab64 = t.kt_n ? reinterpret_cast<double *>(base + o_kt64) : nullptr;
+        t.d_ktabMX = t.kt_n ? reinterpret_cast<double *>(base + o_ktMX) : nullptr;
+        t.d_err = reinterpret_cast<int *>(base + o_err);
+    }
+    return off;
+}
+
+pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su) {
+    if (!(L > 0.0) || !std::isfinite(L) || n2max < 1 || n2max > PWC_MAX_N2MAX) return PWC_ERR_ARG;
+    t.L = L;
+    t.n2max = n2max;
+    t.nmax = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
+    t.K = 2 * t.nmax;
+    t.nd = 2 * t.K + 1;
+    t.mesh = m;
+    t.h_basis = enumerate_basis(n2max);
+    t.N = static_cast<int64_t>(t.h_basis.size() / 3);
+    if (!build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) return PWC_ERR_ARG;
+    t.Q = static_cast<int>(t.h_beta.size());
+    build_fold(t.K, su.fold, su.reps);
+    t.fl.E = static_cast<int>(su.reps.size() / 2);
+    (void)hipGetDevice(&t.device);
+    if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
+        t.n_cu <= 0)
+        t.n_cu = 256;
+    if (!plan_fold(t.Q, t.fl.E, t.n_cu, t.fl) ||
+        !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
+        return PWC_ERR_ARG;
+    // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
+    const int64_t kt_n = static_cast<int64_t>(t.K + 1) * (t.K + 2) * (t.K + 3) / 6;
+    t.kt_n = (kt_n * 8 <= kLdsMax - 4096) ? static_cast<int>(kt_n) : 0;
+    t.bytes = carve(t, su.reps.size(), nullptr);
+    return PWC_OK;
+}
+
+pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
+    hipError_t e = hipMalloc(&t.d_block, t.bytes);
+    if (e != hipSuccess) {
+        t.d_block = nullptr;
+        return from_hip(e);
+    }
+    carve(t, su.reps.size(), static_cast<char *>(t.d_block));
+    const int Q = t.Q;
+    const size_t Qp = static_cast<size_t>(t.fl.Qp);
+    const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
+    // Host-side inputs of the table kernels.
+    std::vector<int32_t> packed(t.N);
+    for (int64_t i = 0; i < t.N; ++i) {
+        const int x = t.h_basis[3 * i], y = t.h_basis[3 * i + 1], z = t.h_basis[3 * i + 2];
+        packed[i] = static_cast<int32_t>((static_cast<uint32_t>(x) & 0xffu) |
+                                         ((static_cast<uint32_t>(y) & 0xffu) << 8) |
+                                         ((static_cast<uint32_t>(z) & 0xffu) << 16));
+    }
+    std::vector<double> glx, glw, gl;
+    gauss_legendre(kGlPanelPoints, 0.0, 1.0, glx, glw);
+    gl = glx;
+    gl.insert(gl.end(), glw.begin(), glw.end());
+    std::vector<double> Wpad(Qp, 0.0), Wdiag(Qd, 0.0);
+    std::vector<float2> WHL(Qp, make_float2(0.f, 0.f)), WdiagHL(Qd, make_float2(0.f, 0.f));
+    // Node q sits at flat slot q of every node-chunked layout; padded slots
+    // carry zero weight.
+    for (int q = 0; q < Q; ++q) {
+        Wpad[q] = t.h_W[q];
+        WHL[q] = split_hilo(t.h_W[q]);
+        Wdiag[q] = t.h_W[q];
+        WdiagHL[q] = split_hilo(t.h_W[q]);
+    }
+    pwc_status st = PWC_OK;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (st == PWC_OK && bytes)
+            st = from_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    };
+    // Padding slots of the node-chunked layouts must read as zero.
+    if (st == PWC_OK)
+        st = from_hip(hipMemsetAsync(t.d_tauF, 0,
+                                     reinterpret_cast<char *>(t.d_Wdiag) -
+                                         reinterpret_cast<char *>(t.d_tauF), s));
+    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_err, 0, sizeof(int) * 64, s));
+    up(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
+    up(t.d_fold, su.fold.data(), sizeof(int32_t) * su.fold.size());
+    up(t.d_reps, su.reps.data(), sizeof(int32_t) * su.reps.size());
+    up(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
+    up(t.d_W, t.h_W.data(), sizeof(double) * Q);
+    up(t.d_gl, gl.data(), sizeof(double) * gl.size());
+    up(t.d_Wpad, Wpad.data(), sizeof(double) * Qp);
+    up(t.d_WHL, WHL.data(), sizeof(float2) * Qp);
+    up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
+    up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
+    if (st == PWC_OK) st = from_hip(launch_table_build(t, s));
+    if (st == PWC_OK) st = from_hip(launch_ktab_build(t, s));
+    // The host staging vectors die with this frame: wait for the stream.
+    const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
+    if (st == PWC_OK) st = st_sync;
+    if (st != PWC_OK) free_table(t);
+    return st;
+}
+
+}  // namespace pwc
 
 extern "C" {
 
@@ -108,7 +253,6 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
                             pwc_table **out) {
     if (!out) return PWC_ERR_ARG;
     *out = nullptr;
-    if (!(L > 0.0) || !std::isfinite(L) || n2max < 1 || n2max > PWC_MAX_N2MAX) return PWC_ERR_ARG;
     pwc_mesh m{};
     if (mesh) {
         int q = 0;
@@ -118,140 +262,12 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     } else if (pwc_mesh_default(n_nodes, &m) != PWC_OK) {
         return PWC_ERR_ARG;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-
     pwc_table *h = new (std::nothrow) pwc_table;
     if (!h) return PWC_ERR_NOMEM;
-    Table &t = h->t;
-    t.L = L;
-    t.n2max = n2max;
-    t.nmax = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
-    t.K = 2 * t.nmax;
-    t.nd = 2 * t.K + 1;
-    t.mesh = m;
-    t.h_basis = pwc::enumerate_basis(n2max);
-    t.N = static_cast<int64_t>(t.h_basis.size() / 3);
-    if (!pwc::build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) {
-        delete h;
-        return PWC_ERR_ARG;
-    }
-    t.Q = static_cast<int>(t.h_beta.size());
-    std::vector<int32_t> fold, reps;
-    pwc::build_fold(t.K, fold, reps);
-    t.fl.E = static_cast<int>(reps.size() / 2);
-    (void)hipGetDevice(&t.device);
-    if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
-        t.n_cu <= 0)
-        t.n_cu = 256;
-    if (!plan_fold(t.Q, t.fl.E, t.n_cu, t.fl) ||
-        !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk)) {
-        delete h;
-        return PWC_ERR_ARG;
-    }
-
-    const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E;
-    const size_t Qp = static_cast<size_t>(t.fl.Qp);
-    const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
-    // Carve one allocation.
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-    const size_t o_basis = take(sizeof(int32_t) * t.N);
-    const size_t o_fold = take(sizeof(int32_t) * nd * nd);
-    const size_t o_reps = take(sizeof(int32_t) * reps.size());
-    const size_t o_beta = take(sizeof(double) * Q);
-    const size_t o_W = take(sizeof(double) * Q);
-    const size_t o_gl = take(sizeof(double) * 2 * pwc::kGlPanelPoints);
-    const size_t o_prim = take(sizeof(double) * Q * 2 * (K + 1));
-    const size_t o_tau = take(sizeof(double) * Q * nd * nd);
-    const size_t o_tauF = take(sizeof(double) * Qp * E);
-    const size_t o_tauHL = take(sizeof(float2) * Qp * E);
-    const size_t o_Wpad = take(sizeof(double) * Qp);
-    const size_t o_WHL = take(sizeof(float2) * Qp);
-    const size_t o_diag = take(sizeof(double) * Qd * (K + 1));
-    const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
-    const size_t o_Wdiag = take(sizeof(double) * Qd);
-    const size_t o_WdiagHL = take(sizeof(float2) * Qd);
-    // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
-    const int64_t kt_n = static_cast<int64_t>(K + 1) * (K + 2) * (K + 3) / 6;
-    t.kt_n = (kt_n * 8 <= pwc::kLdsMax - 4096) ? static_cast<int>(kt_n) : 0;
-    const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
-    const size_t o_ktMX = take(sizeof(double) * static_cast<size_t>(t.kt_n));
-    const size_t o_err = take(sizeof(int) * 64);
-    t.bytes = off;
-    hipError_t e = hipMalloc(&t.d_block, t.bytes);
-    if (e != hipSuccess) {
-        delete h;
-        return from_hip(e);
-    }
-    char *base = static_cast<char *>(t.d_block);
-    t.d_basis = reinterpret_cast<int32_t *>(base + o_basis);
-    t.d_fold = reinterpret_cast<int32_t *>(base + o_fold);
-    t.d_reps = reinterpret_cast<int32_t *>(base + o_reps);
-    t.d_beta = reinterpret_cast<double *>(base + o_beta);
-    t.d_W = reinterpret_cast<double *>(base + o_W);
-    t.d_gl = reinterpret_cast<double *>(base + o_gl);
-    t.d_prim = reinterpret_cast<double *>(base + o_prim);
-    t.d_tau = reinterpret_cast<double *>(base + o_tau);
-    t.d_tauF = reinterpret_cast<double *>(base + o_tauF);
-    t.d_tauHL = reinterpret_cast<float2 *>(base + o_tauHL);
-    t.d_Wpad = reinterpret_cast<double *>(base + o_Wpad);
-    t.d_WHL = reinterpret_cast<float2 *>(base + o_WHL);
-    t.d_diag = reinterpret_cast<double *>(base + o_diag);
-    t.d_diagHL = reinterpret_cast<float2 *>(base + o_diagHL);
-    t.d_Wdiag = reinterpret_cast<double *>(base + o_Wdiag);
-    t.d_WdiagHL = reinterpret_cast<float2 *>(base + o_WdiagHL);
-    t.d_err = reinterpret_cast<int *>(base + o_err);
-    t.d_ktab64 = t.kt_n ? reinterpret_cast<double *>(base + o_kt64) : nullptr;
-    t.d_ktabMX = t.kt_n ? reinterpret_cast<double *>(base + o_ktMX) : nullptr;
-
-    // Host-side inputs of the table kernels.
-    std::vector<int32_t> packed(t.N);
-    for (int64_t i = 0; i < t.N; ++i) {
-        const int x = t.h_basis[3 * i], y = t.h_basis[3 * i + 1], z = t.h_basis[3 * i + 2];
-        packed[i] = static_cast<int32_t>((static_cast<uint32_t>(x) & 0xffu) |
-                                         ((static_cast<uint32_t>(y) & 0xffu) << 8) |
-                                         ((static_cast<uint32_t>(z) & 0xffu) << 16));
-    }
-    std::vector<double> glx, glw, gl;
-    pwc::gauss_legendre(pwc::kGlPanelPoints, 0.0, 1.0, glx, glw);
-    gl = glx;
-    gl.insert(gl.end(), glw.begin(), glw.end());
-    std::vector<double> Wpad(Qp, 0.0), Wdiag(Qd, 0.0);
-    std::vector<float2> WHL(Qp, make_float2(0.f, 0.f)), WdiagHL(Qd, make_float2(0.f, 0.f));
-    // Chunk-local node order equals global node order: node q sits at
-    // chunk q / c, slot q % c; padded slots carry zero weight.
-    for (int q = 0; q < Q; ++q) {
-        Wpad[q] = t.h_W[q];
-        WHL[q] = split_hilo(t.h_W[q]);
-        Wdiag[q] = t.h_W[q];
-        WdiagHL[q] = split_hilo(t.h_W[q]);
-    }
-
-    pwc_status st = PWC_OK;
-    auto up = [&](void *dst, const void *src, size_t bytes) {
-        if (st == PWC_OK && bytes)
-            st = from_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
-    };
-    // Padding slots of the node-chunked layouts must read as zero.
-    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_tauF, 0, o_Wdiag - o_tauF, s));
-    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_err, 0, sizeof(int) * 64, s));
-    up(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
-    up(t.d_fold, fold.data(), sizeof(int32_t) * fold.size());
-    up(t.d_reps, reps.data(), sizeof(int32_t) * reps.size());
-    up(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
-    up(t.d_W, t.h_W.data(), sizeof(double) * Q);
-    up(t.d_gl, gl.data(), sizeof(double) * gl.size());
-    up(t.d_Wpad, Wpad.data(), sizeof(double) * Qp);
-    up(t.d_WHL, WHL.data(), sizeof(float2) * Qp);
-    up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
-    up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
-    if (st == PWC_OK) st = from_hip(pwc::launch_table_build(t, s));
-    if (st == PWC_OK) st = from_hip(pwc::launch_ktab_build(t, s));
-    // The host staging vectors die with this frame: wait for the stream.
-    const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
-    if (st == PWC_OK) st = st_sync;
+    pwc::TableSetup su;
+    pwc_status st = pwc::plan_table(L, n2max, m, h->t, su);
+    if (st == PWC_OK) st = pwc::build_table(h->t, su, static_cast<hipStream_t>(stream));
     if (st != PWC_OK) {
-        free_table(t);
         delete h;
         return st;
     }
@@ -261,7 +277,7 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
 
 pwc_status pwc_table_destroy(pwc_table *t) {
     if (!t) return PWC_OK;
-    free_table(t->t);
+    pwc::free_table(t->t);
     delete t;
     return PWC_OK;
 }

@@ -96,6 +96,16 @@ struct Table {
     int *d_err = nullptr;           // kernel error word
 };
 
+// api.cpp: table set-up in two phases.  plan_table forms the basis, mesh,
+// fold map and layouts on the host and sets t.bytes; build_table allocates,
+// uploads and runs the table kernels (waits for the stream).
+struct TableSetup {
+    std::vector<int32_t> fold, reps;
+};
+pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
+pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s);
+void free_table(Table &t);
+
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s);
 // reconstruct_kernels.hip

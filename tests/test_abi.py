@@ -92,3 +92,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pw, "_lib", None)
     with pytest.raises(ImportError):
         pw.lib()
+
+
+def test_server_create_rejects_bad_arguments(lib):
+    lib.pwc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    assert lib.pwc_server_create(0, 4, ctypes.byref(h)) == 1
+    assert lib.pwc_server_create(1 << 30, 0, ctypes.byref(h)) == 1
+    assert lib.pwc_server_create(1 << 30, 65, ctypes.byref(h)) == 1
+    assert lib.pwc_server_create(1 << 30, 4, None) == 1
+    lib.pwc_server_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.pwc_server_destroy(None) == 0

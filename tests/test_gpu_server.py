@@ -1,0 +1,141 @@
+"""GPU tests of the continuous-batching server (pwc_server_*)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pw():
+    import torch
+    import paper_1502_08043_amd as pw
+    assert torch.cuda.is_available()
+    return pw
+
+
+def _requests(pw, keys, count, seed):
+    """A seeded mix of reconstruct and energies requests over the given keys."""
+    import torch
+    g = workloads.rng(seed)
+    reqs = []
+    basis_n = {}
+    for k in keys:
+        with pw.Table(*k) as t:
+            b = t.basis().astype(np.int64)
+            basis_n[k] = (t.N, (b * b).sum(1))
+    for r in range(count):
+        k = keys[int(g.integers(0, len(keys)))]
+        N, n2 = basis_n[k]
+        prec = int(g.integers(0, 2))
+        if g.uniform() < 0.7:
+            n = int(np.exp(g.uniform(np.log(1e3), np.log(2e5))))
+            q = torch.from_numpy(workloads.uniform_quads(N, n, seed=seed * 1000 + r)).cuda()
+            reqs.append(("rec", k, prec, q, None))
+        else:
+            M = int((n2 <= int(g.integers(1, 10))).sum())
+            occ = torch.arange(M, dtype=torch.int32, device="cuda")
+            reqs.append(("ene", k, prec, occ, int(g.integers(0, 3))))
+    return reqs
+
+
+def _run(pw, srv, reqs, together):
+    import torch
+    outs, tickets = [], []
+    for kind, k, prec, x, algo in reqs:
+        L, n2max, Q = k
+        if kind == "rec":
+            out = torch.full((x.shape[0],), -1.0, dtype=torch.float64, device="cuda")
+            t = srv.submit_reconstruct(L, n2max, x, out, precision=prec, n_nodes=Q)
+        else:
+            out = torch.full((2,), -1.0, dtype=torch.float64, device="cuda")
+            t = srv.submit_energies(L, n2max, x, out, precision=prec, algo=algo, n_nodes=Q)
+        outs.append(out)
+        if together:
+            tickets.append(t)
+        else:
+            res = srv.wait(t)
+            assert res.status == pw.OK, res.status
+    for t in tickets:
+        res = srv.wait(t)
+        assert res.status == pw.OK, res.status
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_each_result_is_identical_alone_and_in_the_mix(pw):
+    import torch
+    keys = [(1.0, 40, 64), (2.0, 25, 48), (0.7, 64, 32), (1.4, 36, 96)]
+    reqs = _requests(pw, keys, 40, seed=11)
+    with pw.Server(8 << 30, max_inflight=6) as srv:
+        alone = _run(pw, srv, reqs, together=False)
+        srv.reset_stats()
+        mixed = _run(pw, srv, reqs, together=True)
+        st = srv.stats()
+    say(f"[server] mix of {len(reqs)}: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms, "
+        f"{st['integrals_per_s']:.3g} integrals/s, builds {st['table_builds']}")
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a, b)
+    # and identical to the library called directly
+    for (kind, k, prec, x, algo), a in list(zip(reqs, alone))[:12]:
+        with pw.Table(*k) as t:
+            if kind == "rec":
+                d = t.reconstruct(x, precision=prec).cpu().numpy()
+            else:
+                d = t.energies_async(x, precision=prec, algo=algo).cpu().numpy()
+            t.sync()
+        assert np.array_equal(a, d)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_small_budget_queues_and_evicts_but_never_fails(pw):
+    import torch
+    keys = [(L, 400, 128) for L in (0.5, 0.6, 0.7, 0.85, 1.0, 1.2, 1.4, 1.7)]
+    with pw.Table(*keys[0]) as t:
+        tb = t.device_bytes
+    budget = 64 << 20
+    assert 2 * tb < budget < len(keys) * tb        # forces eviction
+    reqs = _requests(pw, keys, 18, seed=5)
+    with pw.Server(8 << 30, max_inflight=4) as big:
+        ref = _run(pw, big, reqs, together=False)
+    with pw.Server(budget, max_inflight=4) as srv:
+        got = _run(pw, srv, reqs, together=True)
+        st = srv.stats()
+    say(f"[server] budget 64 MiB, table {tb / 2**20:.1f} MiB: builds {st['table_builds']}, "
+        f"evictions {st['evictions']}, resident {st['resident_bytes'] / 2**20:.1f} MiB")
+    assert st["failed"] == 0 and st["completed"] == len(reqs)
+    assert st["evictions"] > 0 and st["resident_bytes"] <= budget
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_server_errors(pw):
+    import torch
+    q = torch.zeros((10, 4), dtype=torch.int32, device="cuda")
+    out = torch.empty(10, dtype=torch.float64, device="cuda")
+    with pw.Server(1 << 20, max_inflight=2) as srv:       # smaller than any 9171-PW table
+        t = srv.submit_reconstruct(1.0, 169, q, out, n_nodes=96)
+        assert srv.wait(t).status == pw.ERR_NOMEM
+        with pytest.raises(pw.PwcError) as ei:
+            srv.submit_reconstruct(1.0, 169, q, out, n_nodes=50)   # bad node count
+        assert ei.value.status == pw.ERR_ARG
+        with pytest.raises(pw.PwcError) as ei:
+            srv.wait(987654)
+        assert ei.value.status == pw.ERR_STATE
+    with pw.Server(1 << 30, max_inflight=2) as srv:
+        bad = torch.tensor([[0, 0, 0, 10 ** 6]], dtype=torch.int32, device="cuda")
+        o1 = torch.empty(1, dtype=torch.float64, device="cuda")
+        t = srv.submit_reconstruct(1.0, 9, bad, o1, n_nodes=48)
+        assert srv.wait(t).status == pw.ERR_RANGE
+        assert np.isnan(o1.cpu().numpy()[0])
+        occ = torch.arange(7, dtype=torch.int32, device="cuda")
+        e = torch.empty(2, dtype=torch.float64, device="cuda")
+        t = srv.submit_energies(1.0, 600, occ, e, algo=pw.PAIR_KTABLE, n_nodes=16)
+        assert srv.wait(t).status == pw.ERR_ARG
