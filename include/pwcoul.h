@@ -193,6 +193,18 @@ PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, i
                            double *d_out, pwc_precision p, void *stream);
 
 /*
+ * pwc_reconstruct that also reports how long each of its launches took on
+ * `stream` (HIP events between the launches), then waits for the stream.
+ * The reconstruction runs as a decode launch followed by P node-pass
+ * launches; h_ms[0] is the decode and h_ms[1 .. P] the passes (first slab
+ * of at most 2^27 quadruples).  *n_stages = 1 + P; PWC_ERR_ARG if
+ * max_stages < 1 + P.  Results are identical to pwc_reconstruct's.
+ */
+PWC_API pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
+                                           double *d_out, pwc_precision p, void *stream,
+                                           double *h_ms, int max_stages, int *n_stages);
+
+/*
  * Uniform-electron-gas energies of one spin channel (Sec. III) for the M
  * occupied orbitals d_occ (int32 basis indices [M]) with occupations d_f
  * (double [M], NULL = all ones):

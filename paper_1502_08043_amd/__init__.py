@@ -75,6 +75,8 @@ def lib():
             "pwc_energies_ex": (i32, [vp, vp, vp, i64, i32, i32, vp, vp]),
             "pwc_energies": (i32, [vp, vp, vp, i64, i32, vp, vp]),
             "pwc_sync": (i32, [vp, vp]),
+            "pwc_reconstruct_profile": (i32, [vp, vp, i64, vp, i32, vp, vp, i32,
+                                              ctypes.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -195,6 +197,19 @@ class Table:
                                      _dev_ptr(out, torch.float64, "out"), int(precision),
                                      _stream(stream)), "pwc_reconstruct")
         return out
+
+    def reconstruct_profile(self, quads, out=None, precision=FP64, stream=None):
+        """Like reconstruct, then waits; returns (out, per-launch ms [decode, pass 1..P])."""
+        n = quads.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=quads.device)
+        ms = np.zeros(64)
+        ns = ctypes.c_int()
+        _check(lib().pwc_reconstruct_profile(self.handle, _dev_ptr(quads, torch.int32, "quads"), n,
+                                             _dev_ptr(out, torch.float64, "out"), int(precision),
+                                             _stream(stream), ms.ctypes.data_as(ctypes.c_void_p),
+                                             64, ctypes.byref(ns)), "pwc_reconstruct_profile")
+        return out, ms[:ns.value].copy()
 
     def energies_async(self, occ, f=None, precision=FP64, out=None, stream=None,
                        algo=PAIR_AUTO):

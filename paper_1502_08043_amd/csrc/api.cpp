@@ -323,6 +323,33 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
                                             static_cast<hipStream_t>(stream)));
 }
 
+pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
+                                   double *d_out, pwc_precision p, void *stream, double *h_ms,
+                                   int max_stages, int *n_stages) {
+    if (!t || !h_ms || !n_stages || n <= 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!d_quads || !d_out) return PWC_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
+        return PWC_ERR_ARG;
+    const int stages = 1 + t->t.fl.nchunk;
+    *n_stages = stages;
+    if (max_stages < stages) return PWC_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<hipEvent_t> ev(stages + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s, ev.data());
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int k = 0; k < stages && e == hipSuccess; ++k) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        h_ms[k] = ms;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    return from_hip(e);
+}
+
 pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const double *d_f,
                            int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
                            void *stream) {

@@ -109,8 +109,11 @@ void free_table(Table &t);
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s);
 // reconstruct_kernels.hip
+// stage_ev: optional array of nchunk + 2 events (decode start, decode end,
+// end of every node pass), recorded for the first slab.
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
-                              double *d_out, pwc_precision p, hipStream_t s);
+                              double *d_out, pwc_precision p, hipStream_t s,
+                              hipEvent_t *stage_ev = nullptr);
 // pairsum_kernels.hip
 hipError_t launch_ktab_build(Table &t, hipStream_t s);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,

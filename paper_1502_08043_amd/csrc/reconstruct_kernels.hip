@@ -260,8 +260,11 @@ PassKernel pass_kernel(int p, int P) {
     return p == P - 1 ? k_rec_pass<A, false, true> : k_rec_pass<A, false, false>;
 }
 
+// stage_ev (optional): events recorded before the decode and after every
+// launch of the first slab, for per-stage timing.
 template <typename A>
-hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_t s) {
+hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_t s,
+                      hipEvent_t *stage_ev) {
     const int P = t.fl.nchunk;
     for (int p = 0; p < P; ++p) {
         const hipError_t err = hipFuncSetAttribute(
@@ -269,6 +272,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (err != hipSuccess) return err;
     }
+    hipError_t err0 = hipSuccess;
     const int64_t tile = static_cast<int64_t>(kThreads / kGroup) * kRows;
     // LDS copy of the basis (int32) and the fold map (int16) for the decode.
     const size_t maps_bytes = (sizeof(int32_t) * static_cast<size_t>(t.N) +
@@ -285,6 +289,8 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
         a.n = std::min<int64_t>(kRecSlab, a0.n - off);
         a.quads = a0.quads + off;
         a.out = a0.out + off;
+        hipEvent_t *ev = (off == 0) ? stage_ev : nullptr;
+        if (ev && (err0 = hipEventRecord(ev[0], s)) != hipSuccess) return err0;
         const int64_t dblocks = (a.n + kDecodeThreads * kDecodeBatch - 1) / (kDecodeThreads * kDecodeBatch);
         hipError_t err;
         if (maps_bytes <= static_cast<size_t>(kLdsMax)) {
@@ -297,6 +303,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
         }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
+        if (ev && (err = hipEventRecord(ev[1], s)) != hipSuccess) return err;
         const int64_t tiles = (a.n + tile - 1) / tile;
         const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, t.fl.grid_cap));
         for (int p = 0; p < P; ++p) {
@@ -304,6 +311,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
             hipLaunchKernelGGL(pass_kernel<A>(p, P), dim3(grid), dim3(kThreads), lds, s, a);
             err = hipGetLastError();
             if (err != hipSuccess) return err;
+            if (ev && (err = hipEventRecord(ev[2 + p], s)) != hipSuccess) return err;
         }
     }
     return hipSuccess;
@@ -312,7 +320,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
 }  // namespace
 
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
-                              pwc_precision p, hipStream_t s) {
+                              pwc_precision p, hipStream_t s, hipEvent_t *stage_ev) {
     if (n <= 0) return hipSuccess;
     PassArgs a{};
     a.quads = reinterpret_cast<const int4 *>(d_quads);
@@ -335,11 +343,11 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     if (p == PWC_MIXED) {
         a.tab = t.d_tauHL;
         a.w = t.d_WHL;
-        err = run_passes<FF>(a, t, lds, s);
+        err = run_passes<FF>(a, t, lds, s, stage_ev);
     } else {
         a.tab = t.d_tauF;
         a.w = t.d_Wpad;
-        err = run_passes<F64>(a, t, lds, s);
+        err = run_passes<F64>(a, t, lds, s, stage_ev);
     }
     const hipError_t e2 = hipFreeAsync(a.scratch, s);
     if (err == hipSuccess) err = e2;

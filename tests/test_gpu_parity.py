@@ -118,6 +118,16 @@ def test_reconstruct_ragged_sizes(pw, tables, n):
                        label=f"ragged n={n}")
 
 
+def test_reconstruct_profile_matches_and_times_every_launch(pw, tables):
+    import torch
+    t = tables(169, 96)
+    q = _dev(workloads.lookup_stream(9171, 925, 300000, 3), torch.int32)
+    ref = t.reconstruct(q)
+    out, ms = t.reconstruct_profile(q)
+    assert torch.equal(out, ref)
+    assert len(ms) == 1 + 4 and np.all(ms > 0)      # decode + 4 node passes of 24 nodes
+
+
 def test_reconstruct_empty(pw, tables):
     import torch
     t = tables(9, 48)
