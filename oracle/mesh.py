@@ -19,26 +19,62 @@ Mesh 2 (Sec. III, Table I right): interval 1 cut at beta_c * 5^{-7}, ...,
 beta_c * 5^{-1}, q points on each of the 8 pieces, plus q_tail tail points
 (the tail count is not printed; 8 is the default).
 
-Nodes come from numpy's Legendre module (Golub-Welsch eigenvalues), not from
-the Newton iteration the library uses.
+Gauss-Legendre rules are the roots of P_q and the weights 2/((1-x^2) P_q'^2),
+evaluated in 34-digit arithmetic (mpmath; numpy's eigenvalue nodes serve only
+as starting points of the Newton polish) and rounded to FP64 once, after the
+map to the interval -- and for the tail after beta = 1/t^2 and W = 2 w / t^3.
+numpy's own weights are not used: at q >= 90 they carry relative errors up to
+1e-11, above the 1e-12 parity bar.
 """
+import functools
+
+import mpmath as mp
 import numpy as np
+
+_DPS = 34
+
+
+@functools.lru_cache(maxsize=None)
+def _gl_unit(q: int):
+    """Nodes and weights on [-1, 1] as 34-digit mpf tuples, ascending."""
+    with mp.workdps(_DPS):
+        xs, ws = [], []
+        for g in np.polynomial.legendre.leggauss(q)[0]:
+            z = mp.mpf(float(g))
+            for _ in range(5):
+                p, pm = mp.legendre(q, z), mp.legendre(q - 1, z)
+                dp = q * (z * p - pm) / (z * z - 1)     # (z^2 - 1) P' = q (z P_q - P_{q-1})
+                z -= p / dp
+            p, pm = mp.legendre(q, z), mp.legendre(q - 1, z)
+            dp = q * (z * p - pm) / (z * z - 1)
+            xs.append(z)
+            ws.append(2 / ((1 - z * z) * dp * dp))
+        return tuple(xs), tuple(ws)
+
+
+def _gl_mp(q: int, a, b):
+    xs, ws = _gl_unit(q)
+    with mp.workdps(_DPS):
+        a, b = mp.mpf(a), mp.mpf(b)
+        half, mid = (b - a) / 2, (b + a) / 2
+        return [mid + half * x for x in xs], [half * w for w in ws]
 
 
 def gauss_legendre(q: int, a: float, b: float):
-    """q-point Gauss-Legendre nodes and weights on [a, b] (FP64)."""
+    """q-point Gauss-Legendre nodes and weights on [a, b] (FP64, correctly rounded)."""
     if q < 1:
         raise ValueError("q must be >= 1")
-    x, w = np.polynomial.legendre.leggauss(q)
-    half = 0.5 * (b - a)
-    mid = 0.5 * (b + a)
-    return mid + half * x, half * w
+    x, w = _gl_mp(q, a, b)
+    return np.array([float(v) for v in x]), np.array([float(v) for v in w])
 
 
 def _tail(q_tail: int, beta_c: float):
     """Tail nodes: GL in t on (0, beta_c^{-1/2}], beta = 1/t^2, W = 2 w / t^3."""
-    t, w = gauss_legendre(q_tail, 0.0, beta_c ** -0.5)
-    return 1.0 / (t * t), 2.0 * w / (t * t * t)
+    with mp.workdps(_DPS):
+        t, w = _gl_mp(q_tail, 0, 1 / mp.sqrt(mp.mpf(beta_c)))
+        beta = [1 / (x * x) for x in t]
+        W = [2 * y / (x * x * x) for x, y in zip(t, w)]
+    return np.array([float(v) for v in beta]), np.array([float(v) for v in W])
 
 
 def mesh1(q: int, beta_c: float = 1.0):

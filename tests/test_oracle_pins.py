@@ -53,39 +53,38 @@ def test_basis_sizes_and_order():
 
 # ----------------------------------------------------------------- mesh ----
 
-def _mp_gauss_legendre(q, dps=40):
-    """Roots of P_q polished by Newton in mpmath, weights 2/((1-x^2) P'_q^2)."""
+@pytest.mark.parametrize("degree", [2, 3, 4, 5, 6])
+def test_gauss_legendre_against_mpmath_quadrature_class_and_exactness(degree):
+    """mpmath's own Gauss-Legendre rule (3 * 2^(degree-1) points, computed by
+    its quadrature module) against the oracle's, and polynomial exactness."""
     import mpmath as mp
-    mp.mp.dps = dps
-    x0 = np.polynomial.legendre.leggauss(q)[0]
-    xs, ws = [], []
-    for g in x0:
-        x = mp.mpf(g)
-        for _ in range(6):
-            p, dp = mp.legendre(q, x), mp.diff(lambda t: mp.legendre(q, t), x)
-            x -= p / dp
-        dp = mp.diff(lambda t: mp.legendre(q, t), x)
-        xs.append(x)
-        ws.append(2 / ((1 - x * x) * dp * dp))
-    return xs, ws
-
-
-@pytest.mark.parametrize("q", [5, 8, 11, 15, 16, 20])
-def test_gauss_legendre_against_mpmath_and_exactness(q):
+    from mpmath.calculus.quadrature import GaussLegendre
+    with mp.workdps(34):
+        ref = sorted(GaussLegendre(mp.mp).calc_nodes(degree, mp.mp.prec), key=lambda t: t[0])
+    xr = np.array([float(a) for a, _ in ref])
+    wr = np.array([float(b) for _, b in ref])
+    q = len(ref)
     x, w = oracle.gauss_legendre(q, -1.0, 1.0)
-    xm, wm = _mp_gauss_legendre(q)
-    # numpy's Golub-Welsch weights carry up to ~7e-14 relative rounding error
-    # for q <= 20 (nodes are exact to an ulp); that is the oracle's mesh error.
-    assert np.max(np.abs(x - np.array([float(v) for v in xm]))) < 4e-16
-    wm = np.array([float(v) for v in wm])
-    assert np.max(np.abs(w - wm) / wm) < 1e-13
+    assert np.max(np.abs(x - xr)) <= 2.3e-16
+    assert np.max(np.abs(w - wr) / wr) <= 4.5e-16
     a, b = 0.3, 2.7
     x, w = oracle.gauss_legendre(q, a, b)
-    for k in range(2 * q):
+    for k in range(min(2 * q, 60)):
         exact = (b ** (k + 1) - a ** (k + 1)) / (k + 1)
-        # rounding of x**k grows like k ulps, the weights add ~1e-13
-        tol = (2e-13 + 4e-16 * k) * (w * np.abs(x) ** k).sum()
+        # rounding of x**k grows like k ulps
+        tol = (1e-15 + 4e-16 * k) * (w * np.abs(x) ** k).sum()
         assert abs((w * x ** k).sum() - exact) <= tol
+
+
+def test_gauss_legendre_high_order_tail_nodes_are_correctly_rounded():
+    """Mesh 1 of Table I reaches 180 points; its smallest tail nodes t ~ 1e-4
+    must be exact to rounding (W = 2 w / t^3 amplifies their error)."""
+    beta, W, n1 = oracle.mesh1(180)
+    tb, tw = beta[n1:], W[n1:]
+    # exactness of the tail rule on t^(2n) <-> beta^(-(n + 3/2)) for high n
+    for n in (0, 5, 40, 100, 179):
+        exact = 1.0 / (n + 0.5)
+        assert abs((tw * tb ** (-(n + 1.5))).sum() - exact) < 1e-14 * exact
 
 
 @pytest.mark.parametrize("beta_c", [1.0, 0.37, 2.5])
