@@ -1,0 +1,74 @@
+"""The paper's headline accuracy results on the GPU (Sec. III, Table I and Fig. 1).
+
+Exchange energy of M = 9171 same-spin electrons against the quadrature mesh
+(Table I, total column) and the E_x/E_KS curve over the 13 shell closings
+(Fig. 1), each checked against the paper's printed values and against the
+FP64 oracle's difference-histogram route.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    import paper_1502_08043_amd as pw
+    b = oracle.enumerate_basis(169)
+    h, R = oracle.diff_histogram(b)
+    occ = torch.arange(len(b), dtype=torch.int32, device="cuda")
+    return pw, b, h, R, occ
+
+
+def _meshes(pw):
+    g = json.load(open(os.path.join(GOLD, "table1.json")))
+    for Q, (_, tot) in g["mesh1"].items():
+        yield f"mesh1 Q={Q}", pw.Mesh.two_interval(int(Q)), oracle.mesh1(int(Q)), tot
+    for q, (_, tot) in g["mesh2"].items():
+        yield f"mesh2 8x{q}", pw.Mesh.geometric(int(q), 8), oracle.mesh2(int(q), 8), tot
+
+
+def test_table_one_every_mesh(setup):
+    pw, b, h, R, occ = setup
+    eks = oracle.e_ks(len(b))
+    for name, mesh, (beta, W, _), printed in _meshes(pw):
+        with pw.Table(1.0, 169, 0, mesh=mesh) as t:
+            for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
+                eh, ex = t.energies(occ, algo=algo)
+                ref = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W)
+                say(f"[table1] {name} algo={algo}: {ex / eks:.7f} (paper {printed}), "
+                    f"rel vs oracle {abs(ex - ref) / abs(ref):.1e}")
+                assert abs(ex / eks - printed) < 1.5e-6
+                assert abs(ex - ref) < 1e-12 * abs(ref)
+
+
+def test_fig_one_shell_curve(setup):
+    pw, b, h, R, occ = setup
+    g = json.load(open(os.path.join(GOLD, "shell_closings.json")))
+    beta, W, _ = oracle.mesh2(10, 8)
+    diag = oracle.tau_diag(beta, 26)
+    ratios = []
+    with pw.Table(1.0, 169, 0, mesh=pw.Mesh.geometric(10, 8)) as t:
+        for M in g["M"]:
+            eh, ex = t.energies(occ[:M])
+            hm, Rm = oracle.diff_histogram(b[:M])
+            ref = oracle.exchange_from_histogram(hm, Rm, diag, W)
+            assert abs(ex - ref) < 1e-12 * abs(ref)
+            ratios.append(ex / oracle.e_ks(M))
+    say("[fig1] E_x/E_KS: " + " ".join(f"{r:.6f}" for r in ratios))
+    assert np.all(np.diff(ratios) > 0)
+    x = np.array(g["M"], dtype=float) ** (-1.0 / 3.0)
+    slope, icpt = np.polyfit(x[-5:], np.array(ratios[-5:]), 1)
+    assert 0.99 < icpt < 1.0 and slope < 0
