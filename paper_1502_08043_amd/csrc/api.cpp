@@ -42,22 +42,45 @@ bool plan_chunks(int Q, size_t row_bytes, int *c_out, int *nchunk_out) {
     return true;
 }
 
-// Node passes of the reconstruction kernels: the largest pass width c (a
-// multiple of 8 nodes) whose [E][c] slab and weights fit in LDS, the fewest
-// passes P = ceil(Q / c), and c shrunk again to spread the padding.
-bool plan_fold(int Q, int E, int n_cu, pwc::FoldLayout &fl) {
+}  // namespace
+
+namespace pwc {
+
+// Node passes of the reconstruction kernels: G lanes per quadruple, W words
+// per lane, c = 2 G W nodes per pass, P = ceil(Q / c) passes.  The cost of a
+// layout is P times the larger of its LDS time (c node reads at the relative
+// bank sweeps per 16-lane phase of the layout) and its per-pass HBM stream of
+// packed entries and partial sums (worth about 15 node reads).  lanes =
+// words = 0 takes the cheapest layout whose slab fits; otherwise the given
+// one.
+bool plan_fold(int Q, int E, int lanes, int words, FoldLayout &fl) {
+    static const struct { int G, W; double sweeps; } kLayouts[] = {
+        {16, 1, 1.0}, {8, 2, 1.0}, {8, 1, 1.31}, {4, 2, 1.53}, {2, 4, 1.77}, {1, 8, 1.95},
+        {4, 1, 2.12}};
+    constexpr double kPassStream = 15.0;
+    double best = -1.0;
+    for (const auto &l : kLayouts) {
+        if (lanes && (l.G != lanes || l.W != words)) continue;
+        const int c = 2 * l.G * l.W;
+        if (static_cast<size_t>(E) * c * 8 > static_cast<size_t>(kLdsMax)) continue;
+        const int P = (Q + c - 1) / c;
+        const double cost = P * std::max(c * l.sweeps, kPassStream);
+        if (best < 0.0 || cost < best) {
+            best = cost;
+            fl.G = l.G;
+            fl.W = l.W;
+            fl.c = c;
+            fl.nchunk = P;
+        }
+    }
     fl.E = E;
-    const size_t per_node = (static_cast<size_t>(E) + 1) * 8;
-    int cmax = static_cast<int>(pwc::kLdsMax / per_node) / 8 * 8;
-    if (cmax < 8) return false;
-    const int P = (Q + cmax - 1) / cmax;
-    fl.nchunk = P;
-    fl.c = ((Q + P - 1) / P + 7) / 8 * 8;
-    fl.Qp = fl.c * P;
-    const size_t lds = per_node * fl.c;
-    fl.grid_cap = n_cu * std::max(1, std::min(2, static_cast<int>(pwc::kLdsMax / lds)));
-    return true;
+    fl.Qp = (Q + 31) / 32 * 32;
+    return best >= 0.0;
 }
+
+}  // namespace pwc
+
+namespace {
 
 float2 split_hilo(double v) {
     const float hi = static_cast<float>(v);
@@ -91,8 +114,7 @@ size_t carve(Table &t, size_t n_reps, char *base) {
     const size_t o_tau = take(sizeof(double) * Q * nd * nd);
     const size_t o_tauF = take(sizeof(double) * Qp * E);
     const size_t o_tauHL = take(sizeof(float2) * Qp * E);
-    const size_t o_Wpad = take(sizeof(double) * Qp);
-    const size_t o_WHL = take(sizeof(float2) * Qp);
+    const size_t o_Wcbrt = take(sizeof(double) * Q);
     const size_t o_diag = take(sizeof(double) * Qd * (K + 1));
     const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
     const size_t o_Wdiag = take(sizeof(double) * Qd);
@@ -111,8 +133,7 @@ size_t carve(Table &t, size_t n_reps, char *base) {
         t.d_tau = reinterpret_cast<double *>(base + o_tau);
         t.d_tauF = reinterpret_cast<double *>(base + o_tauF);
         t.d_tauHL = reinterpret_cast<float2 *>(base + o_tauHL);
-        t.d_Wpad = reinterpret_cast<double *>(base + o_Wpad);
-        t.d_WHL = reinterpret_cast<float2 *>(base + o_WHL);
+        t.d_Wcbrt = reinterpret_cast<double *>(base + o_Wcbrt);
         t.d_diag = reinterpret_cast<double *>(base + o_diag);
         t.d_diagHL = reinterpret_cast<float2 *>(base + o_diagHL);
         t.d_Wdiag = reinterpret_cast<double *>(base + o_Wdiag);
@@ -142,7 +163,7 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
     if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
         t.n_cu <= 0)
         t.n_cu = 256;
-    if (!plan_fold(t.Q, t.fl.E, t.n_cu, t.fl) ||
+    if (!plan_fold(t.Q, t.fl.E, 0, 0, t.fl) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
     // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
@@ -160,7 +181,6 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
     }
     carve(t, su.reps.size(), static_cast<char *>(t.d_block));
     const int Q = t.Q;
-    const size_t Qp = static_cast<size_t>(t.fl.Qp);
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     // Host-side inputs of the table kernels.
     std::vector<int32_t> packed(t.N);
@@ -174,13 +194,14 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
     gauss_legendre(kGlPanelPoints, 0.0, 1.0, glx, glw);
     gl = glx;
     gl.insert(gl.end(), glw.begin(), glw.end());
-    std::vector<double> Wpad(Qp, 0.0), Wdiag(Qd, 0.0);
-    std::vector<float2> WHL(Qp, make_float2(0.f, 0.f)), WdiagHL(Qd, make_float2(0.f, 0.f));
+    std::vector<double> Wcbrt(Q), Wdiag(Qd, 0.0);
+    std::vector<float2> WdiagHL(Qd, make_float2(0.f, 0.f));
     // Node q sits at flat slot q of every node-chunked layout; padded slots
     // carry zero weight.
     for (int q = 0; q < Q; ++q) {
-        Wpad[q] = t.h_W[q];
-        WHL[q] = split_hilo(t.h_W[q]);
+        // W_q^(1/3) multiplies each of the three factors of a node term in
+        // the folded tables (mesh weights are positive).
+        Wcbrt[q] = static_cast<double>(std::cbrt(static_cast<long double>(t.h_W[q])));
         Wdiag[q] = t.h_W[q];
         WdiagHL[q] = split_hilo(t.h_W[q]);
     }
@@ -201,8 +222,7 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
     up(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
     up(t.d_W, t.h_W.data(), sizeof(double) * Q);
     up(t.d_gl, gl.data(), sizeof(double) * gl.size());
-    up(t.d_Wpad, Wpad.data(), sizeof(double) * Qp);
-    up(t.d_WHL, WHL.data(), sizeof(float2) * Qp);
+    up(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
     up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
     up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
     if (st == PWC_OK) st = from_hip(launch_table_build(t, s));
@@ -289,6 +309,31 @@ pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_node
     if (nmax) *nmax = t->t.nmax;
     if (n_nodes) *n_nodes = t->t.Q;
     if (device_bytes) *device_bytes = t->t.bytes;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_layout(const pwc_table *t, int *lanes, int *words, int *nodes_per_pass,
+                            int *passes, int *entry_bytes) {
+    if (!t) return PWC_ERR_ARG;
+    if (lanes) *lanes = t->t.fl.G;
+    if (words) *words = t->t.fl.W;
+    if (nodes_per_pass) *nodes_per_pass = t->t.fl.c;
+    if (passes) *passes = t->t.fl.nchunk;
+    if (entry_bytes) *entry_bytes = pwc::packed_entry_bytes(t->t.fl.E);
+    return PWC_OK;
+}
+
+pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
+    if (!t) return PWC_ERR_ARG;
+    if (lanes == 0 && words != 0) return PWC_ERR_ARG;
+    if (lanes != 0) {
+        const bool ok = (lanes == 16 && words == 1) || ((lanes == 8 || lanes == 4) && (words == 1 || words == 2)) ||
+                        (lanes == 2 && words == 4) || (lanes == 1 && words == 8);
+        if (!ok) return PWC_ERR_ARG;
+    }
+    pwc::FoldLayout fl = t->t.fl;
+    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, fl)) return PWC_ERR_RANGE;
+    t->t.fl = fl;
     return PWC_OK;
 }
 

@@ -29,43 +29,58 @@ std::vector<int32_t> enumerate_basis(int n2max) {
     return out;
 }
 
+// Gauss-Legendre rules are formed in x87 extended precision (64-bit
+// significand) and rounded to FP64 once, after the map to [a, b] and, for the
+// tail, after beta = 1/t^2 and W = 2 w / t^3.  In plain FP64 the node nearest
+// an endpoint, a + h (1 - z) with z close to 1, loses about log10(1/(1 - z))
+// digits; the tail's smallest t then carries a relative error near 3e-14.
+using ext = long double;
+
 // Legendre P_q(z) and P_q'(z) by the three-term recurrence
 // (k + 1) P_{k+1} = (2k + 1) z P_k - k P_{k-1}.
-static void legendre(int q, double z, double *p, double *dp) {
-    double pk = 1.0, pkm1 = 0.0;
+static void legendre(int q, ext z, ext *p, ext *dp) {
+    ext pk = 1.0L, pkm1 = 0.0L;
     for (int k = 0; k < q; ++k) {
-        const double pk1 = ((2.0 * k + 1.0) * z * pk - k * pkm1) / (k + 1.0);
+        const ext pk1 = ((2.0L * k + 1.0L) * z * pk - k * pkm1) / (k + 1.0L);
         pkm1 = pk;
         pk = pk1;
     }
     *p = pk;
-    *dp = q * (z * pk - pkm1) / (z * z - 1.0);   // from (z^2 - 1) P' = q (z P_q - P_{q-1})
+    *dp = q * (z * pk - pkm1) / ((z - 1.0L) * (z + 1.0L));   // (z^2 - 1) P' = q (z P_q - P_{q-1})
 }
 
-void gauss_legendre(int q, double a, double b, std::vector<double> &x, std::vector<double> &w) {
-    x.assign(q, 0.0);
-    w.assign(q, 0.0);
-    const double half = 0.5 * (b - a), mid = 0.5 * (b + a);
+// q-point rule on [a, b] in extended precision, ascending nodes.
+static void gauss_legendre_ext(int q, ext a, ext b, std::vector<ext> &x, std::vector<ext> &w) {
+    x.assign(q, 0.0L);
+    w.assign(q, 0.0L);
+    const ext half = 0.5L * (b - a);
     for (int i = 0; i < (q + 1) / 2; ++i) {
         // Root i of P_q counted from z = 1, started from the Tricomi estimate
         // cos(pi (i + 3/4) / (q + 1/2)) and refined by Newton's method.
-        double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
-        double p = 0.0, dp = 1.0;
-        for (int it = 0; it < 64; ++it) {
+        ext z = std::cos(static_cast<ext>(M_PI) * (i + 0.75L) / (q + 0.5L));
+        ext p = 0.0L, dp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
             legendre(q, z, &p, &dp);
-            const double step = p / dp;
+            const ext step = p / dp;
             z -= step;
-            if (std::fabs(step) <= 1e-17 * std::fabs(z) + 1e-300) break;
+            if (std::fabs(step) <= 1e-21L * std::fabs(z) + 1e-300L) break;
         }
+        if (q % 2 == 1 && i == q / 2) z = 0.0L;   // the middle root is exactly 0
         legendre(q, z, &p, &dp);
-        const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
-        // ascending order: the largest root goes last
-        x[q - 1 - i] = mid + half * z;
-        x[i] = mid - half * z;
+        const ext wi = 2.0L / ((1.0L - z) * (1.0L + z) * dp * dp);
+        // Each node measured from its nearer end: a + h (1 - z) and b - h (1 - z).
+        x[i] = a + half * (1.0L - z);
+        x[q - 1 - i] = b - half * (1.0L - z);
         w[q - 1 - i] = half * wi;
         w[i] = half * wi;
     }
-    if (q % 2 == 1) x[q / 2] = mid;   // the middle root is exactly 0
+}
+
+void gauss_legendre(int q, double a, double b, std::vector<double> &x, std::vector<double> &w) {
+    std::vector<ext> xe, we;
+    gauss_legendre_ext(q, a, b, xe, we);
+    x.assign(xe.begin(), xe.end());
+    w.assign(we.begin(), we.end());
 }
 
 bool mesh_valid(const pwc_mesh &m, int *n_nodes) {
@@ -112,11 +127,12 @@ bool build_mesh(const pwc_mesh &m, double L, std::vector<double> &beta, std::vec
     *n_interval1 = static_cast<int>(beta.size());
     // Tail (Eqs. 11-13): Gauss-Legendre in t = beta^{-1/2} on (0, beta_c^{-1/2}];
     // d beta = -2 t^{-3} dt, so node t maps to beta = 1/t^2 with weight 2 w / t^3.
-    gauss_legendre(m.q_tail, 0.0, 1.0 / std::sqrt(beta_c), x, w);
+    std::vector<ext> te, we;
+    gauss_legendre_ext(m.q_tail, 0.0L, 1.0L / std::sqrt(static_cast<ext>(beta_c)), te, we);
     for (int i = 0; i < m.q_tail; ++i) {
-        const double t = x[i];
-        beta.push_back(1.0 / (t * t));
-        W.push_back(2.0 * w[i] / (t * t * t));
+        const ext t = te[i];
+        beta.push_back(static_cast<double>(1.0L / (t * t)));
+        W.push_back(static_cast<double>(2.0L * we[i] / (t * t * t)));
     }
     return static_cast<int>(beta.size()) == Q;
 }

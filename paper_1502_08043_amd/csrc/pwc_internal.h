@@ -41,14 +41,16 @@ constexpr int kGlPanelPoints = 16;    // Gauss-Legendre points per panel
 constexpr int kGlPanels = 128;        // panels over the Gaussian's support
 
 // Folded-table layout of the reconstruction kernels (see reconstruct_kernels.hip):
-// P node passes of c nodes each; the [E][c] slab of one pass (plus c weights)
-// must fit in one workgroup's LDS.
+// P node passes of c = 2 G W nodes each, G lanes per quadruple with W
+// 16-byte words each; the [E][c] FP64 slab of one pass must fit in one
+// workgroup's LDS.
 struct FoldLayout {
     int E = 0;          // folded entries per node
-    int Qp = 0;         // nodes padded to nchunk * c (zero weight, zero tau)
-    int c = 0;          // nodes per pass (multiple of 8)
-    int nchunk = 0;     // passes P
-    int grid_cap = 0;   // persistent grid size
+    int Qp = 0;         // nodes padded to a multiple of 32 (zero weight, zero tau)
+    int G = 0;          // lanes per quadruple: 4, 8 or 16
+    int W = 0;          // words (node pairs) per lane and row: 1 or 2
+    int c = 0;          // nodes per pass, 2 G W
+    int nchunk = 0;     // passes P = ceil(Q / c)
 };
 constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
 constexpr int64_t kRecSlab = int64_t(1) << 27;   // quadruples per scratch slab
@@ -82,10 +84,9 @@ struct Table {
     double *d_gl = nullptr;         // [2][kGlPanelPoints] panel rule on [0, 1]
     double *d_prim = nullptr;       // [Q][2][K + 1]  (S, D)
     double *d_tau = nullptr;        // [Q][nd][nd]
-    double *d_tauF = nullptr;       // [E][Qp]  folded FP64
-    float2 *d_tauHL = nullptr;      // [E][Qp]  folded (hi, lo)
-    double *d_Wpad = nullptr;       // [Qp]
-    float2 *d_WHL = nullptr;        // [Qp]
+    double *d_tauF = nullptr;       // [E][Qp]  folded W_q^(1/3) tau_q, FP64
+    float2 *d_tauHL = nullptr;      // [E][Qp]  same, (hi, lo)
+    double *d_Wcbrt = nullptr;      // [Q]      W_q^(1/3)
     double *d_diag = nullptr;       // [dl.nchunk][K + 1][dl.c]  tau_q(m, -m), m >= 0
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
     double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]
@@ -102,6 +103,7 @@ struct Table {
 struct TableSetup {
     std::vector<int32_t> fold, reps;
 };
+bool plan_fold(int Q, int E, int lanes, int words, FoldLayout &fl);
 pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s);
 void free_table(Table &t);
@@ -109,6 +111,8 @@ void free_table(Table &t);
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s);
 // reconstruct_kernels.hip
+// Bytes of one decoded quadruple in the scratch stream (4 when E <= 1024).
+int packed_entry_bytes(int E);
 // stage_ev: optional array of nchunk + 2 events (decode start, decode end,
 // end of every node pass), recorded for the first slab.
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,

@@ -5,24 +5,47 @@
 // Layout.  tau is symmetric under (m, m') -> (m', m) and (m, m') -> (-m, -m'),
 // so the table is stored folded: E orbit representatives per node (about a
 // quarter of nd^2).  In HBM the folded table is [E][Qp]: the Qp (Q padded to
-// a multiple of 16 with zero weight) node values of one entry are contiguous.
+// a multiple of 32 with zero weight) node values of one entry are contiguous.
 //
-// Schedule: node passes.  The node range is cut into P chunks of c nodes,
-// each chunk's [E][c] slab small enough to sit in LDS.  Pass p is one launch
+// Schedule: node passes.  The node range is cut into P passes of c = 2G
+// nodes, small enough for the [E][c] slab to sit in LDS.  Pass p is one launch
 // of a persistent grid; every workgroup stages slab p once and then streams
 // every quadruple through it.  A decode kernel first turns each quadruple into
-// three folded-entry indices (8 bytes, kept in a scratch array); each pass
-// adds its c node terms to an FP64 partial sum kept in the output array, and
-// the last pass applies 1/(sqrt(pi) L).  Table refills from L2 are thus paid
-// once per workgroup and pass, and the per-quadruple traffic is a plain HBM
-// stream (16 B of indices and 8 B of entries for the decode; 8 B of entries
-// plus 8 B (first pass) or 16 B (later passes) of partial sum per pass).
+// its three folded-entry indices (4 bytes when E <= 1024, else 8, kept in a
+// scratch array); each pass adds its c node terms to an FP64 partial sum kept
+// in the output array, and the last pass applies 1/(sqrt(pi) L).  Table
+// refills from L2 are thus paid once per workgroup and pass, and the
+// per-quadruple traffic is a plain HBM stream.
 //
-// Within a pass, G lanes share one quadruple; lane s reads the node pairs
-// 2 (s + G k), k = 0 .. c/(2G) - 1, so the G lanes of a group read G adjacent
-// 16-byte words of one table row (a contiguous, aligned run: on gfx950 this
-// runs about 1.3x faster than independent random 16-byte reads).  Group
-// partial sums are combined with lane shuffles.
+// Lanes.  G lanes share one quadruple and each lane owns W 16-byte words
+// (2W nodes) of every row, c = 2 G W: word s + G k of chunk k.  The lane's
+// weights stay in registers and each row read of a quadruple is W aligned
+// runs of G words.  LDS serves a 16-lane phase of a 128-bit read in one
+// sweep of its 64 banks (256 bytes) when the phase's addresses fall in
+// distinct banks, so the layouts differ in how often a phase clashes:
+//   G = 16: a phase is one run of 256 bytes, always conflict-free;
+//   G = 8, W = 2: rows are 256 bytes; odd groups read their chunks in the
+//           opposite order, so the two runs of a phase are opposite halves;
+//   G = 8, W = 1: rows are 128 bytes, a phase holds two rows that clash when
+//           both sit in the same half, i.e. when their entry indices have
+//           equal parity;
+//   G = 4, W = 2: rows are 128 bytes read as two 64-byte quarters, odd groups
+//           second chunk first; groups 0 and 2 (1 and 3) of a phase clash when
+//           their entry indices have equal parity;
+//   G = 4, W = 1: four random 64-byte quarters per phase;
+//   G = 2, W = 4: rows are 128 bytes read as four 32-byte runs, group g
+//           taking chunk k ^ (g mod 4) at step k; groups g and g + 4 of a
+//           phase clash when their entry indices have equal parity;
+//   G = 1, W = 8: one lane per quadruple, word k ^ (g mod 8) at step k;
+//           lanes g and g + 8 of a phase clash on equal parity.
+// The groups that may clash hold quadruples of different stream position
+// (bit log2(8 / G) of their stream position e), so the decode
+// stores the entries of a quadruple in ascending parity for one of them and
+// descending for the other, which puts opposite halves together where it can.
+// Each lane accumulates one partial sum per quadruple of its group (R); a
+// butterfly of DPP exchanges inside the 16-lane row halves the set at each
+// step, so that after log2(G) steps lane s holds the full sum of one
+// quadruple, which it writes.
 #include <algorithm>
 #include <cmath>
 
@@ -33,8 +56,10 @@ namespace pwc {
 namespace {
 
 constexpr int kThreads = 1024;   // one workgroup per CU when the slab is large
-constexpr int kGroup = 4;        // lanes per quadruple
-constexpr int kRows = 4;         // quadruples per group and iteration
+// Quadruples per group and iteration: 4, fewer when each lane reads more
+// words per row (the loads of an iteration must fit in registers).
+template <int G>
+constexpr int rows_per_group() { return G == 1 ? 1 : G == 2 ? 2 : 4; }
 
 struct PassArgs {
     const int4 *quads;
@@ -43,10 +68,9 @@ struct PassArgs {
     int N;
     const int32_t *fold;
     int K, nd;
-    const void *tab;   // [E][Qp] double or float2
-    const void *w;     // [Qp]    double or float2
-    int E, Qp, c, q0;  // this pass: nodes [q0, q0 + c)
-    uint2 *scratch;    // [n] packed folded entries (multi-pass only)
+    const void *tab;   // [E][Qp] double or float2: W_q^(1/3) tau_q
+    int E, Qp, q0;     // this pass: nodes [q0, q0 + 2G)
+    void *scratch;     // [n] packed folded entries
     double pref;
     double *out;
     int *err;
@@ -57,78 +81,164 @@ __device__ __forceinline__ int bx(int v) { return (v << 24) >> 24; }
 __device__ __forceinline__ int by(int v) { return (v << 16) >> 24; }
 __device__ __forceinline__ int bz(int v) { return (v << 8) >> 24; }
 
-// FP64 arithmetic: one node term is ((x * y) * z) * w added with an FMA.
+// The folded entries carry W_q^(1/3) (the mesh weights are positive), so a
+// node term is the plain product of the three entries.
+// FP64 arithmetic: one node term is (x * y) * z added with an FMA.
 struct F64 {
     using V = double2;   // two adjacent nodes
     struct Acc { double v; };
     __device__ static void zero(Acc &a) { a.v = 0.0; }
-    __device__ static void add2(Acc &a, V x, V y, V z, V w) {
-        a.v = fma(x.x * y.x * z.x, w.x, a.v);
-        a.v = fma(x.y * y.y * z.y, w.y, a.v);
+    __device__ static void add2(Acc &a, V x, V y, V z) {
+        a.v = fma(x.x * y.x, z.x, a.v);
+        a.v = fma(x.y * y.y, z.y, a.v);
     }
     __device__ static double value(const Acc &a) { return a.v; }
 };
 
-// Split-FP32 arithmetic: table entries and weights are (hi, lo) float pairs;
-// node terms are float-float products, summed with TwoSum compensation.
+// Split-FP32 arithmetic: table entries are (hi, lo) float pairs; node terms
+// are float-float products, summed with TwoSum compensation.
 struct FF {
     using V = float4;    // (hi0, lo0, hi1, lo1)
     struct Acc { float h, l; };
     __device__ static void zero(Acc &a) { a.h = a.l = 0.0f; }
-    __device__ static void add2(Acc &a, V x, V y, V z, V w) {
-        ff_acc(a.h, a.l, ff_mul(ff_mul(ff_mul(ff{x.x, x.y}, ff{y.x, y.y}), ff{z.x, z.y}), ff{w.x, w.y}));
-        ff_acc(a.h, a.l, ff_mul(ff_mul(ff_mul(ff{x.z, x.w}, ff{y.z, y.w}), ff{z.z, z.w}), ff{w.z, w.w}));
+    __device__ static void add2(Acc &a, V x, V y, V z) {
+        ff_acc(a.h, a.l, ff_mul(ff_mul(ff{x.x, x.y}, ff{y.x, y.y}), ff{z.x, z.y}));
+        ff_acc(a.h, a.l, ff_mul(ff_mul(ff{x.z, x.w}, ff{y.z, y.w}), ff{z.z, z.w}));
     }
     __device__ static double value(const Acc &a) { return ff_to_double(a.h, a.l); }
 };
 
-__device__ __forceinline__ uint2 pack3(int fx, int fy, int fz) {
-    return make_uint2(static_cast<uint32_t>(fx) | (static_cast<uint32_t>(fy) << 16),
-                      static_cast<uint32_t>(fz));
-}
+// Packed folded entries of one quadruple.  Pk32: three 10-bit fields and
+// a flag in bit 30 (E <= 1024); Pk64: 16-bit fields, the flag in bit 31 of
+// y.  The flag marks a quadruple with an out-of-range index; its fields are
+// zero, so it still addresses row 0.
+struct Pk32 {
+    using T = uint32_t;
+    static constexpr int kMaxE = 1024;
+    __device__ static T pack(int a, int b, int c) {
+        return static_cast<uint32_t>(a) | (static_cast<uint32_t>(b) << 10) |
+               (static_cast<uint32_t>(c) << 20);
+    }
+    __device__ static T flagged() { return 1u << 30; }
+    __device__ static uint32_t flag(T v) { return v >> 30; }
+    __device__ static void unpack(T v, int &a, int &b, int &c) {
+        a = v & 1023u;
+        b = (v >> 10) & 1023u;
+        c = (v >> 20) & 1023u;
+    }
+};
+struct Pk64 {
+    using T = uint2;
+    __device__ static T pack(int a, int b, int c) {
+        return make_uint2(static_cast<uint32_t>(a) | (static_cast<uint32_t>(b) << 16),
+                          static_cast<uint32_t>(c));
+    }
+    __device__ static T flagged() { return make_uint2(0u, 1u << 31); }
+    __device__ static uint32_t flag(T v) { return v.y >> 31; }
+    __device__ static void unpack(T v, int &a, int &b, int &c) {
+        a = v.x & 0xffffu;
+        b = v.x >> 16;
+        c = v.y & 0xffffu;
+    }
+};
 
-// Sum over the 4 lanes of a quad (lanes 4j .. 4j+3) with DPP quad permutes:
-// no LDS traffic.  quad_perm selectors: 0xB1 = (1,0,3,2), 0x4E = (2,3,0,1).
+// Lane exchanges inside a 16-lane DPP row.  quad_perm 0xB1 = (1,0,3,2),
+// 0x4E = (2,3,0,1); row half mirror (0x141) pairs lane i with 7 - i, row
+// mirror (0x140) with 15 - i.
 template <int CTRL>
-__device__ __forceinline__ double quad_swap(double v) {
+__device__ __forceinline__ double dpp_take(double v) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double quad_sum(double v) {
-    v += quad_swap<0xB1>(v);
-    return v + quad_swap<0x4E>(v);
-}
-
-// Per-iteration loads of one lane: the packed entries and (after the first
-// pass) the partial sums, issued one grid-stride iteration ahead of their use.
-template <bool FIRST, int R>
+// Per-iteration loads of one lane, issued one grid-stride iteration ahead
+// of their use: the packed entries of the group's R quadruples and, after
+// the first pass, the partial sum of the quadruple this lane writes.
+template <typename PK, int R>
 struct Stream {
-    uint2 pk[R];
-    double prev[R];
-    __device__ __forceinline__ void load(const PassArgs &a, int64_t base, int NG, int g) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t e = base + r * NG + g;
-            if (e < a.n) {
-                pk[r] = a.scratch[e];
-                if (!FIRST) prev[r] = a.out[e];
-            }
-        }
-    }
+    typename PK::T pk[R];
+    double prev;
 };
 
-// Decode every quadruple into its packed folded entries; an out-of-range
-// index leaves the invalid marker (y = 0xffffffff) and raises the error word.
-// A streaming kernel with many waves per CU.  Each quadruple needs 7
-// dependent random gathers (4 basis vectors, 3 fold entries); when the basis
-// and the fold map fit, they are staged in LDS first, where random gathers
-// are far cheaper than divergent L1/L2 accesses.
-constexpr uint32_t kInvalid = 0xffffffffu;
-constexpr int kDecodeThreads = 256, kDecodeBatch = 4;
+// Butterfly step: lanes on the `up` side keep b and send a, the others keep
+// a and send b; the partner (DPP pattern CTRL) is on the opposite side.
+template <int CTRL>
+__device__ __forceinline__ double bfly(double a, double b, bool up) {
+    return (up ? b : a) + dpp_take<CTRL>(up ? a : b);
+}
 
-template <bool LDS_MAPS>
-__global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a) {
+// Reduce the R per-lane partial sums of a G-lane group.  On return lane s
+// holds the full sum of quadruple own_row<G>(s).
+template <int G>
+__device__ __forceinline__ int own_row(int s) {
+    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
+    return G == 1 ? 0 : G == 2 ? (s & 1) : ((s >> sh) & 3);
+}
+template <int G>
+__device__ __forceinline__ bool row_writer(int s) {
+    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
+    return G <= 2 ? true : (s & ((1 << sh) - 1)) == 0;
+}
+template <int G>
+__device__ __forceinline__ double group_reduce(const double *v, int s) {
+    if (G == 1) return v[0];
+    if (G == 2) return bfly<0xB1>(v[0], v[1], s & 1);   // partner s ^ 1
+    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
+    const bool up1 = (s >> (sh + 1)) & 1, up2 = (s >> sh) & 1;
+    double k0, k1, r;
+    if (G == 16) {          // row mirror: partner 15 - s; half mirror: 7 - s
+        k0 = bfly<0x140>(v[0], v[2], up1);
+        k1 = bfly<0x140>(v[1], v[3], up1);
+        r = bfly<0x141>(k0, k1, up2);
+        r += dpp_take<0x4E>(r);
+        r += dpp_take<0xB1>(r);
+    } else if (G == 8) {    // half mirror: partner 7 - s; then s ^ 2, s ^ 1
+        k0 = bfly<0x141>(v[0], v[2], up1);
+        k1 = bfly<0x141>(v[1], v[3], up1);
+        r = bfly<0x4E>(k0, k1, up2);
+        r += dpp_take<0xB1>(r);
+    } else {                // s ^ 2, then s ^ 1
+        k0 = bfly<0x4E>(v[0], v[2], up1);
+        k1 = bfly<0x4E>(v[1], v[3], up1);
+        r = bfly<0xB1>(k0, k1, up2);
+    }
+    return r;
+}
+
+// Decode every quadruple into its packed folded entries, in the parity
+// order its stream position asks for (above); an out-of-range index writes
+// the flagged word and raises the error word.  Positions n .. n_pad - 1 (the
+// stream padded to whole pass tiles) get row 0, so the node passes read the
+// stream without bounds checks.  A streaming kernel with many waves per CU.
+// Each quadruple needs 7 dependent random gathers (4 basis vectors, 3 fold
+// entries); when the basis and the fold map fit, they are staged in LDS
+// first, where random gathers are far cheaper than divergent L1/L2 accesses.
+constexpr int kDecodeThreads = 256, kDecodeBatch = 4;
+constexpr int kStreamPad = 1024;   // every pass tile divides it
+
+// Entries with odd parity last (ascending) or first (descending).  The two
+// groups of a phase that may clash differ in bit log2(8 / G) of the stream
+// position (G = 8: bit 0; 4: bit 1; 2: bit 2; 1: bit 3).
+__device__ __forceinline__ bool descending_at(int64_t e, int G) {
+    const int b = G >= 8 ? 0 : G == 4 ? 1 : G == 2 ? 2 : 3;
+    return (e >> b) & 1;
+}
+
+__device__ __forceinline__ void order_by_parity(int &a, int &b, int &c) {
+    auto cx = [](int &u, int &v) {
+        if ((u & 1) > (v & 1)) {
+            const int t = u;
+            u = v;
+            v = t;
+        }
+    };
+    cx(a, b);
+    cx(b, c);
+    cx(a, b);
+}
+
+template <typename PK, bool LDS_MAPS>
+__global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n_pad, int G) {
     extern __shared__ uint4 lds_raw[];
     int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw);
     int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
@@ -138,11 +248,12 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a) {
         for (int i = threadIdx.x; i < nd2; i += kDecodeThreads) lfold[i] = static_cast<int16_t>(a.fold[i]);
         __syncthreads();
     }
+    typename PK::T *out = static_cast<typename PK::T *>(a.scratch);
     const unsigned N = static_cast<unsigned>(a.N);
     const int K = a.K, nd = a.nd;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kDecodeThreads * kDecodeBatch;
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * kDecodeThreads * kDecodeBatch;
-         base < a.n; base += stride) {
+         base < n_pad; base += stride) {
         int4 q[kDecodeBatch];
 #pragma unroll
         for (int b = 0; b < kDecodeBatch; ++b) {
@@ -152,9 +263,13 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a) {
 #pragma unroll
         for (int b = 0; b < kDecodeBatch; ++b) {
             const int64_t e = base + b * kDecodeThreads + threadIdx.x;
-            if (e >= a.n) continue;
+            if (e >= n_pad) continue;
+            if (e >= a.n) {
+                out[e] = PK::pack(0, 0, 0);
+                continue;
+            }
             const int4 v = q[b];
-            uint2 pk = make_uint2(0u, kInvalid);
+            typename PK::T pk = PK::flagged();
             if (static_cast<unsigned>(v.x) < N && static_cast<unsigned>(v.y) < N &&
                 static_cast<unsigned>(v.z) < N && static_cast<unsigned>(v.w) < N) {
                 const int ni = LDS_MAPS ? lbasis[v.x] : a.basis[v.x];
@@ -164,125 +279,153 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a) {
                 const int ix = (bx(nk) - bx(ni) + K) * nd + (bx(nl) - bx(nj) + K);
                 const int iy = (by(nk) - by(ni) + K) * nd + (by(nl) - by(nj) + K);
                 const int iz = (bz(nk) - bz(ni) + K) * nd + (bz(nl) - bz(nj) + K);
-                const int fx = LDS_MAPS ? lfold[ix] : a.fold[ix];
-                const int fy = LDS_MAPS ? lfold[iy] : a.fold[iy];
-                const int fz = LDS_MAPS ? lfold[iz] : a.fold[iz];
-                pk = pack3(fx, fy, fz);
+                int fx = LDS_MAPS ? lfold[ix] : a.fold[ix];
+                int fy = LDS_MAPS ? lfold[iy] : a.fold[iy];
+                int fz = LDS_MAPS ? lfold[iz] : a.fold[iz];
+                order_by_parity(fx, fy, fz);
+                if (descending_at(e, G)) {
+                    const int t = fx;
+                    fx = fz;
+                    fz = t;
+                }
+                pk = PK::pack(fx, fy, fz);
             } else {
                 atomicOr(a.err, 1);
             }
-            a.scratch[e] = pk;
+            out[e] = pk;
         }
     }
 }
 
-template <typename A, bool FIRST, bool LAST>
+// One node pass.  LDS: the slab [E][G W] of 16-byte words (nodes q0 ..
+// q0 + c - 1 of every folded entry).  Lane s of group g reads, for each of
+// its R quadruples e = base + r NG + g, its W words of the three rows.
+template <typename A, int G, int W, typename PK, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     using V = typename A::V;
-    extern __shared__ uint4 lds_raw[];
-    constexpr int G = kGroup, R = kRows, NG = kThreads / G, TILE = NG * R;
-    static_assert(G == 4, "the group reduction is a DPP quad sum");
-    V *lds = reinterpret_cast<V *>(lds_raw);
-    const int half = a.c / 2;                   // 16-byte words per table row in LDS
-    V *lw = lds + static_cast<size_t>(a.E) * half;
+    using T = typename PK::T;
+    // A static slab: its LDS address is known when instructions are
+    // selected, so row addresses need no base add.  One workgroup per CU
+    // either way (1024 lanes of up to 128 registers).
+    __shared__ uint4 lds_raw[kLdsMax / 16];
+    constexpr int NG = kThreads / G, R = rows_per_group<G>(), TILE = NG * R;
+    constexpr int ROWB = G * W * 16;                    // bytes per slab row
+    // Groups of one phase whose runs would share banks read their W chunks in
+    // different orders: group g takes chunk k ^ (g mod W) at step k.
+    constexpr bool ROT = (W > 1 && G < 16);
+    static_assert(kStreamPad % TILE == 0, "the padded stream covers every tile");
     const int s = threadIdx.x % G, g = threadIdx.x / G;
+    const int rot = ROT ? (g & (W - 1)) : 0;
+    const int own = own_row<G>(s);                      // quadruple this lane writes
+    const bool writer = row_writer<G>(s);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * TILE;
     int64_t base = static_cast<int64_t>(blockIdx.x) * TILE;
-    Stream<FIRST, R> nxt;
-    nxt.load(a, base, NG, g);                   // overlaps the slab staging
-    // Stage the slab [E][c] of nodes [q0, q0 + c) and its weights.
+    const T *sc = static_cast<const T *>(a.scratch) + g;
+
+    auto load = [&](Stream<PK, R> &st, int64_t b) {
+        const T *p = sc + b;
+#pragma unroll
+        for (int r = 0; r < R; ++r) st.pk[r] = p[r * NG];
+        const int64_t e = b + own * NG + g;
+        if (!FIRST && writer && e < a.n) st.prev = a.out[e];
+    };
+    Stream<PK, R> s0{}, s1{};
+    if (base < a.n) load(s0, base);                     // overlaps the slab staging
     {
+        V *dst = reinterpret_cast<V *>(lds_raw);
         const V *src = static_cast<const V *>(a.tab) + a.q0 / 2;
-        const int row = a.Qp / 2, words = a.E * half;
+        const int row = a.Qp / 2, words = a.E * G * W;
         for (int i = threadIdx.x; i < words; i += kThreads) {
-            const int e = i / half, j = i - e * half;
-            lds[i] = src[static_cast<size_t>(e) * row + j];
+            const int e = i / (G * W), j = i % (G * W);
+            dst[i] = src[static_cast<size_t>(e) * row + j];
         }
-        const V *ws = static_cast<const V *>(a.w) + a.q0 / 2;
-        for (int i = threadIdx.x; i < half; i += kThreads) lw[i] = ws[i];
     }
+    const char *lb = reinterpret_cast<const char *>(lds_raw);
+    const uint32_t lane_b = static_cast<uint32_t>((s + G * rot) * 16);
     __syncthreads();
-    const int pairs = half / G;
-    for (; base < a.n; base += stride) {
-        const Stream<FIRST, R> cur = nxt;
-        if (base + stride < a.n) nxt.load(a, base + stride, NG, g);
-        uint32_t pxy[R], pz[R];
-        double prev[R];
+
+    auto body = [&](const Stream<PK, R> &st, int64_t b) {
+        V x[R][W], y[R][W], z[R][W];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t e = base + r * NG + g;
-            int fx = 0, fy = 0, fz = 0;
-            prev[r] = 0.0;
-            if (e < a.n) {
-                if (cur.pk[r].y == kInvalid) {
-                    prev[r] = NAN;   // set by the first pass, carried by the others
-                } else {
-                    fx = cur.pk[r].x & 0xffffu;
-                    fy = cur.pk[r].x >> 16;
-                    fz = cur.pk[r].y;
-                }
-                if (!FIRST) prev[r] = cur.prev[r];
+            int f0, f1, f2;
+            PK::unpack(st.pk[r], f0, f1, f2);
+            const uint32_t a0 = f0 * ROWB + lane_b, a1 = f1 * ROWB + lane_b, a2 = f2 * ROWB + lane_b;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                // chunk k ^ rot: row base + 16 (s + G (k ^ rot)) = a ^ (16 G k)
+                const uint32_t o = k * G * 16;
+                x[r][k] = *reinterpret_cast<const V *>(lb + (ROT ? (a0 ^ o) : a0 + o));
+                y[r][k] = *reinterpret_cast<const V *>(lb + (ROT ? (a1 ^ o) : a1 + o));
+                z[r][k] = *reinterpret_cast<const V *>(lb + (ROT ? (a2 ^ o) : a2 + o));
             }
-            // word offsets of this lane's first node pair in each row
-            pxy[r] = static_cast<uint32_t>(fx * half + s) | (static_cast<uint32_t>(fy * half + s) << 16);
-            pz[r] = static_cast<uint32_t>(fz * half + s);
         }
-        typename A::Acc acc[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) A::zero(acc[r]);
-        for (int k = 0; k < pairs; ++k) {
-            const int d = k * G;
-            const V w = lw[s + d];
-            V x[R], y[R], z[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                x[r] = lds[(pxy[r] & 0xffffu) + d];
-                y[r] = lds[(pxy[r] >> 16) + d];
-                z[r] = lds[pz[r] + d];
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) A::add2(acc[r], x[r], y[r], z[r], w);
-        }
+        double v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double v = quad_sum(A::value(acc[r]));
-            const int64_t e = base + r * NG + g;
-            if (s == 0 && e < a.n) a.out[e] = LAST ? (prev[r] + v) * a.pref : prev[r] + v;
+            typename A::Acc acc;
+            A::zero(acc);
+#pragma unroll
+            for (int k = 0; k < W; ++k) A::add2(acc, x[r][k], y[r][k], z[r][k]);
+            v[r] = A::value(acc);
         }
+        const double sum = group_reduce<G>(v, s);
+        const int64_t e = b + own * NG + g;
+        if (writer && e < a.n) {
+            double prev;
+            if (FIRST) {   // the first pass marks a bad quadruple; later passes carry the NaN
+                uint32_t bad = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) bad |= PK::flag(st.pk[r]) << r;
+                prev = ((bad >> own) & 1) ? NAN : 0.0;
+            } else {
+                prev = st.prev;
+            }
+            a.out[e] = LAST ? (prev + sum) * a.pref : prev + sum;
+        }
+    };
+
+    // Two stream buffers in turn: the loads for the next iteration are in
+    // flight while this one computes.
+    while (base < a.n) {
+        if (base + stride < a.n) load(s1, base + stride);
+        body(s0, base);
+        base += stride;
+        if (base >= a.n) break;
+        if (base + stride < a.n) load(s0, base + stride);
+        body(s1, base);
+        base += stride;
     }
 }
 
 using PassKernel = void (*)(PassArgs);
 
-template <typename A>
+template <typename A, int G, int W, typename PK>
 PassKernel pass_kernel(int p, int P) {
-    if (p == 0) return P == 1 ? k_rec_pass<A, true, true> : k_rec_pass<A, true, false>;
-    return p == P - 1 ? k_rec_pass<A, false, true> : k_rec_pass<A, false, false>;
+    if (p == 0) return P == 1 ? k_rec_pass<A, G, W, PK, true, true> : k_rec_pass<A, G, W, PK, true, false>;
+    return p == P - 1 ? k_rec_pass<A, G, W, PK, false, true> : k_rec_pass<A, G, W, PK, false, false>;
 }
 
 // stage_ev (optional): events recorded before the decode and after every
 // launch of the first slab, for per-stage timing.
-template <typename A>
-hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_t s,
-                      hipEvent_t *stage_ev) {
+template <typename A, int G, int W, typename PK>
+hipError_t run_passes(const PassArgs &a0, const Table &t, hipStream_t s, hipEvent_t *stage_ev) {
     const int P = t.fl.nchunk;
-    for (int p = 0; p < P; ++p) {
-        const hipError_t err = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(pass_kernel<A>(p, P)),
-            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (err != hipSuccess) return err;
-    }
+    const size_t lds = static_cast<size_t>(t.fl.E) * G * W * 16;   // slab bytes used
+    if (lds > static_cast<size_t>(kLdsMax)) return hipErrorInvalidValue;
     hipError_t err0 = hipSuccess;
-    const int64_t tile = static_cast<int64_t>(kThreads / kGroup) * kRows;
+    constexpr int64_t tile = static_cast<int64_t>(kThreads / G) * rows_per_group<G>();
     // LDS copy of the basis (int32) and the fold map (int16) for the decode.
     const size_t maps_bytes = (sizeof(int32_t) * static_cast<size_t>(t.N) +
                                sizeof(int16_t) * static_cast<size_t>(t.nd) * t.nd + 15) / 16 * 16;
-    if (maps_bytes <= static_cast<size_t>(kLdsMax)) {
-        const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_decode<true>),
+    const bool maps_fit = maps_bytes <= static_cast<size_t>(kLdsMax);
+    if (maps_fit) {
+        const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_decode<PK, true>),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    static_cast<int>(maps_bytes));
         if (err != hipSuccess) return err;
     }
+    const int per_cu = 1;   // the static slab takes the CU's LDS
     // Slabs bound the scratch array: at most kRecSlab quadruples per slab.
     for (int64_t off = 0; off < a0.n; off += kRecSlab) {
         PassArgs a = a0;
@@ -291,24 +434,26 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
         a.out = a0.out + off;
         hipEvent_t *ev = (off == 0) ? stage_ev : nullptr;
         if (ev && (err0 = hipEventRecord(ev[0], s)) != hipSuccess) return err0;
-        const int64_t dblocks = (a.n + kDecodeThreads * kDecodeBatch - 1) / (kDecodeThreads * kDecodeBatch);
+        const int64_t n_pad = (a.n + kStreamPad - 1) / kStreamPad * kStreamPad;
+        const int64_t dblocks = (n_pad + kDecodeThreads * kDecodeBatch - 1) / (kDecodeThreads * kDecodeBatch);
         hipError_t err;
-        if (maps_bytes <= static_cast<size_t>(kLdsMax)) {
-            const int per_cu = std::max(1, std::min(8, static_cast<int>(kLdsMax / std::max<size_t>(maps_bytes, 1))));
-            const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * per_cu));
-            hipLaunchKernelGGL(k_decode<true>, dim3(dgrid), dim3(kDecodeThreads), maps_bytes, s, a);
+        if (maps_fit) {
+            const int dper = std::max(1, std::min(8, static_cast<int>(kLdsMax / std::max<size_t>(maps_bytes, 1))));
+            const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * dper));
+            hipLaunchKernelGGL((k_decode<PK, true>), dim3(dgrid), dim3(kDecodeThreads), maps_bytes, s, a, n_pad, G);
         } else {
             const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * 16));
-            hipLaunchKernelGGL(k_decode<false>, dim3(dgrid), dim3(kDecodeThreads), 0, s, a);
+            hipLaunchKernelGGL((k_decode<PK, false>), dim3(dgrid), dim3(kDecodeThreads), 0, s, a, n_pad, G);
         }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
         if (ev && (err = hipEventRecord(ev[1], s)) != hipSuccess) return err;
         const int64_t tiles = (a.n + tile - 1) / tile;
-        const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, t.fl.grid_cap));
+        const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, int64_t(t.n_cu) * per_cu));
         for (int p = 0; p < P; ++p) {
-            a.q0 = p * t.fl.c;
-            hipLaunchKernelGGL(pass_kernel<A>(p, P), dim3(grid), dim3(kThreads), lds, s, a);
+            a.q0 = p * 2 * G * W;
+            const PassKernel kern = pass_kernel<A, G, W, PK>(p, P);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, a);
             err = hipGetLastError();
             if (err != hipSuccess) return err;
             if (ev && (err = hipEventRecord(ev[2 + p], s)) != hipSuccess) return err;
@@ -317,7 +462,28 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, size_t lds, hipStream_
     return hipSuccess;
 }
 
+template <typename A, int G, int W>
+hipError_t run_pack(const PassArgs &a, const Table &t, hipStream_t s, hipEvent_t *ev) {
+    return t.fl.E <= Pk32::kMaxE ? run_passes<A, G, W, Pk32>(a, t, s, ev)
+                                 : run_passes<A, G, W, Pk64>(a, t, s, ev);
+}
+
+template <typename A>
+hipError_t run_layout(const PassArgs &a, const Table &t, hipStream_t s, hipEvent_t *ev) {
+    const int G = t.fl.G, W = t.fl.W;
+    if (G == 16 && W == 1) return run_pack<A, 16, 1>(a, t, s, ev);
+    if (G == 8 && W == 2) return run_pack<A, 8, 2>(a, t, s, ev);
+    if (G == 8 && W == 1) return run_pack<A, 8, 1>(a, t, s, ev);
+    if (G == 4 && W == 2) return run_pack<A, 4, 2>(a, t, s, ev);
+    if (G == 2 && W == 4) return run_pack<A, 2, 4>(a, t, s, ev);
+    if (G == 1 && W == 8) return run_pack<A, 1, 8>(a, t, s, ev);
+    if (G == 4 && W == 1) return run_pack<A, 4, 1>(a, t, s, ev);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+int packed_entry_bytes(int E) { return E <= Pk32::kMaxE ? 4 : 8; }
 
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
                               pwc_precision p, hipStream_t s, hipEvent_t *stage_ev) {
@@ -332,22 +498,20 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.nd = t.nd;
     a.E = t.fl.E;
     a.Qp = t.fl.Qp;
-    a.c = t.fl.c;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.out = d_out;
     a.err = t.d_err;
-    const size_t lds = (static_cast<size_t>(a.E) + 1) * a.c * 8;
-    const size_t bytes = sizeof(uint2) * static_cast<size_t>(std::min<int64_t>(n, kRecSlab));
-    hipError_t err = hipMallocAsync(reinterpret_cast<void **>(&a.scratch), bytes, s);
+    const int64_t slab = std::min<int64_t>(n, kRecSlab);
+    const size_t bytes = static_cast<size_t>(packed_entry_bytes(t.fl.E)) *
+                         static_cast<size_t>((slab + kStreamPad - 1) / kStreamPad * kStreamPad);
+    hipError_t err = hipMallocAsync(&a.scratch, bytes, s);
     if (err != hipSuccess) return err;
     if (p == PWC_MIXED) {
         a.tab = t.d_tauHL;
-        a.w = t.d_WHL;
-        err = run_passes<FF>(a, t, lds, s, stage_ev);
+        err = run_layout<FF>(a, t, s, stage_ev);
     } else {
         a.tab = t.d_tauF;
-        a.w = t.d_Wpad;
-        err = run_passes<F64>(a, t, lds, s, stage_ev);
+        err = run_layout<F64>(a, t, s, stage_ev);
     }
     const hipError_t e2 = hipFreeAsync(a.scratch, s);
     if (err == hipSuccess) err = e2;

@@ -123,7 +123,7 @@ struct pwc_server {
 };
 
 size_t pwc_server::scratch_bytes(const pwc_request &r) const {
-    if (r.kind == PWC_REQ_RECONSTRUCT)
+    if (r.kind == PWC_REQ_RECONSTRUCT)   // decoded quadruples: at most 8 bytes each
         return sizeof(uint2) * static_cast<size_t>(std::min<int64_t>(r.n, pwc::kRecSlab)) + (1 << 16);
     return 1 << 20;   // pair-sum partials
 }

@@ -79,6 +79,7 @@ __device__ inline float2 split_hilo(double v) {
 
 struct AsmArgs {
     const double *beta;
+    const double *wcbrt;
     const double *prim;
     const int32_t *fold;
     const int32_t *reps;
@@ -109,12 +110,15 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
         v = -(sm + smp) / (M_PI * s * rb);
     }
     a.tau[(static_cast<size_t>(q) * a.nd + row) * a.nd + col] = v;
-    // Folded layout: only the orbit representative writes its slot.
+    // Folded layout: only the orbit representative writes its slot, scaled
+    // by W_q^(1/3) so that a node term of Eq. 14 is the plain product of
+    // three folded entries.
     const int f = a.fold[e];
     if (a.reps[2 * f] == m && a.reps[2 * f + 1] == mp) {
         const size_t idx = static_cast<size_t>(f) * a.Qp + q;
-        a.tauF[idx] = v;
-        a.tauHL[idx] = split_hilo(v);
+        const double vw = v * a.wcbrt[q];
+        a.tauF[idx] = vw;
+        a.tauHL[idx] = split_hilo(vw);
     }
     // Diagonal tau(m, -m) for m >= 0 (the exchange entries; even in m).
     if (s == 0 && m >= 0) {
@@ -131,7 +135,7 @@ hipError_t launch_table_build(Table &t, hipStream_t s) {
     hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    AsmArgs a{t.d_beta, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.Qp, t.dl.c,
+    AsmArgs a{t.d_beta, t.d_Wcbrt, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.Qp, t.dl.c,
               t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
     dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q);
     hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);

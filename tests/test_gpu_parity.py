@@ -53,8 +53,9 @@ def test_tables_basis_mesh_match_oracle(pw, tables, n2max, Q):
     o = P.setup(n2max, Q)
     assert np.array_equal(t.basis(), o["basis"])
     beta, W = t.mesh_nodes()
-    assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 1e-14
-    assert np.max(np.abs(W - o["W"]) / o["W"]) < 1e-13   # oracle weights: numpy leggauss
+    # both sides round an extended-precision rule once: agreement to an ulp or two
+    assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 5e-16
+    assert np.max(np.abs(W - o["W"]) / o["W"]) < 5e-16
     tau = t.copy_tables().cpu().numpy()
     assert tau.shape == o["tau"].shape
     scale = np.abs(o["tau"]).max(axis=(1, 2))
@@ -75,7 +76,8 @@ def test_tables_other_meshes(pw, kind):
         o = P.setup(9, mesh=("geometric", 5, 8), beta_c=0.25)
     with pw.Table(L, 9, 0, mesh=m) as t:
         beta, W = t.mesh_nodes()
-        assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 1e-14
+        assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 5e-16
+        assert np.max(np.abs(W - o["W"]) / o["W"]) < 5e-16
         tau = t.copy_tables().cpu().numpy()
         scale = np.abs(o["tau"]).max(axis=(1, 2))
         assert (np.abs(tau - o["tau"]).max(axis=(1, 2)) / scale).max() < P.TOL_TABLE
@@ -125,7 +127,57 @@ def test_reconstruct_profile_matches_and_times_every_launch(pw, tables):
     ref = t.reconstruct(q)
     out, ms = t.reconstruct_profile(q)
     assert torch.equal(out, ref)
-    assert len(ms) == 1 + 4 and np.all(ms > 0)      # decode + 4 node passes of 24 nodes
+    lay = t.layout()
+    assert lay["passes"] == -(-96 // lay["nodes_per_pass"])
+    assert len(ms) == 1 + lay["passes"] and np.all(ms > 0)
+
+
+ALL_LAYOUTS = [(16, 1), (8, 2), (8, 1), (4, 2), (2, 4), (1, 8), (4, 1)]
+C16 = [(8, 1), (4, 2), (2, 4), (1, 8)]             # 16 nodes per pass
+# (n2max, Q, default (lanes, words), bytes per decoded quadruple, layouts whose slab fits)
+LAYOUTS = [
+    (40, 64, (16, 1), 4, ALL_LAYOUTS),
+    (169, 96, (8, 1), 4, C16 + [(4, 1)]),
+    (256, 32, (8, 1), 8, C16 + [(4, 1)]),
+    (400, 128, (4, 1), 8, [(4, 1)]),
+]
+
+
+@pytest.mark.parametrize("n2max,Q,default,eb,fits", LAYOUTS)
+def test_reconstruct_every_lane_layout(pw, n2max, Q, default, eb, fits):
+    """Every lane layout and both packed-entry widths against the oracle, on
+    a ragged uniform stream, and the layouts against each other."""
+    import torch
+    o = P.setup(n2max, Q)
+    with pw.Table(1.0, n2max, Q) as t:
+        lay = t.layout()
+        assert ((lay["lanes"], lay["words"]), lay["entry_bytes"]) == (default, eb)
+        quads = workloads.uniform_quads(len(o["basis"]), 50001, seed=n2max)
+        dq = _dev(quads, torch.int32)
+        base = {}
+        for G, W in fits:
+            t.set_layout(G, W)
+            lay = t.layout()
+            assert (lay["lanes"], lay["words"]) == (G, W)
+            assert lay["nodes_per_pass"] == 2 * G * W and lay["passes"] == -(-Q // (2 * G * W))
+            _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} layout={G}x{W}")
+            for prec in (pw.FP64, pw.MIXED):
+                out = t.reconstruct(dq, precision=prec)
+                t.sync()
+                if prec in base:   # layouts differ only in rounding order
+                    tol = 1e-13 if prec == pw.FP64 else 1e-12
+                    assert (out - base[prec]).abs().max().item() <= tol * base[prec].abs().max().item()
+                else:
+                    base[prec] = out
+        for G, W in set(ALL_LAYOUTS) - set(fits):
+            with pytest.raises(pw.PwcError) as ei:
+                t.set_layout(G, W)
+            assert ei.value.status == pw.ERR_RANGE
+        with pytest.raises(pw.PwcError) as ei:
+            t.set_layout(16, 2)
+        assert ei.value.status == pw.ERR_ARG
+        t.set_layout(0, 0)
+        assert (t.layout()["lanes"], t.layout()["words"]) == default
 
 
 def test_reconstruct_empty(pw, tables):

@@ -100,7 +100,7 @@ def test_small_budget_queues_and_evicts_but_never_fails(pw):
     keys = [(L, 400, 128) for L in (0.5, 0.6, 0.7, 0.85, 1.0, 1.2, 1.4, 1.7)]
     with pw.Table(*keys[0]) as t:
         tb = t.device_bytes
-    budget = 64 << 20
+    budget = 3 * tb + (4 << 20)                     # three tables and the largest scratch
     assert 2 * tb < budget < len(keys) * tb        # forces eviction
     reqs = _requests(pw, keys, 18, seed=5)
     with pw.Server(8 << 30, max_inflight=4) as big:
@@ -108,7 +108,7 @@ def test_small_budget_queues_and_evicts_but_never_fails(pw):
     with pw.Server(budget, max_inflight=4) as srv:
         got = _run(pw, srv, reqs, together=True)
         st = srv.stats()
-    say(f"[server] budget 64 MiB, table {tb / 2**20:.1f} MiB: builds {st['table_builds']}, "
+    say(f"[server] budget {budget / 2**20:.1f} MiB, table {tb / 2**20:.1f} MiB: builds {st['table_builds']}, "
         f"evictions {st['evictions']}, resident {st['resident_bytes'] / 2**20:.1f} MiB")
     assert st["failed"] == 0 and st["completed"] == len(reqs)
     assert st["evictions"] > 0 and st["resident_bytes"] <= budget
