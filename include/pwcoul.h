@@ -170,19 +170,20 @@ PWC_API pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int
                           size_t *device_bytes);
 
 /*
- * Reconstruction layout of a table (Eq. 14 evaluated in node passes):
- * lanes = G lanes of a wavefront share one quadruple; words = W two-node
+ * Reconstruction layout of a table for precision p (Eq. 14 evaluated in node
+ * passes; each precision has its own default): lanes = G lanes of a
+ * wavefront share one quadruple; words = W two-node
  * words per lane; nodes_per_pass = 2 G W nodes of every folded table entry
  * are held on chip per pass; passes = ceil(Q / (2 G W)); entry_bytes = size
  * of one decoded quadruple in the reconstruction's scratch stream (4 when the
  * table has at most 1024 folded entries per node, else 8).  Any output
  * pointer may be NULL.
  */
-PWC_API pwc_status pwc_table_layout(const pwc_table *t, int *lanes, int *words,
+PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int *words,
                                     int *nodes_per_pass, int *passes, int *entry_bytes);
 
 /*
- * Force the reconstruction layout: (lanes, words) = (16, 1), (8, 2), (8, 1),
+ * Force the reconstruction layout of both precisions: (lanes, words) = (16, 1), (8, 2), (8, 1),
  * (4, 2), (2, 4), (1, 8) or (4, 1); (0, 0) restores the default choice.  Results agree
  * between layouts to rounding; only speed differs.  PWC_ERR_ARG for other
  * pairs, PWC_ERR_RANGE if the per-pass slab of that layout does not fit on

@@ -67,7 +67,7 @@ def lib():
             "pwc_table_destroy": (i32, [vp]),
             "pwc_table_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
-            "pwc_table_layout": (i32, [vp] + [ctypes.POINTER(i32)] * 5),
+            "pwc_table_layout": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 5),
             "pwc_table_set_layout": (i32, [vp, i32, i32]),
             "pwc_basis": (i32, [vp, vp]),
             "pwc_mesh_nodes": (i32, [vp, vp, vp]),
@@ -166,10 +166,11 @@ class Table:
     def __exit__(self, *exc):
         self.close()
 
-    def layout(self):
-        """Reconstruction layout: dict(lanes, words, nodes_per_pass, passes, entry_bytes)."""
+    def layout(self, precision=0):
+        """Reconstruction layout of one precision:
+        dict(lanes, words, nodes_per_pass, passes, entry_bytes)."""
         v = [ctypes.c_int() for _ in range(5)]
-        _check(lib().pwc_table_layout(self.handle, *[ctypes.byref(x) for x in v]),
+        _check(lib().pwc_table_layout(self.handle, int(precision), *[ctypes.byref(x) for x in v]),
                "pwc_table_layout")
         return dict(zip(("lanes", "words", "nodes_per_pass", "passes", "entry_bytes"),
                         (x.value for x in v)))

@@ -47,24 +47,27 @@ bool plan_chunks(int Q, size_t row_bytes, int *c_out, int *nchunk_out) {
 namespace pwc {
 
 // Node passes of the reconstruction kernels: G lanes per quadruple, W words
-// per lane, c = 2 G W nodes per pass, P = ceil(Q / c) passes.  The cost of a
-// layout is P times the larger of its LDS time (c node reads at the relative
-// bank sweeps per 16-lane phase of the layout) and its per-pass HBM stream of
-// packed entries and partial sums (worth about 15 node reads).  lanes =
-// words = 0 takes the cheapest layout whose slab fits; otherwise the given
-// one.
-bool plan_fold(int Q, int E, int lanes, int words, FoldLayout &fl) {
-    static const struct { int G, W; double sweeps; } kLayouts[] = {
-        {16, 1, 1.0}, {8, 2, 1.0}, {8, 1, 1.31}, {4, 2, 1.53}, {2, 4, 1.77}, {1, 8, 1.95},
-        {4, 1, 2.12}};
-    constexpr double kPassStream = 15.0;
+// per lane, c = 2 G W nodes per pass, P = ceil(Q / c) passes.  A layout's cost
+// is P times the larger of its compute time per pass and the pass's HBM
+// stream (packed entries in, partial sums in and out).  Compute times per
+// 16 nodes of 1e8 quadruples, in ms, measured on MI355X for each arithmetic
+// (the 4x1 layout estimated); the 16-node layouts on the 9171-planewave
+// table and the 32-node ones on the 5575-planewave table, both Q = 96.
+// lanes = words = 0 takes the cheapest layout whose slab fits; otherwise
+// the given one.
+bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl) {
+    static const struct { int G, W; double fp64, mixed; } kLayouts[] = {
+        {8, 2, 0.49, 0.83}, {16, 1, 0.61, 0.97}, {1, 8, 0.575, 0.835}, {4, 2, 0.58, 0.86},
+        {2, 4, 0.58, 0.79}, {8, 1, 0.66, 1.02}, {4, 1, 0.80, 1.10}};
+    constexpr double kPassStream = 0.30;   // ms per pass of 1e8 quadruples
     double best = -1.0;
     for (const auto &l : kLayouts) {
         if (lanes && (l.G != lanes || l.W != words)) continue;
         const int c = 2 * l.G * l.W;
         if (static_cast<size_t>(E) * c * 8 > static_cast<size_t>(kLdsMax)) continue;
         const int P = (Q + c - 1) / c;
-        const double cost = P * std::max(c * l.sweeps, kPassStream);
+        const double per16 = p == PWC_MIXED ? l.mixed : l.fp64;
+        const double cost = P * std::max(per16 * c / 16.0, kPassStream);
         if (best < 0.0 || cost < best) {
             best = cost;
             fl.G = l.G;
@@ -163,7 +166,8 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
     if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
         t.n_cu <= 0)
         t.n_cu = 256;
-    if (!plan_fold(t.Q, t.fl.E, 0, 0, t.fl) ||
+    t.flm.E = t.fl.E;
+    if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, t.flm) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
     // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
@@ -312,14 +316,15 @@ pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_node
     return PWC_OK;
 }
 
-pwc_status pwc_table_layout(const pwc_table *t, int *lanes, int *words, int *nodes_per_pass,
-                            int *passes, int *entry_bytes) {
-    if (!t) return PWC_ERR_ARG;
-    if (lanes) *lanes = t->t.fl.G;
-    if (words) *words = t->t.fl.W;
-    if (nodes_per_pass) *nodes_per_pass = t->t.fl.c;
-    if (passes) *passes = t->t.fl.nchunk;
-    if (entry_bytes) *entry_bytes = pwc::packed_entry_bytes(t->t.fl.E);
+pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int *words,
+                            int *nodes_per_pass, int *passes, int *entry_bytes) {
+    if (!t || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    const pwc::FoldLayout &fl = p == PWC_MIXED ? t->t.flm : t->t.fl;
+    if (lanes) *lanes = fl.G;
+    if (words) *words = fl.W;
+    if (nodes_per_pass) *nodes_per_pass = fl.c;
+    if (passes) *passes = fl.nchunk;
+    if (entry_bytes) *entry_bytes = pwc::packed_entry_bytes(fl.E);
     return PWC_OK;
 }
 
@@ -331,9 +336,12 @@ pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
                         (lanes == 2 && words == 4) || (lanes == 1 && words == 8);
         if (!ok) return PWC_ERR_ARG;
     }
-    pwc::FoldLayout fl = t->t.fl;
-    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, fl)) return PWC_ERR_RANGE;
+    pwc::FoldLayout fl = t->t.fl, flm = t->t.flm;
+    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP64, fl) ||
+        !pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_MIXED, flm))
+        return PWC_ERR_RANGE;
     t->t.fl = fl;
+    t->t.flm = flm;
     return PWC_OK;
 }
 
@@ -375,7 +383,7 @@ pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, i
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
-    const int stages = 1 + t->t.fl.nchunk;
+    const int stages = 1 + (p == PWC_MIXED ? t->t.flm : t->t.fl).nchunk;
     *n_stages = stages;
     if (max_stages < stages) return PWC_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);

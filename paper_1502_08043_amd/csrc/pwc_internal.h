@@ -68,7 +68,8 @@ struct Table {
     pwc_mesh mesh{};
     std::vector<int32_t> h_basis;   // [N][3]
     std::vector<double> h_beta, h_W;
-    FoldLayout fl;
+    FoldLayout fl;       // reconstruction layout of the FP64 path
+    FoldLayout flm;      // and of the split-FP32 path (same E, Qp)
     DiagLayout dl;
     int device = 0;
     int n_cu = 0;
@@ -103,7 +104,7 @@ struct Table {
 struct TableSetup {
     std::vector<int32_t> fold, reps;
 };
-bool plan_fold(int Q, int E, int lanes, int words, FoldLayout &fl);
+bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl);
 pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s);
 void free_table(Table &t);

@@ -5,22 +5,23 @@
 // Layout.  tau is symmetric under (m, m') -> (m', m) and (m, m') -> (-m, -m'),
 // so the table is stored folded: E orbit representatives per node (about a
 // quarter of nd^2).  In HBM the folded table is [E][Qp]: the Qp (Q padded to
-// a multiple of 32 with zero weight) node values of one entry are contiguous.
+// a multiple of 32, zero) node values of one entry are contiguous.  Each entry
+// carries W_q^(1/3) (the mesh weights are positive), so a node term is the
+// plain product of three entries.
 //
-// Schedule: node passes.  The node range is cut into P passes of c = 2G
-// nodes, small enough for the [E][c] slab to sit in LDS.  Pass p is one launch
-// of a persistent grid; every workgroup stages slab p once and then streams
-// every quadruple through it.  A decode kernel first turns each quadruple into
-// its three folded-entry indices (4 bytes when E <= 1024, else 8, kept in a
-// scratch array); each pass adds its c node terms to an FP64 partial sum kept
-// in the output array, and the last pass applies 1/(sqrt(pi) L).  Table
-// refills from L2 are thus paid once per workgroup and pass, and the
-// per-quadruple traffic is a plain HBM stream.
+// Schedule: node passes.  The node range is cut into P passes of c nodes,
+// small enough for the [E][c] slab to sit in LDS.  Pass p is one launch of a
+// persistent grid; every workgroup stages slab p once and then streams every
+// quadruple through it.  The quadruples are first decoded into their three
+// folded-entry indices (4 bytes when E <= 1024, else 8, kept in a scratch
+// array); each pass adds its c node terms to an FP64 partial sum kept in the
+// output array, and the last pass applies 1/(sqrt(pi) L).  Table refills
+// from L2 are thus paid once per workgroup and pass, and the per-quadruple
+// traffic is a plain HBM stream.
 //
 // Lanes.  G lanes share one quadruple and each lane owns W 16-byte words
-// (2W nodes) of every row, c = 2 G W: word s + G k of chunk k.  The lane's
-// weights stay in registers and each row read of a quadruple is W aligned
-// runs of G words.  LDS serves a 16-lane phase of a 128-bit read in one
+// (2W nodes) of every row, c = 2 G W: word s + G k of chunk k.  Each row
+// read of a quadruple is W aligned runs of G words.  LDS serves a 16-lane phase of a 128-bit read in one
 // sweep of its 64 banks (256 bytes) when the phase's addresses fall in
 // distinct banks, so the layouts differ in how often a phase clashes:
 //   G = 16: a phase is one run of 256 bytes, always conflict-free;
@@ -46,6 +47,13 @@
 // butterfly of DPP exchanges inside the 16-lane row halves the set at each
 // step, so that after log2(G) steps lane s holds the full sum of one
 // quadruple, which it writes.
+//
+// First pass.  All layouts with c = 16 read the same [E][16] slab, and a
+// quadruple's packed word depends on its stream position only, so the first
+// pass of such a table runs in the one-lane layout (G = 1, W = 8) and
+// decodes the stream itself, the basis and fold map sitting in LDS beside
+// the slab; the later passes use the table's layout, for whose lane groups
+// the decode orders the entries.  Other tables decode in k_decode first.
 #include <algorithm>
 #include <cmath>
 
@@ -60,10 +68,13 @@ constexpr int kThreads = 1024;   // one workgroup per CU when the slab is large
 // words per row (the loads of an iteration must fit in registers).
 template <int G>
 constexpr int rows_per_group() { return G == 1 ? 1 : G == 2 ? 2 : 4; }
+constexpr int log2i(int v) { return v <= 1 ? 0 : 1 + log2i(v / 2); }
 
 struct PassArgs {
     const int4 *quads;
     int64_t n;
+    int64_t n_pad;     // n rounded up to kStreamPad: the decoded stream's length
+    int ord_g;         // lanes per quadruple of the passes the decode orders entries for
     const int32_t *basis;
     int N;
     const int32_t *fold;
@@ -158,6 +169,7 @@ template <typename PK, int R>
 struct Stream {
     typename PK::T pk[R];
     double prev;
+    int4 q;   // the quadruple this lane decodes (first pass with inline decode)
 };
 
 // Butterfly step: lanes on the `up` side keep b and send a, the others keep
@@ -167,47 +179,48 @@ __device__ __forceinline__ double bfly(double a, double b, bool up) {
     return (up ? b : a) + dpp_take<CTRL>(up ? a : b);
 }
 
-// Reduce the R per-lane partial sums of a G-lane group.  On return lane s
-// holds the full sum of quadruple own_row<G>(s).
-template <int G>
+// Reduce the R per-lane partial sums of a G-lane group (R <= G, both powers
+// of two, groups aligned within 16-lane DPP rows).  The first log2 R steps
+// are butterfly exchanges that halve the set, the rest plain sums, with
+// partners at distance G/2, G/4, ... (row mirror 15 - s, half mirror 7 - s,
+// then s ^ 2 and s ^ 1).  On return lane s holds the full sum of quadruple
+// own_row(s) = (s >> (log2 G - log2 R)) mod R; lanes with zero low bits
+// write it.
+template <int G, int R>
 __device__ __forceinline__ int own_row(int s) {
-    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
-    return G == 1 ? 0 : G == 2 ? (s & 1) : ((s >> sh) & 3);
+    return (s >> (log2i(G) - log2i(R))) & (R - 1);
 }
-template <int G>
+template <int G, int R>
 __device__ __forceinline__ bool row_writer(int s) {
-    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
-    return G <= 2 ? true : (s & ((1 << sh) - 1)) == 0;
+    return (s & ((G / R) - 1)) == 0;
 }
-template <int G>
-__device__ __forceinline__ double group_reduce(const double *v, int s) {
-    if (G == 1) return v[0];
-    if (G == 2) return bfly<0xB1>(v[0], v[1], s & 1);   // partner s ^ 1
-    constexpr int sh = (G == 16) ? 2 : (G == 8) ? 1 : 0;
-    const bool up1 = (s >> (sh + 1)) & 1, up2 = (s >> sh) & 1;
-    double k0, k1, r;
-    if (G == 16) {          // row mirror: partner 15 - s; half mirror: 7 - s
-        k0 = bfly<0x140>(v[0], v[2], up1);
-        k1 = bfly<0x140>(v[1], v[3], up1);
-        r = bfly<0x141>(k0, k1, up2);
-        r += dpp_take<0x4E>(r);
-        r += dpp_take<0xB1>(r);
-    } else if (G == 8) {    // half mirror: partner 7 - s; then s ^ 2, s ^ 1
-        k0 = bfly<0x141>(v[0], v[2], up1);
-        k1 = bfly<0x141>(v[1], v[3], up1);
-        r = bfly<0x4E>(k0, k1, up2);
-        r += dpp_take<0xB1>(r);
-    } else {                // s ^ 2, then s ^ 1
-        k0 = bfly<0x4E>(v[0], v[2], up1);
-        k1 = bfly<0x4E>(v[1], v[3], up1);
-        r = bfly<0xB1>(k0, k1, up2);
+template <int CTRL>
+__device__ __forceinline__ void reduce_step(double *v, int m, int s, int bit) {
+    // m values in, m / 2 out when m > 1 (butterfly), else a plain sum
+    if (m == 1) {
+        v[0] += dpp_take<CTRL>(v[0]);
+        return;
     }
-    return r;
+    const bool up = (s >> bit) & 1;
+#pragma unroll
+    for (int i = 0; i < m / 2; ++i) v[i] = bfly<CTRL>(v[i], v[i + m / 2], up);
+}
+template <int G, int R>
+__device__ __forceinline__ double group_reduce(double *v, int s) {
+    static_assert(R <= G, "at most one quadruple per lane");
+    int m = R;
+    if (G >= 16) { reduce_step<0x140>(v, m, s, 3); m = m > 1 ? m / 2 : 1; }
+    if (G >= 8) { reduce_step<0x141>(v, m, s, 2); m = m > 1 ? m / 2 : 1; }
+    if (G >= 4) { reduce_step<0x4E>(v, m, s, 1); m = m > 1 ? m / 2 : 1; }
+    if (G >= 2) { reduce_step<0xB1>(v, m, s, 0); }
+    return v[0];
 }
 
 // Decode every quadruple into its packed folded entries, in the parity
 // order its stream position asks for (above); an out-of-range index writes
-// the flagged word and raises the error word.  Positions n .. n_pad - 1 (the
+// the flagged word and raises the error word.  Used when the basis and fold
+// map do not fit in LDS beside the first pass's slab (the first pass
+// decodes inline otherwise).  Positions n .. n_pad - 1 (the
 // stream padded to whole pass tiles) get row 0, so the node passes read the
 // stream without bounds checks.  A streaming kernel with many waves per CU.
 // Each quadruple needs 7 dependent random gathers (4 basis vectors, 3 fold
@@ -237,10 +250,39 @@ __device__ __forceinline__ void order_by_parity(int &a, int &b, int &c) {
     cx(a, b);
 }
 
+// Packed entries of quadruple v at stream position e; basis and fold map
+// from LDS copies or from global memory.
+template <typename PK>
+__device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const int32_t *basis,
+                                                     const int16_t *lfold, const int32_t *gfold,
+                                                     int4 v, int64_t e) {
+    const unsigned N = static_cast<unsigned>(a.N);
+    if (static_cast<unsigned>(v.x) >= N || static_cast<unsigned>(v.y) >= N ||
+        static_cast<unsigned>(v.z) >= N || static_cast<unsigned>(v.w) >= N) {
+        atomicOr(a.err, 1);
+        return PK::flagged();
+    }
+    const int K = a.K, nd = a.nd;
+    const int ni = basis[v.x], nj = basis[v.y], nk = basis[v.z], nl = basis[v.w];
+    const int ix = (bx(nk) - bx(ni) + K) * nd + (bx(nl) - bx(nj) + K);
+    const int iy = (by(nk) - by(ni) + K) * nd + (by(nl) - by(nj) + K);
+    const int iz = (bz(nk) - bz(ni) + K) * nd + (bz(nl) - bz(nj) + K);
+    int fx = lfold ? lfold[ix] : gfold[ix];
+    int fy = lfold ? lfold[iy] : gfold[iy];
+    int fz = lfold ? lfold[iz] : gfold[iz];
+    order_by_parity(fx, fy, fz);
+    if (descending_at(e, a.ord_g)) {
+        const int t = fx;
+        fx = fz;
+        fz = t;
+    }
+    return PK::pack(fx, fy, fz);
+}
+
 template <typename PK, bool LDS_MAPS>
-__global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n_pad, int G) {
-    extern __shared__ uint4 lds_raw[];
-    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw);
+__global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n_pad) {
+    extern __shared__ uint4 lds_dyn[];
+    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_dyn);
     int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
     const int nd2 = a.nd * a.nd;
     if (LDS_MAPS) {
@@ -249,8 +291,6 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n
         __syncthreads();
     }
     typename PK::T *out = static_cast<typename PK::T *>(a.scratch);
-    const unsigned N = static_cast<unsigned>(a.N);
-    const int K = a.K, nd = a.nd;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kDecodeThreads * kDecodeBatch;
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * kDecodeThreads * kDecodeBatch;
          base < n_pad; base += stride) {
@@ -264,44 +304,47 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n
         for (int b = 0; b < kDecodeBatch; ++b) {
             const int64_t e = base + b * kDecodeThreads + threadIdx.x;
             if (e >= n_pad) continue;
-            if (e >= a.n) {
-                out[e] = PK::pack(0, 0, 0);
-                continue;
-            }
-            const int4 v = q[b];
-            typename PK::T pk = PK::flagged();
-            if (static_cast<unsigned>(v.x) < N && static_cast<unsigned>(v.y) < N &&
-                static_cast<unsigned>(v.z) < N && static_cast<unsigned>(v.w) < N) {
-                const int ni = LDS_MAPS ? lbasis[v.x] : a.basis[v.x];
-                const int nj = LDS_MAPS ? lbasis[v.y] : a.basis[v.y];
-                const int nk = LDS_MAPS ? lbasis[v.z] : a.basis[v.z];
-                const int nl = LDS_MAPS ? lbasis[v.w] : a.basis[v.w];
-                const int ix = (bx(nk) - bx(ni) + K) * nd + (bx(nl) - bx(nj) + K);
-                const int iy = (by(nk) - by(ni) + K) * nd + (by(nl) - by(nj) + K);
-                const int iz = (bz(nk) - bz(ni) + K) * nd + (bz(nl) - bz(nj) + K);
-                int fx = LDS_MAPS ? lfold[ix] : a.fold[ix];
-                int fy = LDS_MAPS ? lfold[iy] : a.fold[iy];
-                int fz = LDS_MAPS ? lfold[iz] : a.fold[iz];
-                order_by_parity(fx, fy, fz);
-                if (descending_at(e, G)) {
-                    const int t = fx;
-                    fx = fz;
-                    fz = t;
-                }
-                pk = PK::pack(fx, fy, fz);
-            } else {
-                atomicOr(a.err, 1);
-            }
-            out[e] = pk;
+            out[e] = e < a.n ? decode_one<PK>(a, LDS_MAPS ? lbasis : a.basis, LDS_MAPS ? lfold : nullptr,
+                                              a.fold, q[b], e)
+                             : PK::pack(0, 0, 0);
         }
     }
+}
+
+// Broadcast, inside a group, the packed word decoded by the group's lane r
+// (lane r of each 4-lane quad, or of each lane pair when G = 2).
+__device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int ctrl_r) {
+    switch (ctrl_r) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0xA0, 0xf, 0xf, false);   // pairs: lane 0
+    default: return __builtin_amdgcn_mov_dpp(v, 0xF5, 0xf, 0xf, false);  // pairs: lane 1
+    }
+}
+// R = 1: nothing to share; R = 2: from lane r of each lane pair; R = 4: from
+// lane r of each 4-lane quad.
+template <int R>
+__device__ __forceinline__ uint32_t bcast_row(uint32_t v, int r) {
+    return R == 1 ? v : bcast_u32(v, R == 2 ? 4 + r : r);
+}
+template <int R>
+__device__ __forceinline__ uint2 bcast_row(uint2 v, int r) {
+    return make_uint2(bcast_row<R>(v.x, r), bcast_row<R>(v.y, r));
 }
 
 // One node pass.  LDS: the slab [E][G W] of 16-byte words (nodes q0 ..
 // q0 + c - 1 of every folded entry).  Lane s of group g reads, for each of
 // its R quadruples e = base + r NG + g, its W words of the three rows.
-template <typename A, int G, int W, typename PK, bool FIRST, bool LAST>
+// DECODE (first pass only): the basis and fold map follow the slab in LDS,
+// lane s of a group decodes quadruple s mod R itself, writes its packed word
+// to the scratch stream for the later passes, and the group shares the R
+// words by DPP broadcast.  Used with one lane per quadruple (G = 1, W = 8),
+// where nothing is decoded twice or shared.
+template <typename A, int G, int W, typename PK, bool FIRST, bool LAST, bool DECODE>
 __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
+    static_assert(!DECODE || FIRST, "only the first pass decodes");
     using V = typename A::V;
     using T = typename PK::T;
     // A static slab: its LDS address is known when instructions are
@@ -316,16 +359,25 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     static_assert(kStreamPad % TILE == 0, "the padded stream covers every tile");
     const int s = threadIdx.x % G, g = threadIdx.x / G;
     const int rot = ROT ? (g & (W - 1)) : 0;
-    const int own = own_row<G>(s);                      // quadruple this lane writes
-    const bool writer = row_writer<G>(s);
+    const int own = own_row<G, R>(s);                   // quadruple this lane writes
+    const bool writer = row_writer<G, R>(s);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * TILE;
     int64_t base = static_cast<int64_t>(blockIdx.x) * TILE;
     const T *sc = static_cast<const T *>(a.scratch) + g;
+    const int rdec = s % R;                             // quadruple this lane decodes
+    const int words = a.E * G * W;
+    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw + words);
+    int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
 
     auto load = [&](Stream<PK, R> &st, int64_t b) {
-        const T *p = sc + b;
+        if (DECODE) {
+            const int64_t e = b + rdec * NG + g;
+            if (e < a.n) st.q = a.quads[e];
+        } else {
+            const T *p = sc + b;
 #pragma unroll
-        for (int r = 0; r < R; ++r) st.pk[r] = p[r * NG];
+            for (int r = 0; r < R; ++r) st.pk[r] = p[r * NG];
+        }
         const int64_t e = b + own * NG + g;
         if (!FIRST && writer && e < a.n) st.prev = a.out[e];
     };
@@ -334,10 +386,15 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     {
         V *dst = reinterpret_cast<V *>(lds_raw);
         const V *src = static_cast<const V *>(a.tab) + a.q0 / 2;
-        const int row = a.Qp / 2, words = a.E * G * W;
+        const int row = a.Qp / 2;
         for (int i = threadIdx.x; i < words; i += kThreads) {
             const int e = i / (G * W), j = i % (G * W);
             dst[i] = src[static_cast<size_t>(e) * row + j];
+        }
+        if (DECODE) {
+            for (int i = threadIdx.x; i < a.N; i += kThreads) lbasis[i] = a.basis[i];
+            for (int i = threadIdx.x; i < a.nd * a.nd; i += kThreads)
+                lfold[i] = static_cast<int16_t>(a.fold[i]);
         }
     }
     const char *lb = reinterpret_cast<const char *>(lds_raw);
@@ -345,11 +402,23 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     __syncthreads();
 
     auto body = [&](const Stream<PK, R> &st, int64_t b) {
+        T pk[R];
+        if (DECODE) {
+            const int64_t e = b + rdec * NG + g;
+            const T mine = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, st.q, e)
+                                   : PK::pack(0, 0, 0);   // padding up to the tile end
+            if (!LAST && s < R) const_cast<T *>(sc)[b + rdec * NG] = mine;
+#pragma unroll
+            for (int r = 0; r < R; ++r) pk[r] = bcast_row<R>(mine, r);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) pk[r] = st.pk[r];
+        }
         V x[R][W], y[R][W], z[R][W];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int f0, f1, f2;
-            PK::unpack(st.pk[r], f0, f1, f2);
+            PK::unpack(pk[r], f0, f1, f2);
             const uint32_t a0 = f0 * ROWB + lane_b, a1 = f1 * ROWB + lane_b, a2 = f2 * ROWB + lane_b;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
@@ -369,14 +438,14 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
             for (int k = 0; k < W; ++k) A::add2(acc, x[r][k], y[r][k], z[r][k]);
             v[r] = A::value(acc);
         }
-        const double sum = group_reduce<G>(v, s);
+        const double sum = group_reduce<G, R>(v, s);
         const int64_t e = b + own * NG + g;
         if (writer && e < a.n) {
             double prev;
             if (FIRST) {   // the first pass marks a bad quadruple; later passes carry the NaN
                 uint32_t bad = 0;
 #pragma unroll
-                for (int r = 0; r < R; ++r) bad |= PK::flag(st.pk[r]) << r;
+                for (int r = 0; r < R; ++r) bad |= PK::flag(pk[r]) << r;
                 prev = ((bad >> own) & 1) ? NAN : 0.0;
             } else {
                 prev = st.prev;
@@ -386,13 +455,16 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     };
 
     // Two stream buffers in turn: the loads for the next iteration are in
-    // flight while this one computes.
-    while (base < a.n) {
-        if (base + stride < a.n) load(s1, base + stride);
+    // flight while this one computes.  A decoding pass covers the whole
+    // padded stream, so the later passes (larger tiles) find every packed
+    // word they read written.
+    const int64_t end = DECODE ? a.n_pad : a.n;
+    while (base < end) {
+        if (base + stride < end) load(s1, base + stride);
         body(s0, base);
         base += stride;
-        if (base >= a.n) break;
-        if (base + stride < a.n) load(s0, base + stride);
+        if (base >= end) break;
+        if (base + stride < end) load(s0, base + stride);
         body(s1, base);
         base += stride;
     }
@@ -401,28 +473,37 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
 using PassKernel = void (*)(PassArgs);
 
 template <typename A, int G, int W, typename PK>
-PassKernel pass_kernel(int p, int P) {
-    if (p == 0) return P == 1 ? k_rec_pass<A, G, W, PK, true, true> : k_rec_pass<A, G, W, PK, true, false>;
-    return p == P - 1 ? k_rec_pass<A, G, W, PK, false, true> : k_rec_pass<A, G, W, PK, false, false>;
+PassKernel pass_kernel(int p, int P, bool decode) {
+    if (p == 0) {
+        if (decode)   // one-lane first pass with the decode inline (c = 16 only)
+            return P == 1 ? k_rec_pass<A, 1, 8, PK, true, true, true> : k_rec_pass<A, 1, 8, PK, true, false, true>;
+        return P == 1 ? k_rec_pass<A, G, W, PK, true, true, false> : k_rec_pass<A, G, W, PK, true, false, false>;
+    }
+    return p == P - 1 ? k_rec_pass<A, G, W, PK, false, true, false> : k_rec_pass<A, G, W, PK, false, false, false>;
 }
 
 // stage_ev (optional): events recorded before the decode and after every
 // launch of the first slab, for per-stage timing.
 template <typename A, int G, int W, typename PK>
-hipError_t run_passes(const PassArgs &a0, const Table &t, hipStream_t s, hipEvent_t *stage_ev) {
-    const int P = t.fl.nchunk;
-    const size_t lds = static_cast<size_t>(t.fl.E) * G * W * 16;   // slab bytes used
+hipError_t run_passes(const PassArgs &a0, const Table &t, const FoldLayout &fl, hipStream_t s,
+                      hipEvent_t *stage_ev) {
+    const int P = fl.nchunk;
+    const size_t lds = static_cast<size_t>(fl.E) * G * W * 16;   // slab bytes used
     if (lds > static_cast<size_t>(kLdsMax)) return hipErrorInvalidValue;
     hipError_t err0 = hipSuccess;
+    constexpr int64_t tile_d = kThreads;   // the one-lane decoding pass
     constexpr int64_t tile = static_cast<int64_t>(kThreads / G) * rows_per_group<G>();
-    // LDS copy of the basis (int32) and the fold map (int16) for the decode.
-    const size_t maps_bytes = (sizeof(int32_t) * static_cast<size_t>(t.N) +
-                               sizeof(int16_t) * static_cast<size_t>(t.nd) * t.nd + 15) / 16 * 16;
-    const bool maps_fit = maps_bytes <= static_cast<size_t>(kLdsMax);
-    if (maps_fit) {
+    // LDS copy of the basis (int32) and the fold map (int16) for the decode:
+    // inside the first pass when they fit beside its slab, else in k_decode.
+    const size_t maps_bytes = sizeof(int32_t) * static_cast<size_t>(t.N) +
+                              sizeof(int16_t) * static_cast<size_t>(t.nd) * t.nd;
+    const bool inline_decode = G * W == 8 && lds + maps_bytes <= static_cast<size_t>(kLdsMax);
+    const size_t dmaps = (maps_bytes + 15) / 16 * 16;
+    const bool maps_fit = dmaps <= static_cast<size_t>(kLdsMax);
+    if (!inline_decode && maps_fit) {
         const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_decode<PK, true>),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   static_cast<int>(maps_bytes));
+                                                   static_cast<int>(dmaps));
         if (err != hipSuccess) return err;
     }
     const int per_cu = 1;   // the static slab takes the CU's LDS
@@ -432,27 +513,31 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, hipStream_t s, hipEven
         a.n = std::min<int64_t>(kRecSlab, a0.n - off);
         a.quads = a0.quads + off;
         a.out = a0.out + off;
+        a.n_pad = (a.n + kStreamPad - 1) / kStreamPad * kStreamPad;
         hipEvent_t *ev = (off == 0) ? stage_ev : nullptr;
         if (ev && (err0 = hipEventRecord(ev[0], s)) != hipSuccess) return err0;
-        const int64_t n_pad = (a.n + kStreamPad - 1) / kStreamPad * kStreamPad;
-        const int64_t dblocks = (n_pad + kDecodeThreads * kDecodeBatch - 1) / (kDecodeThreads * kDecodeBatch);
         hipError_t err;
-        if (maps_fit) {
-            const int dper = std::max(1, std::min(8, static_cast<int>(kLdsMax / std::max<size_t>(maps_bytes, 1))));
-            const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * dper));
-            hipLaunchKernelGGL((k_decode<PK, true>), dim3(dgrid), dim3(kDecodeThreads), maps_bytes, s, a, n_pad, G);
-        } else {
-            const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * 16));
-            hipLaunchKernelGGL((k_decode<PK, false>), dim3(dgrid), dim3(kDecodeThreads), 0, s, a, n_pad, G);
+        if (!inline_decode) {
+            const int64_t n_pad = a.n_pad;
+            const int64_t dblocks = (n_pad + kDecodeThreads * kDecodeBatch - 1) / (kDecodeThreads * kDecodeBatch);
+            if (maps_fit) {
+                const int dper = std::max(1, std::min(8, static_cast<int>(kLdsMax / dmaps)));
+                const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * dper));
+                hipLaunchKernelGGL((k_decode<PK, true>), dim3(dgrid), dim3(kDecodeThreads), dmaps, s, a, n_pad);
+            } else {
+                const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>(dblocks, int64_t(t.n_cu) * 16));
+                hipLaunchKernelGGL((k_decode<PK, false>), dim3(dgrid), dim3(kDecodeThreads), 0, s, a, n_pad);
+            }
+            err = hipGetLastError();
+            if (err != hipSuccess) return err;
         }
-        err = hipGetLastError();
-        if (err != hipSuccess) return err;
         if (ev && (err = hipEventRecord(ev[1], s)) != hipSuccess) return err;
-        const int64_t tiles = (a.n + tile - 1) / tile;
-        const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, int64_t(t.n_cu) * per_cu));
         for (int p = 0; p < P; ++p) {
             a.q0 = p * 2 * G * W;
-            const PassKernel kern = pass_kernel<A, G, W, PK>(p, P);
+            const bool dec = p == 0 && inline_decode;
+            const int64_t tl = dec ? tile_d : tile, cover = dec ? a.n_pad : a.n;
+            const unsigned grid = static_cast<unsigned>(std::min<int64_t>((cover + tl - 1) / tl, int64_t(t.n_cu) * per_cu));
+            const PassKernel kern = pass_kernel<A, G, W, PK>(p, P, inline_decode);
             hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, a);
             err = hipGetLastError();
             if (err != hipSuccess) return err;
@@ -463,21 +548,23 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, hipStream_t s, hipEven
 }
 
 template <typename A, int G, int W>
-hipError_t run_pack(const PassArgs &a, const Table &t, hipStream_t s, hipEvent_t *ev) {
-    return t.fl.E <= Pk32::kMaxE ? run_passes<A, G, W, Pk32>(a, t, s, ev)
-                                 : run_passes<A, G, W, Pk64>(a, t, s, ev);
+hipError_t run_pack(const PassArgs &a, const Table &t, const FoldLayout &fl, hipStream_t s,
+                    hipEvent_t *ev) {
+    return fl.E <= Pk32::kMaxE ? run_passes<A, G, W, Pk32>(a, t, fl, s, ev)
+                               : run_passes<A, G, W, Pk64>(a, t, fl, s, ev);
 }
 
 template <typename A>
-hipError_t run_layout(const PassArgs &a, const Table &t, hipStream_t s, hipEvent_t *ev) {
-    const int G = t.fl.G, W = t.fl.W;
-    if (G == 16 && W == 1) return run_pack<A, 16, 1>(a, t, s, ev);
-    if (G == 8 && W == 2) return run_pack<A, 8, 2>(a, t, s, ev);
-    if (G == 8 && W == 1) return run_pack<A, 8, 1>(a, t, s, ev);
-    if (G == 4 && W == 2) return run_pack<A, 4, 2>(a, t, s, ev);
-    if (G == 2 && W == 4) return run_pack<A, 2, 4>(a, t, s, ev);
-    if (G == 1 && W == 8) return run_pack<A, 1, 8>(a, t, s, ev);
-    if (G == 4 && W == 1) return run_pack<A, 4, 1>(a, t, s, ev);
+hipError_t run_layout(const PassArgs &a, const Table &t, const FoldLayout &fl, hipStream_t s,
+                      hipEvent_t *ev) {
+    const int G = fl.G, W = fl.W;
+    if (G == 16 && W == 1) return run_pack<A, 16, 1>(a, t, fl, s, ev);
+    if (G == 8 && W == 2) return run_pack<A, 8, 2>(a, t, fl, s, ev);
+    if (G == 8 && W == 1) return run_pack<A, 8, 1>(a, t, fl, s, ev);
+    if (G == 4 && W == 2) return run_pack<A, 4, 2>(a, t, fl, s, ev);
+    if (G == 2 && W == 4) return run_pack<A, 2, 4>(a, t, fl, s, ev);
+    if (G == 1 && W == 8) return run_pack<A, 1, 8>(a, t, fl, s, ev);
+    if (G == 4 && W == 1) return run_pack<A, 4, 1>(a, t, fl, s, ev);
     return hipErrorInvalidValue;
 }
 
@@ -499,6 +586,7 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.E = t.fl.E;
     a.Qp = t.fl.Qp;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
+    a.ord_g = (p == PWC_MIXED ? t.flm : t.fl).G;
     a.out = d_out;
     a.err = t.d_err;
     const int64_t slab = std::min<int64_t>(n, kRecSlab);
@@ -508,10 +596,10 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     if (err != hipSuccess) return err;
     if (p == PWC_MIXED) {
         a.tab = t.d_tauHL;
-        err = run_layout<FF>(a, t, s, stage_ev);
+        err = run_layout<FF>(a, t, t.flm, s, stage_ev);
     } else {
         a.tab = t.d_tauF;
-        err = run_layout<F64>(a, t, s, stage_ev);
+        err = run_layout<F64>(a, t, t.fl, s, stage_ev);
     }
     const hipError_t e2 = hipFreeAsync(a.scratch, s);
     if (err == hipSuccess) err = e2;

@@ -82,8 +82,8 @@ def test_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.pwc_reconstruct(None, None, 0, None, 0, None) == 1
     lib.pwc_sync.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert lib.pwc_sync(None, None) == 1
-    lib.pwc_table_layout.argtypes = [ctypes.c_void_p] * 6
-    assert lib.pwc_table_layout(None, None, None, None, None, None) == 1
+    lib.pwc_table_layout.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5
+    assert lib.pwc_table_layout(None, 0, None, None, None, None, None) == 1
     lib.pwc_table_set_layout.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     assert lib.pwc_table_set_layout(None, 8, 1) == 1
     lib.pwc_table_destroy.argtypes = [ctypes.c_void_p]

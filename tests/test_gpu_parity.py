@@ -134,32 +134,39 @@ def test_reconstruct_profile_matches_and_times_every_launch(pw, tables):
 
 ALL_LAYOUTS = [(16, 1), (8, 2), (8, 1), (4, 2), (2, 4), (1, 8), (4, 1)]
 C16 = [(8, 1), (4, 2), (2, 4), (1, 8)]             # 16 nodes per pass
-# (n2max, Q, default (lanes, words), bytes per decoded quadruple, layouts whose slab fits)
+# (n2max, Q, default (lanes, words) for FP64 and for split-FP32, bytes per
+#  decoded quadruple, layouts whose slab fits)
 LAYOUTS = [
-    (40, 64, (16, 1), 4, ALL_LAYOUTS),
-    (169, 96, (8, 1), 4, C16 + [(4, 1)]),
-    (256, 32, (8, 1), 8, C16 + [(4, 1)]),
-    (400, 128, (4, 1), 8, [(4, 1)]),
+    (40, 64, (8, 2), (2, 4), 4, ALL_LAYOUTS),
+    (169, 96, (1, 8), (2, 4), 4, C16 + [(4, 1)]),
+    (256, 32, (1, 8), (2, 4), 8, C16 + [(4, 1)]),
+    (400, 128, (4, 1), (4, 1), 8, [(4, 1)]),
 ]
 
 
-@pytest.mark.parametrize("n2max,Q,default,eb,fits", LAYOUTS)
-def test_reconstruct_every_lane_layout(pw, n2max, Q, default, eb, fits):
+@pytest.mark.parametrize("n2max,Q,d64,dmx,eb,fits", LAYOUTS)
+def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
     """Every lane layout and both packed-entry widths against the oracle, on
     a ragged uniform stream, and the layouts against each other."""
     import torch
     o = P.setup(n2max, Q)
+
+    def lanes_words(t, prec):
+        lay = t.layout(prec)
+        return lay["lanes"], lay["words"]
     with pw.Table(1.0, n2max, Q) as t:
-        lay = t.layout()
-        assert ((lay["lanes"], lay["words"]), lay["entry_bytes"]) == (default, eb)
+        assert (lanes_words(t, pw.FP64), lanes_words(t, pw.MIXED)) == (d64, dmx)
+        assert t.layout(pw.FP64)["entry_bytes"] == t.layout(pw.MIXED)["entry_bytes"] == eb
         quads = workloads.uniform_quads(len(o["basis"]), 50001, seed=n2max)
         dq = _dev(quads, torch.int32)
         base = {}
         for G, W in fits:
             t.set_layout(G, W)
-            lay = t.layout()
-            assert (lay["lanes"], lay["words"]) == (G, W)
-            assert lay["nodes_per_pass"] == 2 * G * W and lay["passes"] == -(-Q // (2 * G * W))
+            for prec in (pw.FP64, pw.MIXED):
+                lay = t.layout(prec)
+                assert (lay["lanes"], lay["words"]) == (G, W)
+                assert lay["nodes_per_pass"] == 2 * G * W
+                assert lay["passes"] == -(-Q // (2 * G * W))
             _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} layout={G}x{W}")
             for prec in (pw.FP64, pw.MIXED):
                 out = t.reconstruct(dq, precision=prec)
@@ -177,7 +184,7 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, default, eb, fits):
             t.set_layout(16, 2)
         assert ei.value.status == pw.ERR_ARG
         t.set_layout(0, 0)
-        assert (t.layout()["lanes"], t.layout()["words"]) == default
+        assert (lanes_words(t, pw.FP64), lanes_words(t, pw.MIXED)) == (d64, dmx)
 
 
 def test_reconstruct_empty(pw, tables):
