@@ -170,6 +170,18 @@ PWC_API pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int
                           size_t *device_bytes);
 
 /*
+ * Small quadruple lists skip the node passes: pwc_reconstruct evaluates a
+ * list of n <= direct_max quadruples with one lane per quadruple reading the
+ * tables from global memory (Eq. 14 over all nodes in one launch); longer
+ * lists run the node-pass kernels.  The two agree to rounding.  The default
+ * is 524288 (about where the two take equal time on MI355X); 0 sends every
+ * list through the node passes.  n must lie in
+ * [0, 1048576] (PWC_ERR_ARG otherwise).  Must not overlap a reconstruction
+ * that uses the same table.
+ */
+PWC_API pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n);
+
+/*
  * Reconstruction layout of a table for precision p (Eq. 14 evaluated in node
  * passes; each precision has its own default): lanes = G lanes of a
  * wavefront share one quadruple; words = W two-node
@@ -299,6 +311,12 @@ typedef struct {
     int64_t n;
     const double *d_f;    /* energies: occupations [n] or NULL */
     double *d_out;        /* reconstruct: [n]; energies: [2] = {E_H, E_x} */
+    void *ready_event;    /* hipEvent_t or NULL: recorded by the caller after the
+                             last work that writes d_idx / d_f or touches d_out;
+                             the server's kernels for this request wait for it on
+                             the device.  It must stay valid until the result is
+                             collected.  With NULL the buffers must already be
+                             idle when the request is submitted. */
 } pwc_request;
 
 typedef struct {
@@ -317,6 +335,8 @@ typedef struct {
     double p50_ms, p99_ms, max_ms;    /* latency over completed requests */
     double wall_s;                    /* first submit -> last completion */
     double integrals_per_s, pairs_per_s;
+    uint64_t launches;                /* kernel groups enqueued (one per slot use) */
+    uint64_t batched;                 /* requests that rode in another's direct launch */
 } pwc_server_stats;
 
 /* Create a server for the current device.  hbm_budget_bytes > 0 bounds the

@@ -69,6 +69,7 @@ def lib():
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
             "pwc_table_layout": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 5),
             "pwc_table_set_layout": (i32, [vp, i32, i32]),
+            "pwc_table_set_direct_max": (i32, [vp, i64]),
             "pwc_basis": (i32, [vp, vp]),
             "pwc_mesh_nodes": (i32, [vp, vp, vp]),
             "pwc_table_copy": (i32, [vp, vp, vp]),
@@ -181,6 +182,10 @@ class Table:
         _check(lib().pwc_table_set_layout(self.handle, int(lanes), int(words)),
                "pwc_table_set_layout")
 
+    def set_direct_max(self, n):
+        """Lists of at most n quadruples skip the node passes (0: never)."""
+        _check(lib().pwc_table_set_direct_max(self.handle, int(n)), "pwc_table_set_direct_max")
+
     def basis(self):
         out = np.empty((self.N, 3), dtype=np.int32)
         _check(lib().pwc_basis(self.handle, out.ctypes.data_as(ctypes.c_void_p)), "pwc_basis")
@@ -268,7 +273,8 @@ class Request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("L", ctypes.c_double), ("n2max", ctypes.c_int),
                 ("n_nodes", ctypes.c_int), ("has_mesh", ctypes.c_int), ("mesh", Mesh),
                 ("prec", ctypes.c_int), ("algo", ctypes.c_int), ("d_idx", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("d_f", ctypes.c_void_p), ("d_out", ctypes.c_void_p)]
+                ("n", ctypes.c_int64), ("d_f", ctypes.c_void_p), ("d_out", ctypes.c_void_p),
+                ("ready_event", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -284,7 +290,8 @@ class ServerStats(ctypes.Structure):
                 ("resident_bytes", ctypes.c_size_t), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("integrals_per_s", ctypes.c_double),
-                ("pairs_per_s", ctypes.c_double)]
+                ("pairs_per_s", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("batched", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -320,6 +327,12 @@ class Server:
         self._keep = {}
 
     def _submit(self, req, keep):
+        # The server's streams wait for the work queued so far on the current
+        # stream (inputs being written, outputs being cleared).
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        req.ready_event = ev.cuda_event
+        keep = keep + (ev,)
         t = ctypes.c_uint64()
         _check(_server_lib().pwc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
                "pwc_server_submit")

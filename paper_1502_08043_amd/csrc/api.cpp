@@ -167,6 +167,7 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
         t.n_cu <= 0)
         t.n_cu = 256;
     t.flm.E = t.fl.E;
+    t.direct_max = kDirectDefault;
     if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, t.flm) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
@@ -372,8 +373,20 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
+    if (n <= t->t.direct_max) {   // small list: one lane per quadruple, no node passes
+        pwc::DirectBatch b{};
+        b.job[0] = pwc::direct_job(t->t, d_quads, n, d_out, p, nullptr);
+        b.njobs = 1;
+        return from_hip(pwc::launch_direct(b, static_cast<hipStream_t>(stream)));
+    }
     return from_hip(pwc::launch_reconstruct(t->t, d_quads, n, d_out, p,
                                             static_cast<hipStream_t>(stream)));
+}
+
+pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n) {
+    if (!t || n < 0 || n > pwc::kDirectMaxN) return PWC_ERR_ARG;
+    t->t.direct_max = n;
+    return PWC_OK;
 }
 
 pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,

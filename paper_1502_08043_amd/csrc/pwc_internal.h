@@ -92,6 +92,7 @@ struct Table {
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
     double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]
     float2 *d_WdiagHL = nullptr;
+    int64_t direct_max = 0;         // pwc_reconstruct takes the direct kernel for n <= this
     int kt_n = 0;                   // exchange kernel table size C(K+3, 3), 0 if not kept
     double *d_ktab64 = nullptr;     // [kt_n] K(a<=b<=c), FP64 node sums
     double *d_ktabMX = nullptr;     // [kt_n] same, split-FP32 node sums
@@ -119,6 +120,30 @@ int packed_entry_bytes(int E);
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               double *d_out, pwc_precision p, hipStream_t s,
                               hipEvent_t *stage_ev = nullptr);
+// direct_kernels.hip: small quadruple lists, up to kDirectMaxJobs requests
+// (any tables and precisions) per launch, jobs passed by value.
+struct DirectJob {
+    const int32_t *quads;     // [n][4]
+    double *out;              // [n]
+    int64_t n;
+    const void *tab;          // folded W^(1/3) tau [E][Qp], double or float2
+    const int32_t *basis;
+    const int32_t *fold;
+    int *err;                 // error word of this job
+    double pref;
+    int N, K, nd, Qp, Q, mixed;
+    uint32_t block0;          // first block of the job (set by launch_direct)
+};
+constexpr int kDirectMaxJobs = 24;
+constexpr int64_t kDirectDefault = int64_t(1) << 19;  // default pwc_reconstruct threshold
+constexpr int64_t kDirectMaxN = int64_t(1) << 20;   // quadruples per job
+struct DirectBatch {
+    DirectJob job[kDirectMaxJobs];
+    int njobs;
+};
+DirectJob direct_job(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
+                     pwc_precision p, int *d_err);
+hipError_t launch_direct(DirectBatch b, hipStream_t s);
 // pairsum_kernels.hip
 hipError_t launch_ktab_build(Table &t, hipStream_t s);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,

@@ -2,16 +2,21 @@
 // over many boxes, cutoffs and meshes on one GPU (see include/pwcoul.h).
 //
 // One scheduler thread owns every HIP call.  Each iteration it
-//   1. reaps slots whose completion event has fired (result, latency, table
-//      reference released, scratch budget returned),
+//   1. reaps slots whose completion event has fired (results, latencies,
+//      table references released, scratch budget returned),
 //   2. admits queued requests in arrival order while a slot is free and the
 //      HBM budget allows: the table is taken from the cache or planned,
 //      priced (exact device bytes), evicted-for and built, then the request's
 //      kernels are enqueued on the slot's stream followed by the copies of
-//      the energies and of the table's error word into pinned host memory
-//      and an event.
-// A request that cannot be admitted for memory blocks the ones behind it
-// (no overtaking), so arrival order is kept and nothing starves.
+//      the energies and of the error words into pinned host memory and an
+//      event.
+// A small reconstruction at the head of the queue (at most the table's
+// direct-kernel size) takes along the later queued small reconstructions
+// whose tables are resident, up to kDirectMaxJobs: one launch of the direct
+// kernel serves them all, each job with its own table, precision, buffers
+// and error word.  Otherwise a request that cannot be admitted for memory
+// blocks the ones behind it, so the head is always served first and nothing
+// starves.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -58,18 +63,25 @@ struct Pending {
     Clock::time_point t_submit;
 };
 
+struct Member {
+    uint64_t ticket = 0;
+    pwc_request r{};
+    Cached *tab = nullptr;
+    int built = 0;
+    Clock::time_point t_submit;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     double *h_e = nullptr;     // pinned [2]
-    int *h_err = nullptr;      // pinned [1]
+    int *h_err = nullptr;      // pinned [kDirectMaxJobs]: error word per member
+    int *d_err = nullptr;      // device [kDirectMaxJobs]: the direct jobs' error words
     bool busy = false;
-    uint64_t ticket = 0;
-    pwc_request r{};
-    Cached *tab = nullptr;
+    bool direct = false;       // members share one direct-kernel launch
+    std::vector<Member> members;
     size_t scratch = 0;
-    int built = 0;
-    Clock::time_point t_submit, t_launch;
+    Clock::time_point t_launch;
 };
 
 pwc_status from_hip(hipError_t e) {
@@ -106,6 +118,7 @@ struct pwc_server {
 
     // statistics (guarded by mu)
     uint64_t submitted = 0, completed = 0, failed = 0, builds = 0, evictions = 0;
+    uint64_t launches = 0, batched = 0;
     std::vector<double> latencies;
     double integrals = 0.0, pairs = 0.0;
     bool have_first = false;
@@ -123,6 +136,7 @@ struct pwc_server {
 };
 
 size_t pwc_server::scratch_bytes(const pwc_request &r) const {
+    if (r.kind == PWC_REQ_RECONSTRUCT && r.n <= pwc::kDirectDefault) return 0;   // direct kernel
     if (r.kind == PWC_REQ_RECONSTRUCT)   // decoded quadruples: at most 8 bytes each
         return sizeof(uint2) * static_cast<size_t>(std::min<int64_t>(r.n, pwc::kRecSlab)) + (1 << 16);
     return 1 << 20;   // pair-sum partials
@@ -174,35 +188,42 @@ bool pwc_server::reap() {
         if (q == hipErrorNotReady) continue;
         any = true;
         const auto now = Clock::now();
-        pwc_result res{};
-        res.status = from_hip(q);
-        if (res.status == PWC_OK && *s.h_err) {
-            res.status = PWC_ERR_RANGE;
-            const int zero = 0;
-            (void)hipMemcpyAsync(s.tab->t->t.d_err, &zero, sizeof(int), hipMemcpyHostToDevice, s.stream);
-            (void)hipStreamSynchronize(s.stream);
+        for (size_t i = 0; i < s.members.size(); ++i) {
+            Member &m = s.members[i];
+            pwc_result res{};
+            res.status = from_hip(q);
+            if (res.status == PWC_OK && s.h_err[i]) {
+                res.status = PWC_ERR_RANGE;
+                if (!s.direct) {   // the node-pass kernels raise the table's own word
+                    const int zero = 0;
+                    (void)hipMemcpyAsync(m.tab->t->t.d_err, &zero, sizeof(int), hipMemcpyHostToDevice, s.stream);
+                    (void)hipStreamSynchronize(s.stream);
+                }
+            }
+            if (m.r.kind == PWC_REQ_ENERGIES) {
+                res.e_h = s.h_e[0];
+                res.e_x = s.h_e[1];
+            }
+            res.queue_ms = ms_between(m.t_submit, s.t_launch);
+            res.latency_ms = ms_between(m.t_submit, now);
+            res.table_built = m.built;
+            m.tab->refs -= 1;
+            std::lock_guard<std::mutex> lk(mu);
+            finished[m.ticket] = res;
+            if (res.status == PWC_OK) {
+                ++completed;
+                latencies.push_back(res.latency_ms);
+                if (m.r.kind == PWC_REQ_RECONSTRUCT) integrals += static_cast<double>(m.r.n);
+                else pairs += static_cast<double>(m.r.n) * static_cast<double>(m.r.n);
+            } else {
+                ++failed;
+            }
+            t_last = now;
         }
-        if (s.r.kind == PWC_REQ_ENERGIES) {
-            res.e_h = s.h_e[0];
-            res.e_x = s.h_e[1];
-        }
-        res.queue_ms = ms_between(s.t_submit, s.t_launch);
-        res.latency_ms = ms_between(s.t_submit, now);
-        res.table_built = s.built;
-        s.tab->refs -= 1;
         used -= s.scratch;
         s.busy = false;
+        s.members.clear();
         std::lock_guard<std::mutex> lk(mu);
-        finished[s.ticket] = res;
-        if (res.status == PWC_OK) {
-            ++completed;
-            latencies.push_back(res.latency_ms);
-            if (s.r.kind == PWC_REQ_RECONSTRUCT) integrals += static_cast<double>(s.r.n);
-            else pairs += static_cast<double>(s.r.n) * static_cast<double>(s.r.n);
-        } else {
-            ++failed;
-        }
-        t_last = now;
         cv_done.notify_all();
     }
     return any;
@@ -288,34 +309,89 @@ bool pwc_server::admit() {
         used += scratch;
         Slot &s = *slot;
         s.busy = true;
-        s.ticket = p.ticket;
-        s.r = p.r;
-        s.tab = &c;
         s.scratch = scratch;
-        s.built = built;
-        s.t_submit = p.t_submit;
         s.t_launch = Clock::now();
+        s.members.clear();
+        Member head;
+        head.ticket = p.ticket;
+        head.r = p.r;
+        head.tab = &c;
+        head.built = built;
+        head.t_submit = p.t_submit;
+        s.members.push_back(head);
         const pwc::Table &t = c.t->t;
-        hipError_t e;
-        if (p.r.kind == PWC_REQ_RECONSTRUCT) {
-            e = pwc::launch_reconstruct(t, p.r.d_idx, p.r.n, p.r.d_out,
-                                        static_cast<pwc_precision>(p.r.prec), s.stream);
-        } else {
-            e = pwc::launch_energies(t, p.r.d_idx, p.r.d_f, p.r.n,
-                                     static_cast<pwc_precision>(p.r.prec),
-                                     static_cast<pwc_pair_algo>(p.r.algo), p.r.d_out, s.stream);
+        s.direct = p.r.kind == PWC_REQ_RECONSTRUCT && p.r.n <= t.direct_max;
+        hipError_t e = hipSuccess;
+        // The caller's pending work on the request's buffers comes first.
+        auto wait_ready = [&](const pwc_request &r) {
+            if (e == hipSuccess && r.ready_event)
+                e = hipStreamWaitEvent(s.stream, static_cast<hipEvent_t>(r.ready_event), 0);
+        };
+        if (s.direct) {
+            // Later queued small reconstructions on resident tables join the launch.
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto q = pending.begin(); q != pending.end() &&
+                                               static_cast<int>(s.members.size()) < pwc::kDirectMaxJobs;) {
+                    if (q->r.kind != PWC_REQ_RECONSTRUCT) { ++q; continue; }
+                    auto ct = cache.find(key_of(q->r, q->mesh));
+                    if (ct == cache.end() || q->r.n > ct->second.t->t.direct_max) { ++q; continue; }
+                    Member m;
+                    m.ticket = q->ticket;
+                    m.r = q->r;
+                    m.tab = &ct->second;
+                    m.t_submit = q->t_submit;
+                    ct->second.refs += 1;
+                    ct->second.last_use = ++clock;
+                    s.members.push_back(m);
+                    q = pending.erase(q);
+                }
+            }
+            pwc::DirectBatch b{};
+            b.njobs = static_cast<int>(s.members.size());
+            for (int i = 0; i < b.njobs; ++i) {
+                const Member &m = s.members[i];
+                b.job[i] = pwc::direct_job(m.tab->t->t, m.r.d_idx, m.r.n, m.r.d_out,
+                                           static_cast<pwc_precision>(m.r.prec), s.d_err + i);
+                wait_ready(m.r);
+            }
+            if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int) * b.njobs, s.stream);
+            if (e == hipSuccess) e = pwc::launch_direct(b, s.stream);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(s.h_e, p.r.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
+                e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int) * b.njobs, hipMemcpyDeviceToHost, s.stream);
+        } else {
+            wait_ready(p.r);
+            if (e == hipSuccess && p.r.kind == PWC_REQ_RECONSTRUCT) {
+                e = pwc::launch_reconstruct(t, p.r.d_idx, p.r.n, p.r.d_out,
+                                            static_cast<pwc_precision>(p.r.prec), s.stream);
+            } else if (e == hipSuccess) {
+                e = pwc::launch_energies(t, p.r.d_idx, p.r.d_f, p.r.n,
+                                         static_cast<pwc_precision>(p.r.prec),
+                                         static_cast<pwc_pair_algo>(p.r.algo), p.r.d_out, s.stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(s.h_e, p.r.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s.h_err, t.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
         }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s.h_err, t.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-        if (e != hipSuccess) {
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            ++launches;
+            batched += s.members.size() - 1;
+        } else {
             (void)hipStreamSynchronize(s.stream);
             s.busy = false;
-            c.refs -= 1;
             used -= scratch;
-            fail(p, from_hip(e), ms_between(p.t_submit, s.t_launch), built);
+            for (const Member &m : s.members) {
+                m.tab->refs -= 1;
+                Pending fp;
+                fp.ticket = m.ticket;
+                fp.r = m.r;
+                fp.t_submit = m.t_submit;
+                fail(fp, from_hip(e), ms_between(m.t_submit, s.t_launch), m.built);
+            }
+            s.members.clear();
         }
         any = true;
     }
@@ -355,12 +431,15 @@ pwc_status pwc_server_create(size_t hbm_budget_bytes, int max_inflight, pwc_serv
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_e), 2 * sizeof(double));
-        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_err), sizeof(int));
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_err), sizeof(int) * pwc::kDirectMaxJobs);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_err), sizeof(int) * pwc::kDirectMaxJobs);
     }
     if (e != hipSuccess) {
         for (Slot &sl : s->slots) {
             if (sl.h_e) (void)hipHostFree(sl.h_e);
             if (sl.h_err) (void)hipHostFree(sl.h_err);
+            if (sl.d_err) (void)hipFree(sl.d_err);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
@@ -448,6 +527,8 @@ pwc_status pwc_server_get_stats(pwc_server *s, pwc_server_stats *st) {
         st->failed = s->failed;
         st->table_builds = s->builds;
         st->evictions = s->evictions;
+        st->launches = s->launches;
+        st->batched = s->batched;
         lat = s->latencies;
         if (s->have_first && s->completed) st->wall_s = ms_between(s->t_first, s->t_last) * 1e-3;
         if (st->wall_s > 0) {
@@ -474,6 +555,7 @@ pwc_status pwc_server_reset_stats(pwc_server *s) {
     if (!s) return PWC_ERR_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     s->submitted = s->completed = s->failed = s->builds = s->evictions = 0;
+    s->launches = s->batched = 0;
     s->latencies.clear();
     s->integrals = s->pairs = 0.0;
     s->have_first = false;
@@ -494,6 +576,7 @@ pwc_status pwc_server_destroy(pwc_server *s) {
         (void)hipStreamSynchronize(sl.stream);
         (void)hipHostFree(sl.h_e);
         (void)hipHostFree(sl.h_err);
+        (void)hipFree(sl.d_err);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }

@@ -102,29 +102,71 @@ def _check_reconstruct(pw, t, o, quads, L=1.0, label=""):
     return errs
 
 
-def test_reconstruct_plain_all_occupied_quadruples(pw, tables):
+@pytest.mark.parametrize("path", ["direct", "passes"])
+def test_reconstruct_plain_all_occupied_quadruples(pw, tables, path):
     w = workloads.C1_PLAIN
     t = tables(w.n2max, w.n_nodes)
     o = P.setup(w.n2max, w.n_nodes)
     M = int((np.asarray(o["basis"]) ** 2).sum(1).__le__(w.n2occ).sum())
     assert M == 19
-    _check_reconstruct(pw, t, o, workloads.all_quads(M), label="19^4 (123 PW, Q=48)")
+    t.set_direct_max(DIRECT_DEFAULT if path == "direct" else 0)
+    try:
+        _check_reconstruct(pw, t, o, workloads.all_quads(M), label=f"19^4 (123 PW, Q=48) {path}")
+    finally:
+        t.set_direct_max(DIRECT_DEFAULT)
 
 
-@pytest.mark.parametrize("n", [1, 2, 255, 2047, 2048, 2049, 4097, 30001])
-def test_reconstruct_ragged_sizes(pw, tables, n):
+DIRECT_DEFAULT = 1 << 19
+
+
+@pytest.mark.parametrize("path", ["direct", "passes"])
+@pytest.mark.parametrize("n", [1, 2, 255, 1023, 1024, 1025, 2047, 2048, 2049, 4097, 30001])
+def test_reconstruct_ragged_sizes(pw, tables, n, path):
+    """Sizes around the tiles of both reconstruction paths (one lane per
+    quadruple in one launch; node passes over the padded stream)."""
     w = workloads.C2_SPLIT
     t = tables(w.n2max, w.n_nodes)
     o = P.setup(w.n2max, w.n_nodes)
-    _check_reconstruct(pw, t, o, workloads.uniform_quads(len(o["basis"]), n, seed=n),
-                       label=f"ragged n={n}")
+    t.set_direct_max(DIRECT_DEFAULT if path == "direct" else 0)
+    try:
+        _check_reconstruct(pw, t, o, workloads.uniform_quads(len(o["basis"]), n, seed=n),
+                           label=f"ragged n={n} {path}")
+    finally:
+        t.set_direct_max(DIRECT_DEFAULT)
+
+
+@pytest.mark.parametrize("n2max,Q", [(9, 48), (40, 64), (169, 96), (400, 128)])
+def test_direct_and_node_passes_agree(pw, n2max, Q):
+    """The direct kernel (small lists) and the node passes on the same
+    quadruples, both against the oracle and against each other."""
+    import torch
+    o = P.setup(n2max, Q)
+    with pw.Table(1.0, n2max, Q) as t:
+        quads = workloads.uniform_quads(len(o["basis"]), 20000, seed=Q)
+        dq = _dev(quads, torch.int32)
+        out = {}
+        for path, m in (("direct", DIRECT_DEFAULT), ("passes", 0)):
+            t.set_direct_max(m)
+            _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} {path}")
+            for prec in (pw.FP64, pw.MIXED):
+                out[path, prec] = t.reconstruct(dq, precision=prec)
+        t.sync()
+        for prec, tol in ((pw.FP64, 1e-13), (pw.MIXED, 1e-12)):
+            a, b = out["direct", prec], out["passes", prec]
+            assert (a - b).abs().max().item() <= tol * b.abs().max().item()
+        with pytest.raises(pw.PwcError):
+            t.set_direct_max((1 << 20) + 1)
 
 
 def test_reconstruct_profile_matches_and_times_every_launch(pw, tables):
     import torch
     t = tables(169, 96)
     q = _dev(workloads.lookup_stream(9171, 925, 300000, 3), torch.int32)
-    ref = t.reconstruct(q)
+    t.set_direct_max(0)                 # the profile entry point always runs the node passes
+    try:
+        ref = t.reconstruct(q)
+    finally:
+        t.set_direct_max(DIRECT_DEFAULT)
     out, ms = t.reconstruct_profile(q)
     assert torch.equal(out, ref)
     lay = t.layout()
@@ -155,6 +197,7 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
         lay = t.layout(prec)
         return lay["lanes"], lay["words"]
     with pw.Table(1.0, n2max, Q) as t:
+        t.set_direct_max(0)                             # node passes at every size
         assert (lanes_words(t, pw.FP64), lanes_words(t, pw.MIXED)) == (d64, dmx)
         assert t.layout(pw.FP64)["entry_bytes"] == t.layout(pw.MIXED)["entry_bytes"] == eb
         quads = workloads.uniform_quads(len(o["basis"]), 50001, seed=n2max)
@@ -326,8 +369,11 @@ def test_out_of_range_index_reports_and_poisons_only_its_row(pw, tables):
     bad = quads.copy()
     bad[17, 2] = N
     bad[4000, 0] = -3
-    for prec in (pw.FP64, pw.MIXED):
+    for prec, direct_max in ((pw.FP64, DIRECT_DEFAULT), (pw.MIXED, DIRECT_DEFAULT),
+                             (pw.FP64, 0), (pw.MIXED, 0)):
+        t.set_direct_max(direct_max)
         out = t.reconstruct(_dev(bad, torch.int32), precision=prec)
+        t.set_direct_max(DIRECT_DEFAULT)
         with pytest.raises(pw.PwcError) as ei:
             t.sync()
         assert ei.value.status == pw.ERR_RANGE

@@ -79,7 +79,9 @@ def test_each_result_is_identical_alone_and_in_the_mix(pw):
         mixed = _run(pw, srv, reqs, together=True)
         st = srv.stats()
     say(f"[server] mix of {len(reqs)}: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms, "
-        f"{st['integrals_per_s']:.3g} integrals/s, builds {st['table_builds']}")
+        f"{st['integrals_per_s']:.3g} integrals/s, builds {st['table_builds']}, "
+        f"launches {st['launches']}, batched {st['batched']}")
+    assert st["batched"] > 0 and st["launches"] + st["batched"] == len(reqs)
     for a, b in zip(alone, mixed):
         assert np.array_equal(a, b)
     # and identical to the library called directly
@@ -114,6 +116,37 @@ def test_small_budget_queues_and_evicts_but_never_fails(pw):
     assert st["evictions"] > 0 and st["resident_bytes"] <= budget
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
+
+
+def test_bad_request_inside_a_batch_fails_alone(pw):
+    """One slot busy with a long request while three small ones queue: they
+    share one direct launch, and the bad one fails without touching the
+    others."""
+    import torch
+    good = torch.from_numpy(workloads.uniform_quads(123, 3000, seed=4)).cuda()
+    bad = good.clone()
+    bad[1234, 3] = 10 ** 6
+    big = torch.from_numpy(workloads.uniform_quads(9171, 4_000_000, seed=5)).cuda()
+    big_out = torch.empty(big.shape[0], dtype=torch.float64, device="cuda")
+    outs = [torch.empty(3000, dtype=torch.float64, device="cuda") for _ in range(3)]
+    with pw.Server(1 << 30, max_inflight=1) as srv:
+        t0 = srv.submit_reconstruct(1.0, 9, good, torch.empty_like(outs[0]), n_nodes=48)
+        srv.wait(t0)                                     # the 123-PW table is resident
+        tb = srv.submit_reconstruct(1.0, 169, big, big_out, n_nodes=96)   # build + 4e6 quads
+        ts = [srv.submit_reconstruct(1.0, 9, q, o, n_nodes=48) for q, o in zip((good, bad, good), outs)]
+        sts = [srv.wait(x).status for x in ts]
+        assert srv.wait(tb).status == pw.OK
+        st = srv.stats()
+    say(f"[server] batch: launches {st['launches']}, batched {st['batched']}")
+    assert sts == [pw.OK, pw.ERR_RANGE, pw.OK]
+    assert st["batched"] >= 2
+    with pw.Table(1.0, 9, 48) as tab:
+        ref = tab.reconstruct(good).cpu().numpy()
+    assert np.array_equal(outs[0].cpu().numpy(), ref) and np.array_equal(outs[2].cpu().numpy(), ref)
+    got = outs[1].cpu().numpy()
+    assert np.isnan(got[1234])
+    keep = np.arange(3000) != 1234
+    assert np.array_equal(got[keep], ref[keep])
 
 
 def test_server_errors(pw):
