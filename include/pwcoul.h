@@ -65,7 +65,8 @@ typedef enum {
     PWC_ERR_NOMEM = 3,   /* device or host allocation failed */
     PWC_ERR_DEVICE = 4,  /* HIP runtime error */
     PWC_ERR_BUSY = 5,    /* server: queue full or shutting down */
-    PWC_ERR_STATE = 6    /* server: unknown ticket, or object in the wrong state */
+    PWC_ERR_STATE = 6,   /* server: unknown ticket, or object in the wrong state */
+    PWC_ERR_IO = 7       /* table file missing, unreadable, corrupt or inconsistent */
 } pwc_status;
 
 typedef enum {
@@ -203,6 +204,25 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
  * that uses the same table.
  */
 PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
+
+/*
+ * Table persistence.  The 1-D tables of Eq. 8 depend only on the box, the
+ * cutoff and the mesh, so a built table can be kept and reused.
+ * pwc_table_save writes the mesh nodes and weights and the FP64 tables
+ * tau_q(m, m') (Q * nd^2 doubles, the layout of pwc_table_copy) with the box,
+ * cutoff and mesh fields and a checksum to `path` (synchronous; PWC_ERR_IO
+ * if the file cannot be written).  pwc_table_load reads such a file and
+ * creates the table from it without recomputing the 1-D integrals; the
+ * folded, split-FP32, diagonal and kernel tables are derived on the device as
+ * in pwc_table_create.  It returns PWC_ERR_IO for a missing, truncated,
+ * corrupt (checksum) or inconsistent file, before any device work.  *out is
+ * NULL on failure.
+ */
+PWC_API pwc_status pwc_table_save(const pwc_table *t, const char *path);
+PWC_API pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out);
+
+/* Box side, cutoff and mesh of a table.  Any output pointer may be NULL. */
+PWC_API pwc_status pwc_table_params(const pwc_table *t, double *L, int *n2max, pwc_mesh *mesh);
 
 /* Canonical basis vectors: h_n[3 * i + d] = n_d of basis function i (host). */
 PWC_API pwc_status pwc_basis(const pwc_table *t, int32_t *h_n);

@@ -23,7 +23,7 @@ MESH_GEOMETRIC = 0
 MESH_TWO_INTERVAL = 1
 PAIR_AUTO, PAIR_NODESUM, PAIR_KTABLE = 0, 1, 2
 
-OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE = range(7)
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE, ERR_IO = range(8)
 
 
 class PwcError(RuntimeError):
@@ -65,6 +65,10 @@ def lib():
             "pwc_table_create": (i32, [dbl, i32, i32, ctypes.POINTER(Mesh), vp,
                                        ctypes.POINTER(vp)]),
             "pwc_table_destroy": (i32, [vp]),
+            "pwc_table_save": (i32, [vp, ctypes.c_char_p]),
+            "pwc_table_params": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32),
+                                       ctypes.POINTER(Mesh)]),
+            "pwc_table_load": (i32, [ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
             "pwc_table_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
             "pwc_table_layout": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 5),
@@ -131,16 +135,22 @@ def mesh_count(mesh):
 class Table:
     """Owning handle of a pwc_table (tables for one box, cutoff and mesh)."""
 
-    def __init__(self, L, n2max, n_nodes=0, mesh=None, stream=None):
-        h = ctypes.c_void_p()
-        mp = ctypes.byref(mesh) if mesh is not None else None
-        _check(lib().pwc_table_create(float(L), int(n2max), int(n_nodes), mp, _stream(stream),
-                                      ctypes.byref(h)), "pwc_table_create")
+    def __init__(self, L, n2max, n_nodes=0, mesh=None, stream=None, _handle=None):
+        if _handle is not None:
+            h = _handle
+        else:
+            h = ctypes.c_void_p()
+            mp = ctypes.byref(mesh) if mesh is not None else None
+            _check(lib().pwc_table_create(float(L), int(n2max), int(n_nodes), mp, _stream(stream),
+                                          ctypes.byref(h)), "pwc_table_create")
         self._h = h
         N, nmax, Q, nb = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
         _check(lib().pwc_table_info(h, ctypes.byref(N), ctypes.byref(nmax), ctypes.byref(Q),
                                     ctypes.byref(nb)), "pwc_table_info")
-        self.L, self.n2max = float(L), int(n2max)
+        Lv, n2v, mesh_v = ctypes.c_double(), ctypes.c_int(), Mesh()
+        _check(lib().pwc_table_params(h, ctypes.byref(Lv), ctypes.byref(n2v), ctypes.byref(mesh_v)),
+               "pwc_table_params")
+        self.L, self.n2max, self.mesh = Lv.value, n2v.value, mesh_v
         self.N, self.nmax, self.Q, self.device_bytes = N.value, nmax.value, Q.value, nb.value
         self.nd = 4 * self.nmax + 1
 
@@ -166,6 +176,18 @@ class Table:
 
     def __exit__(self, *exc):
         self.close()
+
+    def save(self, path):
+        """Write the mesh and the FP64 tables to `path` (see pwc_table_save)."""
+        _check(lib().pwc_table_save(self.handle, os.fsencode(path)), "pwc_table_save")
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A table from a file written by save(), without recomputing the integrals."""
+        h = ctypes.c_void_p()
+        _check(lib().pwc_table_load(os.fsencode(path), _stream(stream), ctypes.byref(h)),
+               "pwc_table_load")
+        return cls(None, 0, _handle=h)
 
     def layout(self, precision=0):
         """Reconstruction layout of one precision:

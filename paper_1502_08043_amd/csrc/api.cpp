@@ -1,6 +1,7 @@
 // C ABI of libpwcoul: argument checks, table set-up and ownership, launches.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -178,7 +179,7 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
     return PWC_OK;
 }
 
-pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
+pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau) {
     hipError_t e = hipMalloc(&t.d_block, t.bytes);
     if (e != hipSuccess) {
         t.d_block = nullptr;
@@ -230,7 +231,8 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s) {
     up(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
     up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
     up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
-    if (st == PWC_OK) st = from_hip(launch_table_build(t, s));
+    if (h_tau) up(t.d_tau, h_tau, sizeof(double) * static_cast<size_t>(Q) * t.nd * t.nd);
+    if (st == PWC_OK) st = from_hip(launch_table_build(t, s, h_tau != nullptr));
     if (st == PWC_OK) st = from_hip(launch_ktab_build(t, s));
     // The host staging vectors die with this frame: wait for the stream.
     const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
@@ -254,6 +256,7 @@ const char *pwc_status_str(pwc_status s) {
         case PWC_ERR_DEVICE: return "HIP device error";
         case PWC_ERR_BUSY: return "busy";
         case PWC_ERR_STATE: return "invalid state";
+        case PWC_ERR_IO: return "table file error";
     }
     return "unknown status";
 }
@@ -300,6 +303,118 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     return PWC_OK;
 }
 
+namespace {
+
+// Table file: a fixed header, then beta[Q], W[Q] and tau[Q][nd][nd] (FP64,
+// native byte order), the payload covered by an FNV-1a checksum.
+constexpr char kTableMagic[8] = {'P', 'W', 'C', 'T', 'A', 'B', 'L', '1'};
+constexpr uint32_t kTableVersion = 1;
+
+struct TableFileHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    double L;
+    int32_t n2max, Q, nd, mesh_kind;
+    int64_t N;
+    int32_t n_sub, q_sub, q_tail, pad;
+    double ratio, alpha_c;
+    uint64_t payload_bytes, checksum;
+};
+
+uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+pwc_status pwc_table_save(const pwc_table *t, const char *path) {
+    if (!t || !path) return PWC_ERR_ARG;
+    const pwc::Table &tb = t->t;
+    const size_t ntau = static_cast<size_t>(tb.Q) * tb.nd * tb.nd;
+    std::vector<double> payload(2 * static_cast<size_t>(tb.Q) + ntau);
+    std::memcpy(payload.data(), tb.h_beta.data(), sizeof(double) * tb.Q);
+    std::memcpy(payload.data() + tb.Q, tb.h_W.data(), sizeof(double) * tb.Q);
+    const hipError_t e = hipMemcpy(payload.data() + 2 * tb.Q, tb.d_tau, sizeof(double) * ntau,
+                                   hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    TableFileHeader h{};
+    std::memcpy(h.magic, kTableMagic, sizeof(h.magic));
+    h.version = kTableVersion;
+    h.header_bytes = sizeof(h);
+    h.L = tb.L;
+    h.n2max = tb.n2max;
+    h.Q = tb.Q;
+    h.nd = tb.nd;
+    h.mesh_kind = tb.mesh.kind;
+    h.N = tb.N;
+    h.n_sub = tb.mesh.n_sub;
+    h.q_sub = tb.mesh.q_sub;
+    h.q_tail = tb.mesh.q_tail;
+    h.ratio = tb.mesh.ratio;
+    h.alpha_c = tb.mesh.alpha_c;
+    h.payload_bytes = sizeof(double) * payload.size();
+    h.checksum = fnv1a(payload.data(), h.payload_bytes);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return PWC_ERR_IO;
+    const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+                    std::fwrite(payload.data(), 1, h.payload_bytes, f) == h.payload_bytes;
+    const bool closed = std::fclose(f) == 0;
+    return ok && closed ? PWC_OK : PWC_ERR_IO;
+}
+
+pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
+    if (!out) return PWC_ERR_ARG;
+    *out = nullptr;
+    if (!path) return PWC_ERR_ARG;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return PWC_ERR_IO;
+    TableFileHeader h{};
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1 &&
+              std::memcmp(h.magic, kTableMagic, sizeof(h.magic)) == 0 &&
+              h.version == kTableVersion && h.header_bytes == sizeof(h) && h.Q > 0 && h.nd > 0 &&
+              h.payload_bytes == sizeof(double) * (2 * static_cast<uint64_t>(h.Q) +
+                                                   static_cast<uint64_t>(h.Q) * h.nd * h.nd);
+    std::vector<double> payload;
+    if (ok) {
+        payload.resize(h.payload_bytes / sizeof(double));
+        ok = std::fread(payload.data(), 1, h.payload_bytes, f) == h.payload_bytes &&
+             std::fgetc(f) == EOF && fnv1a(payload.data(), h.payload_bytes) == h.checksum;
+    }
+    std::fclose(f);
+    if (!ok) return PWC_ERR_IO;
+    pwc_mesh m{};
+    m.kind = static_cast<pwc_mesh_kind>(h.mesh_kind);
+    m.n_sub = h.n_sub;
+    m.q_sub = h.q_sub;
+    m.q_tail = h.q_tail;
+    m.ratio = h.ratio;
+    m.alpha_c = h.alpha_c;
+    int q = 0;
+    if (!pwc::mesh_valid(m, &q) || q != h.Q) return PWC_ERR_IO;
+    pwc_table *t = new (std::nothrow) pwc_table;
+    if (!t) return PWC_ERR_NOMEM;
+    pwc::TableSetup su;
+    pwc_status st = pwc::plan_table(h.L, h.n2max, m, t->t, su);
+    if (st == PWC_OK && (t->t.Q != h.Q || t->t.nd != h.nd || t->t.N != h.N)) st = PWC_ERR_IO;
+    if (st == PWC_OK) {
+        // The stored mesh is the table's mesh.
+        t->t.h_beta.assign(payload.begin(), payload.begin() + h.Q);
+        t->t.h_W.assign(payload.begin() + h.Q, payload.begin() + 2 * h.Q);
+        st = pwc::build_table(t->t, su, static_cast<hipStream_t>(stream), payload.data() + 2 * h.Q);
+    }
+    if (st != PWC_OK) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return PWC_OK;
+}
+
 pwc_status pwc_table_destroy(pwc_table *t) {
     if (!t) return PWC_OK;
     pwc::free_table(t->t);
@@ -343,6 +458,14 @@ pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
         return PWC_ERR_RANGE;
     t->t.fl = fl;
     t->t.flm = flm;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_params(const pwc_table *t, double *L, int *n2max, pwc_mesh *mesh) {
+    if (!t) return PWC_ERR_ARG;
+    if (L) *L = t->t.L;
+    if (n2max) *n2max = t->t.n2max;
+    if (mesh) *mesh = t->t.mesh;
     return PWC_OK;
 }
 

@@ -107,11 +107,13 @@ struct TableSetup {
 };
 bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl);
 pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
-pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s);
+// h_tau: the FP64 tables [Q][nd][nd] of a loaded table (the 1-D integrals are
+// then not recomputed), or nullptr.
+pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau = nullptr);
 void free_table(Table &t);
 
 // table_kernels.hip
-hipError_t launch_table_build(Table &t, hipStream_t s);
+hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau);
 // reconstruct_kernels.hip
 // Bytes of one decoded quadruple in the scratch stream (4 when E <= 1024).
 int packed_entry_bytes(int E);

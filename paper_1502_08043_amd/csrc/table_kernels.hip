@@ -84,6 +84,7 @@ struct AsmArgs {
     const int32_t *fold;
     const int32_t *reps;
     int K, nd, E, Qp, dc;
+    int from_tau;      // 1: tau is given (a loaded table), derive the layouts only
     double *tau;
     double *tauF;
     float2 *tauHL;
@@ -97,19 +98,24 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
     if (e >= a.nd * a.nd) return;
     const int row = e / a.nd, col = e % a.nd;
     const int m = row - a.K, mp = col - a.K;
-    const double *S = a.prim + static_cast<size_t>(q) * 2 * (a.K + 1);
-    const double *D = S + (a.K + 1);
-    const double rb = sqrt(a.beta[q]);
     const int s = m + mp;
+    const size_t ti = (static_cast<size_t>(q) * a.nd + row) * a.nd + col;
     double v;
-    if (s == 0) {
-        v = 2.0 / rb * D[m < 0 ? -m : m];
+    if (a.from_tau) {
+        v = a.tau[ti];
     } else {
-        const double sm = m < 0 ? -S[-m] : S[m];
-        const double smp = mp < 0 ? -S[-mp] : S[mp];
-        v = -(sm + smp) / (M_PI * s * rb);
+        const double *S = a.prim + static_cast<size_t>(q) * 2 * (a.K + 1);
+        const double *D = S + (a.K + 1);
+        const double rb = sqrt(a.beta[q]);
+        if (s == 0) {
+            v = 2.0 / rb * D[m < 0 ? -m : m];
+        } else {
+            const double sm = m < 0 ? -S[-m] : S[m];
+            const double smp = mp < 0 ? -S[-mp] : S[mp];
+            v = -(sm + smp) / (M_PI * s * rb);
+        }
+        a.tau[ti] = v;
     }
-    a.tau[(static_cast<size_t>(q) * a.nd + row) * a.nd + col] = v;
     // Folded layout: only the orbit representative writes its slot, scaled
     // by W_q^(1/3) so that a node term of Eq. 14 is the plain product of
     // three folded entries.
@@ -130,13 +136,15 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
 
 }  // namespace
 
-hipError_t launch_table_build(Table &t, hipStream_t s) {
-    dim3 gp(t.K + 1, t.Q);
-    hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
+hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau) {
+    if (!from_tau) {
+        dim3 gp(t.K + 1, t.Q);
+        hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
     AsmArgs a{t.d_beta, t.d_Wcbrt, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.Qp, t.dl.c,
-              t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
+              from_tau ? 1 : 0, t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
     dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q);
     hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);
     return hipGetLastError();

@@ -107,3 +107,36 @@ def test_server_create_rejects_bad_arguments(lib):
     assert lib.pwc_server_create(1 << 30, 4, None) == 1
     lib.pwc_server_destroy.argtypes = [ctypes.c_void_p]
     assert lib.pwc_server_destroy(None) == 0
+
+
+def test_table_files_rejected_before_device_work(lib, tmp_path):
+    """pwc_table_load refuses missing, foreign and corrupt files with
+    PWC_ERR_IO before touching the device."""
+    import struct
+
+    import numpy as np
+    lib.pwc_table_load.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.pwc_table_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    lib.pwc_status_str.restype = ctypes.c_char_p
+    assert lib.pwc_status_str(7) == b"table file error"
+    h = ctypes.c_void_p()
+    assert lib.pwc_table_load(str(tmp_path / "missing.tab").encode(), None, ctypes.byref(h)) == 7
+    assert h.value is None
+    assert lib.pwc_table_load(None, None, ctypes.byref(h)) == 1
+    assert lib.pwc_table_save(None, str(tmp_path / "x.tab").encode()) == 1
+    foreign = tmp_path / "foreign.tab"
+    foreign.write_bytes(b"not a table file" * 16)
+    assert lib.pwc_table_load(str(foreign).encode(), None, ctypes.byref(h)) == 7
+    # a well-formed header (Q = 16, nd = 5) whose payload fails the checksum
+    Q, nd = 16, 5
+    payload = np.arange(2 * Q + Q * nd * nd, dtype=np.float64).tobytes()
+    head = struct.pack("<8sIIdiiiiqiiiiddQQ", b"PWCTABL1", 1, 96, 1.0, 2, Q, nd, 0, 19,
+                       8, 1, 8, 0, 5.0, 0.0, len(payload), 12345)
+    assert len(head) == 96
+    bad = tmp_path / "bad.tab"
+    bad.write_bytes(head + payload)
+    assert lib.pwc_table_load(str(bad).encode(), None, ctypes.byref(h)) == 7
+    trunc = tmp_path / "trunc.tab"
+    trunc.write_bytes(head + payload[:-8])
+    assert lib.pwc_table_load(str(trunc).encode(), None, ctypes.byref(h)) == 7
+    assert h.value is None

@@ -417,3 +417,45 @@ def test_concurrent_streams_share_one_table(pw, tables):
     torch.cuda.synchronize()
     assert torch.equal(a, ref) and torch.equal(c, ref)
     assert (b - ref).abs().max().item() < 1e-12
+
+
+@pytest.mark.parametrize("n2max,mesh", [(169, ("geometric", 11, 8)), (25, ("two_interval", 20))])
+def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
+    """A saved and reloaded table has the same mesh and FP64 tables and gives
+    bitwise the same integrals (both paths, both precisions) and energies;
+    a damaged file is refused."""
+    import torch
+    m = pw.Mesh.geometric(mesh[1], mesh[2]) if mesh[0] == "geometric" else pw.Mesh.two_interval(mesh[1])
+    path = tmp_path / "t.tab"
+    with pw.Table(1.0, n2max, 0, mesh=m) as t:
+        t.save(path)
+        quads = _dev(workloads.uniform_quads(t.N, 700_001, seed=3), torch.int32)
+        occ = torch.arange(min(t.N, 123), dtype=torch.int32, device="cuda")
+        ref = {}
+        for dm in (DIRECT_DEFAULT, 0):
+            t.set_direct_max(dm)
+            for prec in (pw.FP64, pw.MIXED):
+                ref[dm, prec] = t.reconstruct(quads[:200_000] if dm else quads, precision=prec)
+        t.set_direct_max(DIRECT_DEFAULT)
+        e_ref = t.energies(occ)
+        tau_ref, mesh_ref = t.copy_tables(), t.mesh_nodes()
+        t.sync()
+    with pw.Table.load(path) as u:
+        assert (u.L, u.n2max, u.Q) == (1.0, n2max, sum(1 for _ in mesh_ref[0]))
+        assert torch.equal(u.copy_tables(), tau_ref)
+        for a, b in zip(u.mesh_nodes(), mesh_ref):
+            assert np.array_equal(a, b)
+        for dm in (DIRECT_DEFAULT, 0):
+            u.set_direct_max(dm)
+            for prec in (pw.FP64, pw.MIXED):
+                got = u.reconstruct(quads[:200_000] if dm else quads, precision=prec)
+                assert torch.equal(got, ref[dm, prec])
+        u.set_direct_max(DIRECT_DEFAULT)
+        assert np.array_equal(u.energies(occ), e_ref)
+        u.sync()
+    raw = bytearray(path.read_bytes())
+    raw[200] ^= 1
+    (tmp_path / "flip.tab").write_bytes(bytes(raw))
+    with pytest.raises(pw.PwcError) as ei:
+        pw.Table.load(tmp_path / "flip.tab")
+    assert ei.value.status == pw.ERR_IO
