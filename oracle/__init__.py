@@ -14,7 +14,9 @@ Many-Electron Quantum Mechanical Coulomb Problem to O(N^{2/3}) Storage"):
               with the t = 1/sqrt(alpha) map on the tail (Eqs. 10-14), and the
               geometric "Mesh 2" sub-intervals (Sec. III, Table I).
 * tables   -- the 1-D integral of Eq. 8 for planewave factors, one table per
-              quadrature node indexed by the two wavevector differences.
+              quadrature node indexed by the two wavevector differences;
+              for a rectangular box one such table per direction, at the
+              node scaled by that direction's side (box_tables).
 * sums     -- the node sum of Eq. 14 (reconstruction of <ij|kl>) and the
               uniform-electron-gas Hartree / exchange pair sums of Sec. III,
               in plain C with Neumaier-compensated FP64 accumulation.
@@ -27,14 +29,14 @@ are none.
 """
 from .basis import enumerate_basis, shell_counts
 from .mesh import gauss_legendre, mesh1, mesh2, default_mesh
-from .tables import primitives, tau_table, tau_diag, tau00_closed_form
+from .tables import primitives, tau_table, tau_diag, tau00_closed_form, box_tables
 from .sums import reconstruct, energies
 from .exchange_hist import diff_histogram, exchange_from_histogram
 from .physics import e_ks, k_cube
 
 __all__ = [
     "enumerate_basis", "shell_counts", "gauss_legendre", "mesh1", "mesh2",
-    "default_mesh", "primitives", "tau_table", "tau_diag", "tau00_closed_form",
+    "default_mesh", "primitives", "tau_table", "tau_diag", "tau00_closed_form", "box_tables",
     "reconstruct", "energies", "diff_histogram",
     "exchange_from_histogram", "e_ks", "k_cube",
 ]

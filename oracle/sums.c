@@ -4,12 +4,14 @@
  * TEST INFRASTRUCTURE ONLY: linked by nothing in the product path.
  *
  * Inputs are the oracle's own tables (tables.py), mesh (mesh.py) and basis
- * (basis.py).  Table layout: tau[q][m + K][m' + K], m, m' in [-K, K],
- * nd = 2K + 1.
+ * (basis.py).  Table layout: tau[d][q][m + K][m' + K], m, m' in [-K, K],
+ * nd = 2K + 1, with ndir = 1 (a cube: one table serves every direction) or
+ * ndir = 3 (a rectangular box: table d for direction d).
  *
  * reconstruct: Eq. 14 -- <ij|kl> = (1/(sqrt(pi) L)) sum_q W_q
- *              tau_q(m_x, m'_x) tau_q(m_y, m'_y) tau_q(m_z, m'_z),
- *              with m = n_k - n_i and m' = n_l - n_j per direction.
+ *              tau^x_q(m_x, m'_x) tau^y_q(m_y, m'_y) tau^z_q(m_z, m'_z),
+ *              with m = n_k - n_i and m' = n_l - n_j per direction (L the
+ *              cube side, or the reference length of a box).
  * energies:    Sec. III uniform electron gas, one spin channel:
  *              E_H =  1/2 sum_{i,j} f_i f_j <ij|ij>,
  *              E_x = -1/2 sum_{i,j} f_i f_j <ij|ji>   (i = j included),
@@ -50,13 +52,14 @@ static void set_threads(int nthreads) {
 #endif
 }
 
-/* Node sum for one integral given the three flat table offsets. */
-static double node_sum(const double *tau, const double *W, int Q, int64_t slice,
-                       int64_t ox, int64_t oy, int64_t oz) {
+/* Node sum for one integral given the three flat table offsets; direction
+ * d reads table tau + d * dstride (dstride = 0 for a cube). */
+static double node_sum(const double *tau, int64_t dstride, const double *W, int Q,
+                       int64_t slice, int64_t ox, int64_t oy, int64_t oz) {
     nsum acc = {0.0, 0.0};
     for (int q = 0; q < Q; ++q) {
         const double *t = tau + (int64_t)q * slice;
-        double term = W[q] * t[ox] * t[oy] * t[oz];
+        double term = W[q] * t[ox] * t[dstride + oy] * t[2 * dstride + oz];
         nadd(&acc, term);
     }
     return nval(&acc);
@@ -67,10 +70,12 @@ static inline int64_t offset(int64_t m, int64_t mp, int K) {
     return (m + K) * (int64_t)(2 * K + 1) + (mp + K);
 }
 
-int oracle_reconstruct(const double *tau, const double *W, int Q, int K,
+int oracle_reconstruct(const double *tau, int ndir, const double *W, int Q, int K,
                        const int64_t *basis, int64_t N, const int32_t *quads,
                        int64_t n, double L, double *out, int nthreads) {
     const int64_t nd = 2 * K + 1, slice = nd * nd;
+    const int64_t dstride = ndir == 3 ? (int64_t)Q * slice : 0;
+    if (ndir != 1 && ndir != 3) return 1;
     const double pref = 1.0 / (sqrt(M_PI) * L);
     int bad = 0;
     for (int64_t e = 0; e < 4 * n; ++e)
@@ -90,16 +95,18 @@ int oracle_reconstruct(const double *tau, const double *W, int Q, int K,
             o[d] = offset(m, mp, K);
         }
         if (o[0] < 0 || o[1] < 0 || o[2] < 0) { out[e] = NAN; continue; }
-        out[e] = pref * node_sum(tau, W, Q, slice, o[0], o[1], o[2]);
+        out[e] = pref * node_sum(tau, dstride, W, Q, slice, o[0], o[1], o[2]);
     }
     return 0;
 }
 
-int oracle_energies(const double *tau, const double *W, int Q, int K,
+int oracle_energies(const double *tau, int ndir, const double *W, int Q, int K,
                     const int64_t *basis, int64_t N, const int32_t *occ,
                     const double *f, int64_t M, double L, double *eh, double *ex,
                     int nthreads) {
     const int64_t nd = 2 * K + 1, slice = nd * nd;
+    const int64_t dstride = ndir == 3 ? (int64_t)Q * slice : 0;
+    if (ndir != 1 && ndir != 3) return 1;
     const double pref = 1.0 / (sqrt(M_PI) * L);
     for (int64_t i = 0; i < M; ++i)
         if (occ[i] < 0 || occ[i] >= N) return 2;
@@ -117,11 +124,11 @@ int oracle_energies(const double *tau, const double *W, int Q, int K,
             const double fij = fi * (f ? f[j] : 1.0);
             /* <ij|ij>: k = i, l = j -> m = m' = 0 in every direction. */
             int64_t oh = offset(0, 0, K);
-            nadd(&h, fij * node_sum(tau, W, Q, slice, oh, oh, oh));
+            nadd(&h, fij * node_sum(tau, dstride, W, Q, slice, oh, oh, oh));
             /* <ij|ji>: k = j, l = i -> m = n_j - n_i, m' = n_i - n_j. */
             int64_t o[3];
             for (int d = 0; d < 3; ++d) o[d] = offset(nj[d] - ni[d], ni[d] - nj[d], K);
-            nadd(&x, fij * node_sum(tau, W, Q, slice, o[0], o[1], o[2]));
+            nadd(&x, fij * node_sum(tau, dstride, W, Q, slice, o[0], o[1], o[2]));
         }
         rowh[i] = nval(&h);
         rowx[i] = nval(&x);

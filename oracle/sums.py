@@ -40,11 +40,11 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)
         i32p = ctypes.POINTER(ctypes.c_int32)
-        lib.oracle_reconstruct.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, i64p,
+        lib.oracle_reconstruct.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, i64p,
                                            ctypes.c_int64, i32p, ctypes.c_int64,
                                            ctypes.c_double, dp, ctypes.c_int]
         lib.oracle_reconstruct.restype = ctypes.c_int
-        lib.oracle_energies.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, i64p,
+        lib.oracle_energies.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, i64p,
                                         ctypes.c_int64, i32p, dp, ctypes.c_int64,
                                         ctypes.c_double, dp, dp, ctypes.c_int]
         lib.oracle_energies.restype = ctypes.c_int
@@ -57,21 +57,27 @@ def _ptr(a, ctype):
 
 
 def _prep(tau, W, basis):
+    """tau: [Q, nd, nd] (a cube) or [3, Q, nd, nd] (a box, one table per direction)."""
     tau = np.ascontiguousarray(tau, dtype=np.float64)
     W = np.ascontiguousarray(W, dtype=np.float64)
     basis = np.ascontiguousarray(basis, dtype=np.int64)
-    Q, nd, nd2 = tau.shape
+    ndir = 3 if tau.ndim == 4 else 1
+    if ndir == 3 and tau.shape[0] != 3:
+        raise ValueError("a box takes three direction tables")
+    Q, nd, nd2 = tau.shape[-3:]
     if nd != nd2 or nd % 2 != 1 or W.shape != (Q,):
-        raise ValueError("tau must be [Q, 2K+1, 2K+1] and W [Q]")
-    return tau, W, basis, Q, (nd - 1) // 2
+        raise ValueError("tau must be [(3,) Q, 2K+1, 2K+1] and W [Q]")
+    return tau, ndir, W, basis, Q, (nd - 1) // 2
 
 
 def reconstruct(tau, W, basis, quads, L=1.0, nthreads=0):
-    """<ij|kl> for each row (i, j, k, l) of quads, by Eq. 14 (FP64, compensated)."""
-    tau, W, basis, Q, K = _prep(tau, W, basis)
+    """<ij|kl> for each row (i, j, k, l) of quads, by Eq. 14 (FP64, compensated).
+    For a box, tau holds the three direction tables and L is the reference
+    length (box_tables)."""
+    tau, ndir, W, basis, Q, K = _prep(tau, W, basis)
     quads = np.ascontiguousarray(quads, dtype=np.int32).reshape(-1, 4)
     out = np.empty(quads.shape[0])
-    rc = _load().oracle_reconstruct(_ptr(tau, ctypes.c_double), _ptr(W, ctypes.c_double),
+    rc = _load().oracle_reconstruct(_ptr(tau, ctypes.c_double), ndir, _ptr(W, ctypes.c_double),
                                     Q, K, _ptr(basis, ctypes.c_int64), basis.shape[0],
                                     _ptr(quads, ctypes.c_int32), quads.shape[0],
                                     float(L), _ptr(out, ctypes.c_double), int(nthreads))
@@ -84,7 +90,7 @@ def reconstruct(tau, W, basis, quads, L=1.0, nthreads=0):
 
 def energies(tau, W, basis, occ, f=None, L=1.0, nthreads=0):
     """(E_H, E_x) per spin channel by literal double loops over ordered pairs."""
-    tau, W, basis, Q, K = _prep(tau, W, basis)
+    tau, ndir, W, basis, Q, K = _prep(tau, W, basis)
     occ = np.ascontiguousarray(occ, dtype=np.int32).reshape(-1)
     fp = None
     if f is not None:
@@ -94,7 +100,7 @@ def energies(tau, W, basis, occ, f=None, L=1.0, nthreads=0):
         fp = _ptr(f, ctypes.c_double)
     eh = ctypes.c_double()
     ex = ctypes.c_double()
-    rc = _load().oracle_energies(_ptr(tau, ctypes.c_double), _ptr(W, ctypes.c_double),
+    rc = _load().oracle_energies(_ptr(tau, ctypes.c_double), ndir, _ptr(W, ctypes.c_double),
                                  Q, K, _ptr(basis, ctypes.c_int64), basis.shape[0],
                                  _ptr(occ, ctypes.c_int32), fp, occ.shape[0], float(L),
                                  ctypes.byref(eh), ctypes.byref(ex), int(nthreads))

@@ -92,6 +92,27 @@ def tau_table(beta, K: int) -> np.ndarray:
     return out
 
 
+def box_tables(beta, K: int, sides):
+    """Direction tables of a rectangular box with sides (Lx, Ly, Lz).
+
+    Writing 1/r as a Gaussian integral, each direction d of a box factorises
+    as in a cube of side L_d, with its Gaussian exponent scaled by the side:
+    on the reference mesh beta = 1/(t L0^2) direction d sees
+    beta_d = beta / rho_d^2, rho_d = L_d / L0, and the node sum of Eq. 14
+    becomes (sqrt(pi) L0 rho_x rho_y rho_z)^{-1} sum_q W_q prod_d
+    tau(beta_q / rho_d^2; m_d, m'_d).  With L0 the geometric mean of the
+    sides the rho product is 1 and the prefactor keeps its cube form.
+
+    Returns (L0, rho [3], tau [3, Q, 2K+1, 2K+1]).
+    """
+    sides = np.asarray(sides, dtype=np.float64)
+    L0 = float(np.prod(sides) ** (1.0 / 3.0))
+    rho = sides / L0
+    beta = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+    tau = np.stack([tau_table(beta / (r * r), K) for r in rho])
+    return L0, rho, tau
+
+
 def tau_diag(beta, K: int) -> np.ndarray:
     """Diagonal entries tau_q(m, -m) for m in [-K, K]: float64 [Q, 2K+1].
 

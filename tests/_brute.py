@@ -47,20 +47,22 @@ def _overlap(u, m, mp):
 
 
 def coulomb6d(ni, nj, nk, nl, L=1.0, n=40):
-    """Exact <ij|kl> = Int Int phi_i*(r) phi_j*(r') phi_k(r) phi_l(r') / |r - r'|.
+    """Exact <ij|kl> = Int Int phi_i*(r) phi_j*(r') phi_k(r) phi_l(r') / |r - r'|
+    in a box with sides L (a number for a cube, or (Lx, Ly, Lz)).
 
-    With m = n_k - n_i, m' = n_l - n_j and u = xi - xi' the integral is
-    (1/L) Int_{[-1,1]^3} prod_d G_d(u_d) / |u| d^3u.  Each sign octant of u is
-    split into three pyramids (one per coordinate being the largest); with
-    v = r (1, s, t), d^3v = r^2 dr ds dt and |v| = r sqrt(1 + s^2 + t^2), the
-    integrand is smooth, so plain tensor Gauss-Legendre converges fast.
+    With m = n_k - n_i, m' = n_l - n_j and u = xi - xi' (reduced coordinates
+    r_d = L_d xi_d) the integral is Int_{[-1,1]^3} prod_d G_d(u_d) /
+    sqrt(sum_d L_d^2 u_d^2) d^3u.  Each sign octant of u is split into three
+    pyramids (one per coordinate being the largest); with v = r (1, s, t),
+    d^3v = r^2 dr ds dt and the distance r sqrt(L_a^2 + L_b^2 s^2 + L_c^2 t^2),
+    the integrand is smooth, so plain tensor Gauss-Legendre converges fast.
     """
     m = np.asarray(nk) - np.asarray(ni)
     mp = np.asarray(nl) - np.asarray(nj)
+    Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
     x, w = _gl(n)
     R, S, T = np.meshgrid(x, x, x, indexing="ij")
     Wt = w[:, None, None] * w[None, :, None] * w[None, None, :]
-    base = Wt * R / np.sqrt(1.0 + S * S + T * T)
     total = 0.0 + 0.0j
     for sx in (1.0, -1.0):
         for sy in (1.0, -1.0):
@@ -72,8 +74,10 @@ def coulomb6d(ni, nj, nk, nl, L=1.0, n=40):
                     others = [d for d in range(3) if d != apex]
                     comp[others[0]] = R * S
                     comp[others[1]] = R * T
+                    base = Wt * R / np.sqrt(Ls[apex] ** 2 + (Ls[others[0]] * S) ** 2 +
+                                            (Ls[others[1]] * T) ** 2)
                     g = np.ones_like(R, dtype=complex)
                     for d in range(3):
                         g = g * _overlap(sg[d] * comp[d], int(m[d]), int(mp[d]))
                     total += (base * g).sum()
-    return total / L
+    return total

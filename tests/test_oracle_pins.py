@@ -339,3 +339,49 @@ def test_exchange_ratio_tends_to_one_with_shell_size():
     x = np.array(g["M"], dtype=float) ** (-1.0 / 3.0)
     slope, icpt = np.polyfit(x[-5:], ratios[-5:], 1)
     assert 0.99 < icpt < 1.0 and slope < 0
+
+
+# ------------------------------------------------------ rectangular boxes ----
+# Each direction of a box with sides (Lx, Ly, Lz) uses the cube's table
+# function at the node scaled by (L_d / L0)^-2, L0 = (Lx Ly Lz)^(1/3).
+
+BOXES = [(1.0, 1.3, 0.8), (2.0, 1.0, 0.5)]
+
+
+@pytest.mark.parametrize("sides", BOXES)
+def test_box_integrals_against_bruteforce_6d(sides):
+    b = oracle.enumerate_basis(2)
+    beta, W, _ = oracle.mesh2(21, 24)     # aspect ratios up to 4 need a finer mesh
+    L0, rho, taus = oracle.box_tables(beta, 2, sides)
+    assert abs(np.prod(rho) - 1.0) < 1e-15
+    quads = [(0, 0, 0, 0), (1, 2, 3, 4), (5, 1, 0, 7), (3, 3, 12, 18), (7, 9, 11, 13), (18, 2, 4, 16)]
+    got = oracle.reconstruct(taus, W, b, np.array(quads), L=L0)
+    for q, c in zip(quads, got):
+        ref = _brute.coulomb6d(*[b[x] for x in q], L=sides, n=40)
+        assert abs(ref.imag) < 1e-14
+        assert abs(c - ref.real) < 1e-10 * max(abs(ref.real), 1e-3), (sides, q, c, ref)
+
+
+def test_box_axis_permutation_and_scaling():
+    """Swapping two sides and the same two components of every basis vector
+    leaves each integral unchanged; scaling all sides by s divides it by s;
+    equal sides give the cube's tables exactly."""
+    b = oracle.enumerate_basis(9)
+    beta, W, _ = oracle.default_mesh(48)
+    quads = workloads.uniform_quads(len(b), 400, seed=21)
+    L0, _, t1 = oracle.box_tables(beta, 6, (1.0, 1.4, 0.7))
+    v1 = oracle.reconstruct(t1, W, b, quads, L=L0)
+    L0s, _, t2 = oracle.box_tables(beta, 6, (1.4, 1.0, 0.7))
+    v2 = oracle.reconstruct(t2, W, b[:, [1, 0, 2]], quads, L=L0s)
+    scale = np.abs(v1).max()
+    assert np.max(np.abs(v1 - v2)) < 1e-15 * scale
+    L0d, _, t3 = oracle.box_tables(beta, 6, (2.0, 2.8, 1.4))
+    v3 = oracle.reconstruct(t3, W, b, quads, L=L0d)
+    assert np.max(np.abs(2.0 * v3 - v1)) < 1e-15 * scale
+    _, _, tc = oracle.box_tables(beta, 6, (1.0, 1.0, 1.0))
+    assert np.array_equal(tc[0], oracle.tau_table(beta, 6)) and np.array_equal(tc[1], tc[2])
+    # Hartree: every <ij|ij> is <00|00>
+    occ = np.arange(19)
+    eh, ex = oracle.energies(t1, W, b, occ, L=L0)
+    c00 = oracle.reconstruct(t1, W, b, np.zeros((1, 4), dtype=np.int32), L=L0)[0]
+    assert abs(eh - 0.5 * 19 ** 2 * c00) < 1e-13 * eh and ex < 0
