@@ -160,6 +160,22 @@ PWC_API pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes);
 PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *mesh,
                             void *stream, pwc_table **out);
 
+/*
+ * A rectangular box with sides (Lx, Ly, Lz).  The summary of the paper
+ * names such separable cases without formulas; writing 1/r as a Gaussian
+ * integral, direction d factorises as in a cube of side L_d, so on the
+ * reference mesh beta = 4 alpha / L0^2, L0 = (Lx Ly Lz)^(1/3), direction d
+ * reads its own tables at the node beta_q / rho_d^2, rho_d = L_d / L0, and
+ *   <ij|kl> = (1/(sqrt(pi) L0)) sum_q W_q tau^x_q tau^y_q tau^z_q.
+ * alpha_c of a mesh refers to L0.  The basis is the same |n|^2 <= n2max set
+ * of integer vectors.  Equal sides give exactly the table of
+ * pwc_table_create.  The exchange kernel table of a box has (K+1)^3 entries
+ * (no sorting across directions) and is kept when it fits on chip.  Errors
+ * and ownership as pwc_table_create.
+ */
+PWC_API pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int n_nodes,
+                                        const pwc_mesh *mesh, void *stream, pwc_table **out);
+
 /* Free a table and its device memory.  NULL is accepted. */
 PWC_API pwc_status pwc_table_destroy(pwc_table *t);
 
@@ -209,7 +225,7 @@ PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
  * Table persistence.  The 1-D tables of Eq. 8 depend only on the box, the
  * cutoff and the mesh, so a built table can be kept and reused.
  * pwc_table_save writes the mesh nodes and weights and the FP64 tables
- * tau_q(m, m') (Q * nd^2 doubles, the layout of pwc_table_copy) with the box,
+ * tau_q(m, m') (the layout of pwc_table_copy) with the box sides,
  * cutoff and mesh fields and a checksum to `path` (synchronous; PWC_ERR_IO
  * if the file cannot be written).  pwc_table_load reads such a file and
  * creates the table from it without recomputing the 1-D integrals; the
@@ -221,8 +237,12 @@ PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
 PWC_API pwc_status pwc_table_save(const pwc_table *t, const char *path);
 PWC_API pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out);
 
-/* Box side, cutoff and mesh of a table.  Any output pointer may be NULL. */
+/* Reference length (cube side, or (Lx Ly Lz)^(1/3) of a box), cutoff and
+ * mesh of a table.  Any output pointer may be NULL. */
 PWC_API pwc_status pwc_table_params(const pwc_table *t, double *L, int *n2max, pwc_mesh *mesh);
+
+/* The three box sides of a table: sides[3] (host). */
+PWC_API pwc_status pwc_table_box(const pwc_table *t, double *sides);
 
 /* Canonical basis vectors: h_n[3 * i + d] = n_d of basis function i (host). */
 PWC_API pwc_status pwc_basis(const pwc_table *t, int32_t *h_n);
@@ -232,8 +252,9 @@ PWC_API pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_
 
 /*
  * Copy the FP64 tables into the caller's device buffer, layout
- * d_dst[(q * nd + (m + 2 nmax)) * nd + (m' + 2 nmax)] = tau_q(m, m'),
- * nd = 4 nmax + 1, m, m' in [-2 nmax, 2 nmax].  Async on `stream`.
+ * d_dst[((d * Q + q) * nd + (m + 2 nmax)) * nd + (m' + 2 nmax)] = tau^d_q(m, m'),
+ * nd = 4 nmax + 1, m, m' in [-2 nmax, 2 nmax], d < 1 for a cube (one table
+ * serves every direction) and d < 3 for a box.  Async on `stream`.
  */
 PWC_API pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream);
 

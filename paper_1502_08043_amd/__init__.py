@@ -66,6 +66,9 @@ def lib():
                                        ctypes.POINTER(vp)]),
             "pwc_table_destroy": (i32, [vp]),
             "pwc_table_save": (i32, [vp, ctypes.c_char_p]),
+            "pwc_table_create_box": (i32, [dbl, dbl, dbl, i32, i32, ctypes.POINTER(Mesh), vp,
+                                           ctypes.POINTER(vp)]),
+            "pwc_table_box": (i32, [vp, ctypes.POINTER(dbl)]),
             "pwc_table_params": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                        ctypes.POINTER(Mesh)]),
             "pwc_table_load": (i32, [ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
@@ -152,6 +155,10 @@ class Table:
                "pwc_table_params")
         self.L, self.n2max, self.mesh = Lv.value, n2v.value, mesh_v
         self.N, self.nmax, self.Q, self.device_bytes = N.value, nmax.value, Q.value, nb.value
+        sides = (ctypes.c_double * 3)()
+        _check(lib().pwc_table_box(h, sides), "pwc_table_box")
+        self.sides = tuple(sides)
+        self.ndir = 1 if self.sides[0] == self.sides[1] == self.sides[2] else 3
         self.nd = 4 * self.nmax + 1
 
     @property
@@ -180,6 +187,16 @@ class Table:
     def save(self, path):
         """Write the mesh and the FP64 tables to `path` (see pwc_table_save)."""
         _check(lib().pwc_table_save(self.handle, os.fsencode(path)), "pwc_table_save")
+
+    @classmethod
+    def box(cls, Lx, Ly, Lz, n2max, n_nodes=0, mesh=None, stream=None):
+        """Tables of a rectangular box with sides (Lx, Ly, Lz) (see pwc_table_create_box)."""
+        h = ctypes.c_void_p()
+        mp = ctypes.byref(mesh) if mesh is not None else None
+        _check(lib().pwc_table_create_box(float(Lx), float(Ly), float(Lz), int(n2max), int(n_nodes),
+                                          mp, _stream(stream), ctypes.byref(h)),
+               "pwc_table_create_box")
+        return cls(None, 0, _handle=h)
 
     @classmethod
     def load(cls, path, stream=None):
@@ -221,9 +238,10 @@ class Table:
         return beta, W
 
     def copy_tables(self, out=None, stream=None):
-        """FP64 tables as a device tensor [Q, nd, nd]."""
+        """FP64 tables as a device tensor [Q, nd, nd] (a cube) or [3, Q, nd, nd] (a box)."""
         if out is None:
-            out = torch.empty((self.Q, self.nd, self.nd), dtype=torch.float64, device="cuda")
+            shape = (self.Q, self.nd, self.nd) if self.ndir == 1 else (3, self.Q, self.nd, self.nd)
+            out = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(lib().pwc_table_copy(self.handle, _dev_ptr(out, torch.float64, "out"),
                                     _stream(stream)), "pwc_table_copy")
         return out

@@ -103,7 +103,7 @@ void free_table(Table &t) {
 // Carve the table's single device allocation.  With base == nullptr only the
 // size is computed (used for admission before anything is allocated).
 size_t carve(Table &t, size_t n_reps, char *base) {
-    const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E;
+    const int Q = t.Q, K = t.K, nd = t.nd, E = t.fl.E, D = t.ndir;
     const size_t Qp = static_cast<size_t>(t.fl.Qp);
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     size_t off = 0;
@@ -111,16 +111,16 @@ size_t carve(Table &t, size_t n_reps, char *base) {
     const size_t o_basis = take(sizeof(int32_t) * t.N);
     const size_t o_fold = take(sizeof(int32_t) * nd * nd);
     const size_t o_reps = take(sizeof(int32_t) * n_reps);
-    const size_t o_beta = take(sizeof(double) * Q);
+    const size_t o_beta = take(sizeof(double) * D * Q);
     const size_t o_W = take(sizeof(double) * Q);
     const size_t o_gl = take(sizeof(double) * 2 * kGlPanelPoints);
-    const size_t o_prim = take(sizeof(double) * Q * 2 * (K + 1));
-    const size_t o_tau = take(sizeof(double) * Q * nd * nd);
+    const size_t o_prim = take(sizeof(double) * D * Q * 2 * (K + 1));
+    const size_t o_tau = take(sizeof(double) * D * Q * nd * nd);
     const size_t o_tauF = take(sizeof(double) * Qp * E);
     const size_t o_tauHL = take(sizeof(float2) * Qp * E);
     const size_t o_Wcbrt = take(sizeof(double) * Q);
-    const size_t o_diag = take(sizeof(double) * Qd * (K + 1));
-    const size_t o_diagHL = take(sizeof(float2) * Qd * (K + 1));
+    const size_t o_diag = take(sizeof(double) * Qd * D * (K + 1));
+    const size_t o_diagHL = take(sizeof(float2) * Qd * D * (K + 1));
     const size_t o_Wdiag = take(sizeof(double) * Qd);
     const size_t o_WdiagHL = take(sizeof(float2) * Qd);
     const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
@@ -149,9 +149,21 @@ size_t carve(Table &t, size_t n_reps, char *base) {
     return off;
 }
 
-pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su) {
-    if (!(L > 0.0) || !std::isfinite(L) || n2max < 1 || n2max > PWC_MAX_N2MAX) return PWC_ERR_ARG;
-    t.L = L;
+pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table &t, TableSetup &su) {
+    for (int d = 0; d < 3; ++d)
+        if (!(sides[d] > 0.0) || !std::isfinite(sides[d])) return PWC_ERR_ARG;
+    if (n2max < 1 || n2max > PWC_MAX_N2MAX) return PWC_ERR_ARG;
+    const bool cube = sides[0] == sides[1] && sides[1] == sides[2];
+    t.ndir = cube ? 1 : 3;
+    // Reference length: the side of a cube; the geometric mean of a box's sides,
+    // which makes rho_x rho_y rho_z = 1 and keeps the cube's prefactor.
+    t.L = cube ? sides[0]
+               : static_cast<double>(std::cbrt(static_cast<long double>(sides[0]) * sides[1] * sides[2]));
+    for (int d = 0; d < 3; ++d) {
+        t.Ld[d] = sides[d];
+        t.rho[d] = cube ? 1.0 : sides[d] / t.L;
+    }
+    const double L = t.L;
     t.n2max = n2max;
     t.nmax = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
     t.K = 2 * t.nmax;
@@ -162,7 +174,8 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
     if (!build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) return PWC_ERR_ARG;
     t.Q = static_cast<int>(t.h_beta.size());
     build_fold(t.K, su.fold, su.reps);
-    t.fl.E = static_cast<int>(su.reps.size() / 2);
+    t.E1 = static_cast<int>(su.reps.size() / 2);
+    t.fl.E = t.ndir * t.E1;                 // slab rows: the direction tables stacked
     (void)hipGetDevice(&t.device);
     if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
         t.n_cu <= 0)
@@ -170,10 +183,12 @@ pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSet
     t.flm.E = t.fl.E;
     t.direct_max = kDirectDefault;
     if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, t.flm) ||
-        !plan_chunks(t.Q, static_cast<size_t>(t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
+        !plan_chunks(t.Q, static_cast<size_t>(t.ndir) * (t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
-    // Exchange kernel table K(a <= b <= c) when it fits in one workgroup's LDS.
-    const int64_t kt_n = static_cast<int64_t>(t.K + 1) * (t.K + 2) * (t.K + 3) / 6;
+    // Exchange kernel table when it fits in one workgroup's LDS: K(a <= b <= c)
+    // for a cube (the three directions share one table), K(a, b, c) for a box.
+    const int64_t n1 = t.K + 1;
+    const int64_t kt_n = cube ? n1 * (n1 + 1) * (n1 + 2) / 6 : n1 * n1 * n1;
     t.kt_n = (kt_n * 8 <= kLdsMax - 4096) ? static_cast<int>(kt_n) : 0;
     t.bytes = carve(t, su.reps.size(), nullptr);
     return PWC_OK;
@@ -225,13 +240,16 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
     up(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
     up(t.d_fold, su.fold.data(), sizeof(int32_t) * su.fold.size());
     up(t.d_reps, su.reps.data(), sizeof(int32_t) * su.reps.size());
-    up(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
+    std::vector<double> beta_d(static_cast<size_t>(t.ndir) * Q);   // node of each direction
+    for (int d = 0; d < t.ndir; ++d)
+        for (int q = 0; q < Q; ++q) beta_d[static_cast<size_t>(d) * Q + q] = t.h_beta[q] / (t.rho[d] * t.rho[d]);
+    up(t.d_beta, beta_d.data(), sizeof(double) * beta_d.size());
     up(t.d_W, t.h_W.data(), sizeof(double) * Q);
     up(t.d_gl, gl.data(), sizeof(double) * gl.size());
     up(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
     up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
     up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
-    if (h_tau) up(t.d_tau, h_tau, sizeof(double) * static_cast<size_t>(Q) * t.nd * t.nd);
+    if (h_tau) up(t.d_tau, h_tau, sizeof(double) * static_cast<size_t>(t.ndir) * Q * t.nd * t.nd);
     if (st == PWC_OK) st = from_hip(launch_table_build(t, s, h_tau != nullptr));
     if (st == PWC_OK) st = from_hip(launch_ktab_build(t, s));
     // The host staging vectors die with this frame: wait for the stream.
@@ -279,6 +297,11 @@ pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes) {
 
 pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *mesh, void *stream,
                             pwc_table **out) {
+    return pwc_table_create_box(L, L, L, n2max, n_nodes, mesh, stream, out);
+}
+
+pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int n_nodes,
+                                const pwc_mesh *mesh, void *stream, pwc_table **out) {
     if (!out) return PWC_ERR_ARG;
     *out = nullptr;
     pwc_mesh m{};
@@ -293,7 +316,8 @@ pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *me
     pwc_table *h = new (std::nothrow) pwc_table;
     if (!h) return PWC_ERR_NOMEM;
     pwc::TableSetup su;
-    pwc_status st = pwc::plan_table(L, n2max, m, h->t, su);
+    const double sides[3] = {Lx, Ly, Lz};
+    pwc_status st = pwc::plan_table(sides, n2max, m, h->t, su);
     if (st == PWC_OK) st = pwc::build_table(h->t, su, static_cast<hipStream_t>(stream));
     if (st != PWC_OK) {
         delete h;
@@ -313,10 +337,10 @@ constexpr uint32_t kTableVersion = 1;
 struct TableFileHeader {
     char magic[8];
     uint32_t version, header_bytes;
-    double L;
+    double Lx, Ly, Lz;
     int32_t n2max, Q, nd, mesh_kind;
     int64_t N;
-    int32_t n_sub, q_sub, q_tail, pad;
+    int32_t n_sub, q_sub, q_tail, ndir;
     double ratio, alpha_c;
     uint64_t payload_bytes, checksum;
 };
@@ -335,7 +359,7 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) 
 pwc_status pwc_table_save(const pwc_table *t, const char *path) {
     if (!t || !path) return PWC_ERR_ARG;
     const pwc::Table &tb = t->t;
-    const size_t ntau = static_cast<size_t>(tb.Q) * tb.nd * tb.nd;
+    const size_t ntau = static_cast<size_t>(tb.ndir) * tb.Q * tb.nd * tb.nd;
     std::vector<double> payload(2 * static_cast<size_t>(tb.Q) + ntau);
     std::memcpy(payload.data(), tb.h_beta.data(), sizeof(double) * tb.Q);
     std::memcpy(payload.data() + tb.Q, tb.h_W.data(), sizeof(double) * tb.Q);
@@ -346,7 +370,10 @@ pwc_status pwc_table_save(const pwc_table *t, const char *path) {
     std::memcpy(h.magic, kTableMagic, sizeof(h.magic));
     h.version = kTableVersion;
     h.header_bytes = sizeof(h);
-    h.L = tb.L;
+    h.Lx = tb.Ld[0];
+    h.Ly = tb.Ld[1];
+    h.Lz = tb.Ld[2];
+    h.ndir = tb.ndir;
     h.n2max = tb.n2max;
     h.Q = tb.Q;
     h.nd = tb.nd;
@@ -377,8 +404,9 @@ pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
     bool ok = std::fread(&h, sizeof(h), 1, f) == 1 &&
               std::memcmp(h.magic, kTableMagic, sizeof(h.magic)) == 0 &&
               h.version == kTableVersion && h.header_bytes == sizeof(h) && h.Q > 0 && h.nd > 0 &&
+              (h.ndir == 1 || h.ndir == 3) &&
               h.payload_bytes == sizeof(double) * (2 * static_cast<uint64_t>(h.Q) +
-                                                   static_cast<uint64_t>(h.Q) * h.nd * h.nd);
+                                                   static_cast<uint64_t>(h.ndir) * h.Q * h.nd * h.nd);
     std::vector<double> payload;
     if (ok) {
         payload.resize(h.payload_bytes / sizeof(double));
@@ -399,8 +427,10 @@ pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
     pwc_table *t = new (std::nothrow) pwc_table;
     if (!t) return PWC_ERR_NOMEM;
     pwc::TableSetup su;
-    pwc_status st = pwc::plan_table(h.L, h.n2max, m, t->t, su);
-    if (st == PWC_OK && (t->t.Q != h.Q || t->t.nd != h.nd || t->t.N != h.N)) st = PWC_ERR_IO;
+    const double sides[3] = {h.Lx, h.Ly, h.Lz};
+    pwc_status st = pwc::plan_table(sides, h.n2max, m, t->t, su);
+    if (st == PWC_OK && (t->t.Q != h.Q || t->t.nd != h.nd || t->t.N != h.N || t->t.ndir != h.ndir))
+        st = PWC_ERR_IO;
     if (st == PWC_OK) {
         // The stored mesh is the table's mesh.
         t->t.h_beta.assign(payload.begin(), payload.begin() + h.Q);
@@ -469,6 +499,12 @@ pwc_status pwc_table_params(const pwc_table *t, double *L, int *n2max, pwc_mesh 
     return PWC_OK;
 }
 
+pwc_status pwc_table_box(const pwc_table *t, double *sides) {
+    if (!t || !sides) return PWC_ERR_ARG;
+    for (int d = 0; d < 3; ++d) sides[d] = t->t.Ld[d];
+    return PWC_OK;
+}
+
 pwc_status pwc_basis(const pwc_table *t, int32_t *h_n) {
     if (!t || !h_n) return PWC_ERR_ARG;
     std::memcpy(h_n, t->t.h_basis.data(), sizeof(int32_t) * t->t.h_basis.size());
@@ -484,7 +520,7 @@ pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_W) {
 
 pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
     if (!t || !d_dst) return PWC_ERR_ARG;
-    const size_t bytes = sizeof(double) * t->t.Q * t->t.nd * t->t.nd;
+    const size_t bytes = sizeof(double) * t->t.ndir * t->t.Q * t->t.nd * t->t.nd;
     return from_hip(hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice,
                                    static_cast<hipStream_t>(stream)));
 }

@@ -57,9 +57,10 @@ __global__ __launch_bounds__(kDirectThreads) void k_rec_direct(DirectBatch b) {
     }
     const int ni = J.basis[v.x], nj = J.basis[v.y], nk = J.basis[v.z], nl = J.basis[v.w];
     const int K = J.K, nd = J.nd;
+    // A box stacks its direction tables: y at rows E1.., z at rows 2 E1...
     const int f0 = J.fold[(sx(nk) - sx(ni) + K) * nd + (sx(nl) - sx(nj) + K)];
-    const int f1 = J.fold[(sy(nk) - sy(ni) + K) * nd + (sy(nl) - sy(nj) + K)];
-    const int f2 = J.fold[(sz(nk) - sz(ni) + K) * nd + (sz(nl) - sz(nj) + K)];
+    const int f1 = J.fold[(sy(nk) - sy(ni) + K) * nd + (sy(nl) - sy(nj) + K)] + J.ystride;
+    const int f2 = J.fold[(sz(nk) - sz(ni) + K) * nd + (sz(nl) - sz(nj) + K)] + 2 * J.ystride;
     const int words = (J.Q + 1) / 2;            // node pairs; entries past Q are zero
     const size_t row = static_cast<size_t>(J.Qp / 2);
     double r;
@@ -112,6 +113,7 @@ DirectJob direct_job(const Table &t, const int32_t *d_quads, int64_t n, double *
     j.nd = t.nd;
     j.Qp = t.fl.Qp;
     j.Q = t.Q;
+    j.ystride = t.ndir == 3 ? t.E1 : 0;
     return j;
 }
 

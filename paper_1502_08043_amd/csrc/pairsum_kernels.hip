@@ -3,7 +3,8 @@
 // For planewaves <ij|ji> depends on Delta = n_j - n_i only through the
 // diagonal entries tau_q(Delta_d, -Delta_d), which are even in Delta_d, so the
 // exchange kernel K(Delta) = sum_q W_q D_q(|Dx|) D_q(|Dy|) D_q(|Dz|) reads a
-// (K+1) x Q table that fits in LDS.  <ij|ij> has m = m' = 0 in every
+// (K+1) x Q table that fits in LDS (three of them for a box, one per
+// direction).  <ij|ij> has m = m' = 0 in every
 // direction and equals the single integral <00|00> for every pair; its pair
 // sum is carried as sum f_i f_j and multiplied by <00|00> at the end.
 //
@@ -33,9 +34,10 @@ struct PairArgs {
     int M;
     const int32_t *basis;
     int N;
-    const void *diag;   // [nchunk][K+1][dc] double or float2
+    const void *diag;   // [nchunk][ndir][K+1][dc] double or float2
     const void *w;      // [nchunk * dc]     double or float2
     int K, dc, nchunk, nT;
+    int ndir;           // 3 for a box (one diagonal table per direction), else 1
     double *partial;    // [nT * nT][2]
     int *err;           // table error word
 };
@@ -73,9 +75,10 @@ __device__ __forceinline__ bool pair_setup(const PairArgs &a, int ti, int tj, in
         return false;
     }
     const int vi = a.basis[oi], vj = a.basis[oj];
+    const int dstride = a.ndir == 3 ? (a.K + 1) * a.dc : 0;   // a box: per-direction tables
     ax = iabs(bx(vj) - bx(vi)) * a.dc;
-    ay = iabs(by(vj) - by(vi)) * a.dc;
-    az = iabs(bz(vj) - bz(vi)) * a.dc;
+    ay = iabs(by(vj) - by(vi)) * a.dc + dstride;
+    az = iabs(bz(vj) - bz(vi)) * a.dc + 2 * dstride;
     const double fi = a.f ? a.f[i] : 1.0, fj = a.f ? a.f[j] : 1.0;
     wf = (i == j ? 1.0 : 2.0) * fi * fj;
     return true;
@@ -83,7 +86,7 @@ __device__ __forceinline__ bool pair_setup(const PairArgs &a, int ti, int tj, in
 
 template <typename T>
 __device__ __forceinline__ void stage_diag(const PairArgs &a, int ch, T *ld, T *lw) {
-    const int n = (a.K + 1) * a.dc;
+    const int n = a.ndir * (a.K + 1) * a.dc;
     const T *src = static_cast<const T *>(a.diag) + static_cast<size_t>(ch) * n;
     for (int i = threadIdx.x; i < n; i += kThreads) ld[i] = src[i];
     const T *ws = static_cast<const T *>(a.w) + static_cast<size_t>(ch) * a.dc;
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_f64(PairArgs a) {
     extern __shared__ uint4 lds_raw[];
     __shared__ double red[kThreads / 64];
     double *ld = reinterpret_cast<double *>(lds_raw);
-    double *lw = ld + (a.K + 1) * a.dc;
+    double *lw = ld + a.ndir * (a.K + 1) * a.dc;
     const int ti = blockIdx.y, tj = blockIdx.x;
     const int bid = ti * a.nT + tj;
     if (ti > tj) {   // whole workgroup leaves together
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(PairArgs a) {
     extern __shared__ uint4 lds_raw[];
     __shared__ double red[kThreads / 64];
     float2 *ld = reinterpret_cast<float2 *>(lds_raw);
-    float2 *lw = ld + (a.K + 1) * a.dc;
+    float2 *lw = ld + a.ndir * (a.K + 1) * a.dc;
     const int ti = blockIdx.y, tj = blockIdx.x;
     const int bid = ti * a.nT + tj;
     if (ti > tj) {
@@ -201,13 +204,13 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(PairArgs a) {
 
 // Fixed-order FP64 sum of the workgroup partials, then the energies:
 // E_x = -1/2 pref S_x, E_H = 1/2 pref <00|00>_raw S_h, with
-// <00|00>_raw = sum_q W_q tau_q(0,0)^3 read from c0 when given, else summed
-// here from the FP64 diagonal table.
+// <00|00>_raw = sum_q W_q tau^x_q(0,0) tau^y_q(0,0) tau^z_q(0,0) read from c0
+// when given, else summed here from the FP64 diagonal tables.
 __global__ __launch_bounds__(kThreads) void k_pair_final(const double *__restrict__ partial,
                                                         int nblk, const double *__restrict__ c0p,
                                                         const double *__restrict__ diag,
                                                         const double *__restrict__ wd, int K,
-                                                        int dc, int nchunk, double pref,
+                                                        int dc, int nchunk, int ndir, double pref,
                                                         double *__restrict__ out) {
     __shared__ double red[kThreads / 64];
     double sx = 0.0, sh = 0.0;
@@ -224,8 +227,10 @@ __global__ __launch_bounds__(kThreads) void k_pair_final(const double *__restric
         } else {
             for (int ch = 0; ch < nchunk; ++ch)
                 for (int q = 0; q < dc; ++q) {
-                    const double d0 = diag[(static_cast<size_t>(ch) * (K + 1)) * dc + q];
-                    c0 = fma(d0 * d0 * d0, wd[ch * dc + q], c0);
+                    const size_t base = static_cast<size_t>(ch) * ndir * (K + 1) * dc + q;
+                    const size_t step = ndir == 3 ? static_cast<size_t>(K + 1) * dc : 0;
+                    const double dx = diag[base], dy = diag[base + step], dz = diag[base + 2 * step];
+                    c0 = fma(dx * dy * dz, wd[ch * dc + q], c0);
                 }
         }
         out[0] = 0.5 * pref * c0 * sh;
@@ -245,34 +250,39 @@ __device__ __forceinline__ int ktab_index(int a, int b, int c) {
     return c * (c + 1) * (c + 2) / 6 + b * (b + 1) / 2 + a;
 }
 
-// One thread per (a, b, c) of the cube; sorted triples write their sum.
+// One thread per (a, b, c) of the cube.  A cube's directions share one
+// diagonal table, so only sorted triples are kept (a = the x entry); a box
+// keeps every triple, a from the x table, b from y and c from z, at
+// (a (K+1) + b) (K+1) + c.
 __global__ __launch_bounds__(kThreads) void k_ktab_build(const double *__restrict__ diag,
                                                         const float2 *__restrict__ diagHL,
                                                         const double *__restrict__ wd,
                                                         const float2 *__restrict__ wdHL, int K,
-                                                        int dc, int nchunk,
+                                                        int dc, int nchunk, int ndir,
                                                         double *__restrict__ k64,
                                                         double *__restrict__ kmx) {
     const int n1 = K + 1;
     const int id = blockIdx.x * kThreads + threadIdx.x;
     if (id >= n1 * n1 * n1) return;
     const int c = id / (n1 * n1), b = (id / n1) % n1, a = id % n1;
-    if (a > b || b > c) return;
+    const bool box = ndir == 3;
+    if (!box && (a > b || b > c)) return;
+    const int ry = box ? n1 : 0, rz = box ? 2 * n1 : 0;   // direction rows in a chunk
     double s64 = 0.0;
     float sh = 0.0f, sl = 0.0f;
     for (int ch = 0; ch < nchunk; ++ch) {
-        const size_t row = static_cast<size_t>(ch) * n1;
+        const size_t row = static_cast<size_t>(ch) * ndir * n1;
         for (int q = 0; q < dc; ++q) {
-            const double da = diag[(row + a) * dc + q], db = diag[(row + b) * dc + q];
-            const double dcv = diag[(row + c) * dc + q];
+            const double da = diag[(row + a) * dc + q], db = diag[(row + ry + b) * dc + q];
+            const double dcv = diag[(row + rz + c) * dc + q];
             s64 = fma(da * db * dcv, wd[ch * dc + q], s64);
-            const float2 ha = diagHL[(row + a) * dc + q], hb = diagHL[(row + b) * dc + q];
-            const float2 hc = diagHL[(row + c) * dc + q], hw = wdHL[ch * dc + q];
+            const float2 ha = diagHL[(row + a) * dc + q], hb = diagHL[(row + ry + b) * dc + q];
+            const float2 hc = diagHL[(row + rz + c) * dc + q], hw = wdHL[ch * dc + q];
             ff_acc(sh, sl, ff_mul(ff_mul(ff_mul(ff{ha.x, ha.y}, ff{hb.x, hb.y}), ff{hc.x, hc.y}),
                                   ff{hw.x, hw.y}));
         }
     }
-    const int idx = ktab_index(a, b, c);
+    const int idx = box ? (a * n1 + b) * n1 + c : ktab_index(a, b, c);
     k64[idx] = s64;
     kmx[idx] = ff_to_double(sh, sl);
 }
@@ -289,6 +299,8 @@ struct KtArgs {
     const double *ktab;
     int kt_n;
     int nT;
+    int box;           // unsorted (K+1)^3 table of a box
+    int n1;            // K + 1
     double *partial;   // [gridDim.x][2]
     int *err;
 };
@@ -347,9 +359,15 @@ __global__ __launch_bounds__(kThreads) void k_pair_ktab(KtArgs a) {
             dx = dx < 0 ? -dx : dx;
             dy = dy < 0 ? -dy : dy;
             dz = dz < 0 ? -dz : dz;
-            sort3(dx, dy, dz);
+            int kidx;
+            if (a.box) {
+                kidx = (dx * a.n1 + dy) * a.n1 + dz;
+            } else {
+                sort3(dx, dy, dz);
+                kidx = ktab_index(dx, dy, dz);
+            }
             const double wf = (i < j ? 2.0 : (i == j ? 1.0 : 0.0)) * fi_s[il] * fj;
-            sx = fma(wf, lk[ktab_index(dx, dy, dz)], sx);
+            sx = fma(wf, lk[kidx], sx);
             sh += wf;
         }
     }
@@ -378,7 +396,8 @@ hipError_t launch_ktab_build(Table &t, hipStream_t s) {
     const int n1 = t.K + 1;
     const int blocks = (n1 * n1 * n1 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_ktab_build, dim3(blocks), dim3(kThreads), 0, s, t.d_diag, t.d_diagHL,
-                       t.d_Wdiag, t.d_WdiagHL, t.K, t.dl.c, t.dl.nchunk, t.d_ktab64, t.d_ktabMX);
+                       t.d_Wdiag, t.d_WdiagHL, t.K, t.dl.c, t.dl.nchunk, t.ndir, t.d_ktab64,
+                       t.d_ktabMX);
     return hipGetLastError();
 }
 
@@ -399,6 +418,8 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         a.N = static_cast<int>(t.N);
         a.ktab = (p == PWC_MIXED) ? t.d_ktabMX : t.d_ktab64;
         a.kt_n = t.kt_n;
+        a.box = t.ndir == 3;
+        a.n1 = t.K + 1;
         a.nT = static_cast<int>((M + kKtTile - 1) / kKtTile);
         a.err = t.d_err;
         const size_t lds = sizeof(double) * static_cast<size_t>(t.kt_n);
@@ -413,7 +434,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         hipLaunchKernelGGL(k_pair_ktab, dim3(grid), dim3(kThreads), lds, s, a);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, grid, a.ktab,
-                           t.d_diag, t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, pref, d_out);
+                           t.d_diag, t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, t.ndir, pref, d_out);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         return hipFreeAsync(partial, s);
     }
@@ -427,6 +448,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     a.K = t.K;
     a.dc = t.dl.c;
     a.nchunk = t.dl.nchunk;
+    a.ndir = t.ndir;
     a.nT = static_cast<int>((M + kTile - 1) / kTile);
     a.err = t.d_err;
     const int nblk = a.nT * a.nT;
@@ -435,7 +457,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
                          sizeof(double) * 2 * static_cast<size_t>(nblk), s);
     if (err != hipSuccess) return err;
     a.partial = partial;
-    const size_t lds = (static_cast<size_t>(a.K + 1) * a.dc + a.dc) * 8;
+    const size_t lds = (static_cast<size_t>(a.ndir) * (a.K + 1) * a.dc + a.dc) * 8;
     const dim3 grid(a.nT, a.nT);
     if (p == PWC_MIXED) {
         a.diag = t.d_diagHL;
@@ -451,7 +473,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, nblk,
                        static_cast<const double *>(nullptr), t.d_diag, t.d_Wdiag, t.K, t.dl.c,
-                       t.dl.nchunk, pref, d_out);
+                       t.dl.nchunk, t.ndir, pref, d_out);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return hipFreeAsync(partial, s);
 }

@@ -61,7 +61,14 @@ struct DiagLayout {
 };
 
 struct Table {
+    // Box sides (a cube has three equal sides).  L is the reference length:
+    // the side of a cube, (Lx Ly Lz)^(1/3) for a box; direction d of a box
+    // uses the node beta / rho_d^2, rho_d = L_d / L, and its own tables.
     double L = 0.0;
+    double Ld[3] = {0.0, 0.0, 0.0};
+    double rho[3] = {1.0, 1.0, 1.0};
+    int ndir = 1;                   // direction tables: 1 (cube) or 3 (box)
+    int E1 = 0;                     // folded entries per direction and node
     int n2max = 0, nmax = 0, K = 0, nd = 0, Q = 0;
     int64_t N = 0;
     int n_interval1 = 0;
@@ -80,21 +87,22 @@ struct Table {
     int32_t *d_basis = nullptr;     // [N] packed (x, y, z) as int8 lanes of an int32
     int32_t *d_fold = nullptr;      // [nd * nd]
     int32_t *d_reps = nullptr;      // [E][2]
-    double *d_beta = nullptr;       // [Q]
+    double *d_beta = nullptr;       // [ndir][Q] node of each direction
     double *d_W = nullptr;          // [Q]
     double *d_gl = nullptr;         // [2][kGlPanelPoints] panel rule on [0, 1]
-    double *d_prim = nullptr;       // [Q][2][K + 1]  (S, D)
-    double *d_tau = nullptr;        // [Q][nd][nd]
-    double *d_tauF = nullptr;       // [E][Qp]  folded W_q^(1/3) tau_q, FP64
-    float2 *d_tauHL = nullptr;      // [E][Qp]  same, (hi, lo)
+    double *d_prim = nullptr;       // [ndir][Q][2][K + 1]  (S, D)
+    double *d_tau = nullptr;        // [ndir][Q][nd][nd]
+    double *d_tauF = nullptr;       // [ndir * E1][Qp]  folded W_q^(1/3) tau_q, FP64
+    float2 *d_tauHL = nullptr;      // [ndir * E1][Qp]  same, (hi, lo)
     double *d_Wcbrt = nullptr;      // [Q]      W_q^(1/3)
-    double *d_diag = nullptr;       // [dl.nchunk][K + 1][dl.c]  tau_q(m, -m), m >= 0
+    double *d_diag = nullptr;       // [dl.nchunk][ndir][K + 1][dl.c]  tau_q(m, -m), m >= 0
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
     double *d_Wdiag = nullptr;      // [dl.nchunk * dl.c]
     float2 *d_WdiagHL = nullptr;
     int64_t direct_max = 0;         // pwc_reconstruct takes the direct kernel for n <= this
-    int kt_n = 0;                   // exchange kernel table size C(K+3, 3), 0 if not kept
-    double *d_ktab64 = nullptr;     // [kt_n] K(a<=b<=c), FP64 node sums
+    int kt_n = 0;                   // exchange kernel table size: C(K+3, 3) for a cube
+                                    // (a <= b <= c), (K+1)^3 for a box; 0 if not kept
+    double *d_ktab64 = nullptr;     // [kt_n] K(a, b, c), FP64 node sums
     double *d_ktabMX = nullptr;     // [kt_n] same, split-FP32 node sums
     int *d_err = nullptr;           // kernel error word
 };
@@ -106,7 +114,7 @@ struct TableSetup {
     std::vector<int32_t> fold, reps;
 };
 bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl);
-pwc_status plan_table(double L, int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
+pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
 // h_tau: the FP64 tables [Q][nd][nd] of a loaded table (the 1-D integrals are
 // then not recomputed), or nullptr.
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau = nullptr);
@@ -134,6 +142,7 @@ struct DirectJob {
     int *err;                 // error word of this job
     double pref;
     int N, K, nd, Qp, Q, mixed;
+    int ystride;              // rows between direction tables (E1 for a box, 0 for a cube)
     uint32_t block0;          // first block of the job (set by launch_direct)
 };
 constexpr int kDirectMaxJobs = 24;

@@ -4,7 +4,9 @@
 //
 // Layout.  tau is symmetric under (m, m') -> (m', m) and (m, m') -> (-m, -m'),
 // so the table is stored folded: E orbit representatives per node (about a
-// quarter of nd^2).  In HBM the folded table is [E][Qp]: the Qp (Q padded to
+// quarter of nd^2).  A rectangular box stacks its three direction tables
+// (E = 3 E1 rows, direction d at rows d E1 ..), and the decode offsets each
+// direction's entry into its own table; the passes see one taller slab.  In HBM the folded table is [E][Qp]: the Qp (Q padded to
 // a multiple of 32, zero) node values of one entry are contiguous.  Each entry
 // carries W_q^(1/3) (the mesh weights are positive), so a node term is the
 // plain product of three entries.
@@ -75,6 +77,7 @@ struct PassArgs {
     int64_t n;
     int64_t n_pad;     // n rounded up to kStreamPad: the decoded stream's length
     int ord_g;         // lanes per quadruple of the passes the decode orders entries for
+    int E1, ndir;      // entries per direction; 3 direction tables for a box, else 1
     const int32_t *basis;
     int N;
     const int32_t *fold;
@@ -270,11 +273,16 @@ __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const in
     int fx = lfold ? lfold[ix] : gfold[ix];
     int fy = lfold ? lfold[iy] : gfold[iy];
     int fz = lfold ? lfold[iz] : gfold[iz];
-    order_by_parity(fx, fy, fz);
-    if (descending_at(e, a.ord_g)) {
-        const int t = fx;
-        fx = fz;
-        fz = t;
+    if (a.ndir == 3) {       // a box: each direction reads its own table's rows
+        fy += a.E1;
+        fz += 2 * a.E1;
+    } else {                 // a cube: the three entries are interchangeable
+        order_by_parity(fx, fy, fz);
+        if (descending_at(e, a.ord_g)) {
+            const int t = fx;
+            fx = fz;
+            fz = t;
+        }
     }
     return PK::pack(fx, fy, fz);
 }
@@ -584,6 +592,8 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.K = t.K;
     a.nd = t.nd;
     a.E = t.fl.E;
+    a.E1 = t.E1;
+    a.ndir = t.ndir;
     a.Qp = t.fl.Qp;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.ord_g = (p == PWC_MIXED ? t.flm : t.fl).G;

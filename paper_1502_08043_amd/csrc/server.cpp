@@ -252,7 +252,8 @@ bool pwc_server::admit() {
                 if (planned) pwc_table_destroy(planned);
                 planned = new (std::nothrow) pwc_table;
                 planned_key = key;
-                st = planned ? pwc::plan_table(p.r.L, p.r.n2max, p.mesh, planned->t, planned_su)
+                const double sides[3] = {p.r.L, p.r.L, p.r.L};   // the server serves cubes
+                st = planned ? pwc::plan_table(sides, p.r.n2max, p.mesh, planned->t, planned_su)
                              : PWC_ERR_NOMEM;
             }
             if (st == PWC_OK && planned->t.bytes + scratch > budget) st = PWC_ERR_NOMEM;

@@ -1,6 +1,7 @@
 // Table construction on the GPU (FP64): the 1-D integrals of Eq. 8 for
 // planewave factors at every quadrature node, and the layouts the hot
-// kernels read.
+// kernels read.  A rectangular box has one table per direction, built at
+// that direction's node beta_q / rho_d^2 (see pwc_table_create_box).
 //
 // For one direction, with m = n_k - n_i, m' = n_l - n_j and s = m + m',
 //   tau_q(m, m') = 2 beta^{-1/2} D(m)                          if s = 0,
@@ -34,11 +35,12 @@ __device__ inline void sincos_2pi_mu(int m, double u, double *s, double *c) {
     *c = fma(-pda, sa, ca);
 }
 
+// Grid (K + 1, Q, ndir): direction d of a box has its own node beta[d][q].
 __global__ __launch_bounds__(kThreads) void k_prim(const double *__restrict__ beta,
                                                   const double *__restrict__ gl, int K,
                                                   double *__restrict__ prim) {
     const int m = blockIdx.x;
-    const int q = blockIdx.y;
+    const int q = blockIdx.y + blockIdx.z * gridDim.y;   // (direction, node) flat
     const double b = beta[q];
     const double up = fmin(1.0, 8.0 * sqrt(b));
     const double h = up / kGlPanels;
@@ -78,12 +80,12 @@ __device__ inline float2 split_hilo(double v) {
 }
 
 struct AsmArgs {
-    const double *beta;
-    const double *wcbrt;
-    const double *prim;
+    const double *beta;     // [ndir][Q]
+    const double *wcbrt;    // [Q]
+    const double *prim;     // [ndir][Q][2][K + 1]
     const int32_t *fold;
     const int32_t *reps;
-    int K, nd, E, Qp, dc;
+    int K, nd, E1, Qp, dc, Q, ndir;
     int from_tau;      // 1: tau is given (a loaded table), derive the layouts only
     double *tau;
     double *tauF;
@@ -92,21 +94,23 @@ struct AsmArgs {
     float2 *diagHL;
 };
 
+// Grid (nd^2 / kThreads, Q, ndir).
 __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
     const int e = blockIdx.x * kThreads + threadIdx.x;
-    const int q = blockIdx.y;
+    const int q = blockIdx.y, d = blockIdx.z;
+    const int dq = d * a.Q + q;                          // (direction, node) flat
     if (e >= a.nd * a.nd) return;
     const int row = e / a.nd, col = e % a.nd;
     const int m = row - a.K, mp = col - a.K;
     const int s = m + mp;
-    const size_t ti = (static_cast<size_t>(q) * a.nd + row) * a.nd + col;
+    const size_t ti = (static_cast<size_t>(dq) * a.nd + row) * a.nd + col;
     double v;
     if (a.from_tau) {
         v = a.tau[ti];
     } else {
-        const double *S = a.prim + static_cast<size_t>(q) * 2 * (a.K + 1);
+        const double *S = a.prim + static_cast<size_t>(dq) * 2 * (a.K + 1);
         const double *D = S + (a.K + 1);
-        const double rb = sqrt(a.beta[q]);
+        const double rb = sqrt(a.beta[dq]);
         if (s == 0) {
             v = 2.0 / rb * D[m < 0 ? -m : m];
         } else {
@@ -121,14 +125,14 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
     // three folded entries.
     const int f = a.fold[e];
     if (a.reps[2 * f] == m && a.reps[2 * f + 1] == mp) {
-        const size_t idx = static_cast<size_t>(f) * a.Qp + q;
+        const size_t idx = static_cast<size_t>(d * a.E1 + f) * a.Qp + q;   // direction d's rows
         const double vw = v * a.wcbrt[q];
         a.tauF[idx] = vw;
         a.tauHL[idx] = split_hilo(vw);
     }
     // Diagonal tau(m, -m) for m >= 0 (the exchange entries; even in m).
     if (s == 0 && m >= 0) {
-        const size_t idx = (static_cast<size_t>(q / a.dc) * (a.K + 1) + m) * a.dc + (q % a.dc);
+        const size_t idx = ((static_cast<size_t>(q / a.dc) * a.ndir + d) * (a.K + 1) + m) * a.dc + (q % a.dc);
         a.diag[idx] = v;
         a.diagHL[idx] = split_hilo(v);
     }
@@ -138,14 +142,14 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
 
 hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau) {
     if (!from_tau) {
-        dim3 gp(t.K + 1, t.Q);
+        dim3 gp(t.K + 1, t.Q, t.ndir);
         hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    AsmArgs a{t.d_beta, t.d_Wcbrt, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.fl.E, t.fl.Qp, t.dl.c,
-              from_tau ? 1 : 0, t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
-    dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q);
+    AsmArgs a{t.d_beta, t.d_Wcbrt, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.E1, t.fl.Qp, t.dl.c,
+              t.Q, t.ndir, from_tau ? 1 : 0, t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
+    dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q, t.ndir);
     hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
