@@ -341,7 +341,7 @@ typedef enum { PWC_REQ_RECONSTRUCT = 0, PWC_REQ_ENERGIES = 1 } pwc_request_kind;
 
 typedef struct {
     int kind;             /* pwc_request_kind */
-    double L;             /* box side */
+    double L;             /* box side (along x for a rectangular box) */
     int n2max;            /* basis cutoff */
     int n_nodes;          /* default mesh for this node count, used if !has_mesh */
     int has_mesh;
@@ -358,6 +358,9 @@ typedef struct {
                              the device.  It must stay valid until the result is
                              collected.  With NULL the buffers must already be
                              idle when the request is submitted. */
+    double Ly, Lz;        /* box sides along y and z for a rectangular box
+                             (pwc_table_create_box, with L along x); 0 and 0
+                             for a cube of side L */
 } pwc_request;
 
 typedef struct {

@@ -314,7 +314,7 @@ class Request(ctypes.Structure):
                 ("n_nodes", ctypes.c_int), ("has_mesh", ctypes.c_int), ("mesh", Mesh),
                 ("prec", ctypes.c_int), ("algo", ctypes.c_int), ("d_idx", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("d_f", ctypes.c_void_p), ("d_out", ctypes.c_void_p),
-                ("ready_event", ctypes.c_void_p)]
+                ("ready_event", ctypes.c_void_p), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -381,7 +381,12 @@ class Server:
 
     @staticmethod
     def _key(req, L, n2max, n_nodes, mesh):
-        req.L, req.n2max, req.n_nodes = float(L), int(n2max), int(n_nodes)
+        """L: a cube side, or the sides (Lx, Ly, Lz) of a rectangular box."""
+        if isinstance(L, (tuple, list)):
+            req.L, req.Ly, req.Lz = (float(v) for v in L)
+        else:
+            req.L = float(L)
+        req.n2max, req.n_nodes = int(n2max), int(n_nodes)
         if mesh is not None:
             req.has_mesh, req.mesh = 1, mesh
 

@@ -18,6 +18,7 @@
 // blocks the ones behind it, so the head is always served first and nothing
 // starves.
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -42,11 +43,15 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-// Table cache key: box, cutoff and every mesh field.
-using Key = std::tuple<double, int, int, int, double, int, int, double>;
+// Table cache key: the three box sides, cutoff and every mesh field.
+using Key = std::tuple<double, double, double, int, int, int, double, int, int, double>;
+
+double side_y(const pwc_request &r) { return r.Ly > 0.0 ? r.Ly : r.L; }
+double side_z(const pwc_request &r) { return r.Lz > 0.0 ? r.Lz : r.L; }
 
 Key key_of(const pwc_request &r, const pwc_mesh &m) {
-    return Key(r.L, r.n2max, m.kind, m.n_sub, m.ratio, m.q_sub, m.q_tail, m.alpha_c);
+    return Key(r.L, side_y(r), side_z(r), r.n2max, m.kind, m.n_sub, m.ratio, m.q_sub, m.q_tail,
+               m.alpha_c);
 }
 
 struct Cached {
@@ -252,7 +257,7 @@ bool pwc_server::admit() {
                 if (planned) pwc_table_destroy(planned);
                 planned = new (std::nothrow) pwc_table;
                 planned_key = key;
-                const double sides[3] = {p.r.L, p.r.L, p.r.L};   // the server serves cubes
+                const double sides[3] = {p.r.L, side_y(p.r), side_z(p.r)};
                 st = planned ? pwc::plan_table(sides, p.r.n2max, p.mesh, planned->t, planned_su)
                              : PWC_ERR_NOMEM;
             }
@@ -457,6 +462,8 @@ pwc_status pwc_server_submit(pwc_server *s, const pwc_request *r, uint64_t *tick
     if (!s || !r || !ticket) return PWC_ERR_ARG;
     if (r->kind != PWC_REQ_RECONSTRUCT && r->kind != PWC_REQ_ENERGIES) return PWC_ERR_ARG;
     if (!(r->L > 0.0) || r->n2max < 1 || r->n2max > PWC_MAX_N2MAX || r->n < 0) return PWC_ERR_ARG;
+    if (!(r->Ly >= 0.0) || !(r->Lz >= 0.0) || !std::isfinite(r->Ly) || !std::isfinite(r->Lz))
+        return PWC_ERR_ARG;
     if (r->prec != PWC_FP64 && r->prec != PWC_MIXED) return PWC_ERR_ARG;
     if (!r->d_out || (r->n > 0 && !r->d_idx)) return PWC_ERR_ARG;
     if (r->kind == PWC_REQ_RECONSTRUCT && (reinterpret_cast<uintptr_t>(r->d_idx) & 15))

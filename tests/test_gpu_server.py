@@ -172,3 +172,25 @@ def test_server_errors(pw):
         e = torch.empty(2, dtype=torch.float64, device="cuda")
         t = srv.submit_energies(1.0, 600, occ, e, algo=pw.PAIR_KTABLE, n_nodes=16)
         assert srv.wait(t).status == pw.ERR_ARG
+
+
+def test_box_requests_match_the_library(pw):
+    """Requests on rectangular boxes (L = (Lx, Ly, Lz)) share the queue with
+    cubes, get their own cached tables and give the library's results."""
+    import torch
+    box, cube = (1.0, 1.3, 0.8), 1.0
+    q = torch.from_numpy(workloads.uniform_quads(1045, 40_000, seed=12)).cuda()
+    outs = {k: torch.empty(40_000, dtype=torch.float64, device="cuda") for k in ("box", "cube")}
+    occ = torch.arange(123, dtype=torch.int32, device="cuda")
+    e_box = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pw.Server(1 << 30, max_inflight=2) as srv:
+        ts = [srv.submit_reconstruct(box, 40, q, outs["box"], n_nodes=64),
+              srv.submit_reconstruct(cube, 40, q, outs["cube"], n_nodes=64),
+              srv.submit_energies(box, 40, occ, e_box, n_nodes=64)]
+        assert all(srv.wait(t).status == pw.OK for t in ts)
+        assert srv.stats()["table_builds"] == 2
+    with pw.Table.box(*box, 40, 64) as tb, pw.Table(cube, 40, 64) as tc:
+        assert torch.equal(outs["box"], tb.reconstruct(q))
+        assert torch.equal(outs["cube"], tc.reconstruct(q))
+        assert np.array_equal(e_box.cpu().numpy(), np.array(tb.energies(occ)))
+        assert not torch.equal(outs["box"], outs["cube"])
