@@ -21,7 +21,8 @@
  *               (Eq. 8 after the p integral, reduced coordinates), one real
  *               table of (4 nmax + 1)^2 entries per node serving all three
  *               directions of the cube (Sec. III: planewave products are
- *               planewaves, so only index differences matter).
+ *               planewaves, so only index differences matter); a rectangular
+ *               box has one table per direction (pwc_table_create_box).
  *   energies    uniform electron gas, one spin channel (Sec. III):
  *               E_H =  1/2 sum_{i,j} f_i f_j <ij|ij>,
  *               E_x = -1/2 sum_{i,j} f_i f_j <ij|ji>  (i = j included).
@@ -81,11 +82,13 @@ typedef enum {
  * up to rounding.
  *   NODESUM: the Q-node sum of Eq. 14 for every pair, from the diagonal
  *            entries tau_q(m, -m) (the paper's O(M^2 Q) evaluation).
- *   KTABLE:  <ij|ji> depends only on the sorted |n_j - n_i| per direction;
- *            the node sums K(a, b, c) = sum_q W_q D_q(a) D_q(b) D_q(c),
- *            a <= b <= c <= 4 nmax, are formed once at table creation and
- *            each pair reads one entry.  Available when the C(4 nmax + 3, 3)
- *            entries fit in LDS (nmax <= 23).
+ *   KTABLE:  <ij|ji> depends only on |n_j - n_i| per direction (sorted,
+ *            for a cube); the node sums K(a, b, c) = sum_q W_q D_q(a) D_q(b)
+ *            D_q(c), a <= b <= c <= 4 nmax for a cube and every a, b, c for a
+ *            box, are formed once at table creation and each pair reads one
+ *            entry.  Available when the entries fit in LDS: C(4 nmax + 3, 3)
+ *            for a cube (nmax <= 23), (4 nmax + 1)^3 for a box (nmax <= 6 ...
+ *            13, i.e. n2max <= 195).
  *   AUTO:    KTABLE when available, else NODESUM.
  */
 typedef enum {
@@ -148,7 +151,8 @@ PWC_API pwc_status pwc_mesh_default(int n_nodes, pwc_mesh *out);
 PWC_API pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes);
 
 /*
- * Build the tables for a cube of side L > 0 and the basis |n|^2 <= n2max
+ * Build the tables for a cube of side L > 0 (pwc_table_create_box for a
+ * rectangular box) and the basis |n|^2 <= n2max
  * (1 <= n2max <= PWC_MAX_N2MAX) on the mesh `mesh` (NULL: the default mesh
  * for n_nodes).  If mesh is given, n_nodes must be 0 or equal its node count.
  * Basis, mesh and index maps are formed on the host in FP64; the 1-D
@@ -161,9 +165,10 @@ PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_
                             void *stream, pwc_table **out);
 
 /*
- * A rectangular box with sides (Lx, Ly, Lz).  The summary of the paper
- * names such separable cases without formulas; writing 1/r as a Gaussian
- * integral, direction d factorises as in a cube of side L_d, so on the
+ * A rectangular box with sides (Lx, Ly, Lz).  The derivation (Sec. II)
+ * counts planewaves in a box among the separable bases but works the
+ * formulas out for the cube only; writing 1/r as a Gaussian integral
+ * (Eqs. 5-6), direction d factorises as in a cube of side L_d, so on the
  * reference mesh beta = 4 alpha / L0^2, L0 = (Lx Ly Lz)^(1/3), direction d
  * reads its own tables at the node beta_q / rho_d^2, rho_d = L_d / L0, and
  *   <ij|kl> = (1/(sqrt(pi) L0)) sum_q W_q tau^x_q tau^y_q tau^z_q.
@@ -188,13 +193,13 @@ PWC_API pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int
 
 /*
  * Small quadruple lists skip the node passes: pwc_reconstruct evaluates a
- * list of n <= direct_max quadruples with one lane per quadruple reading the
- * tables from global memory (Eq. 14 over all nodes in one launch); longer
- * lists run the node-pass kernels.  The two agree to rounding.  The default
- * is 524288 (about where the two take equal time on MI355X); 0 sends every
- * list through the node passes.  n must lie in
- * [0, 1048576] (PWC_ERR_ARG otherwise).  Must not overlap a reconstruction
- * that uses the same table.
+ * list of n <= direct_max quadruples with four lanes per quadruple reading
+ * the tables from global memory (Eq. 14 over all nodes in one launch);
+ * longer lists run the node-pass kernels.  The two agree to rounding.  The
+ * default is 524288 (about where the two take equal time on MI355X); 0 sends
+ * every list through the node passes.  n must lie in [0, 1048576]
+ * (PWC_ERR_ARG otherwise).  Must not overlap a reconstruction that uses the
+ * same table.
  */
 PWC_API pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n);
 
@@ -269,12 +274,13 @@ PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, i
                            double *d_out, pwc_precision p, void *stream);
 
 /*
- * pwc_reconstruct that also reports how long each of its launches took on
- * `stream` (HIP events between the launches), then waits for the stream.
- * The reconstruction runs as a decode launch followed by P node-pass
- * launches; h_ms[0] is the decode and h_ms[1 .. P] the passes (first slab
- * of at most 2^27 quadruples).  *n_stages = 1 + P; PWC_ERR_ARG if
- * max_stages < 1 + P.  Results are identical to pwc_reconstruct's.
+ * The node-pass reconstruction (whatever the direct-kernel size) that also
+ * reports how long each of its launches took on `stream` (HIP events
+ * between the launches), then waits for the stream.  h_ms[0] is the
+ * standalone decode launch (near zero when the first pass decodes the
+ * stream itself) and h_ms[1 .. P] are the P passes (first slab of at most
+ * 2^27 quadruples).  *n_stages = 1 + P; PWC_ERR_ARG if max_stages < 1 + P.
+ * Results are identical to pwc_reconstruct's with direct_max = 0.
  */
 PWC_API pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                            double *d_out, pwc_precision p, void *stream,
@@ -319,23 +325,30 @@ PWC_API pwc_status pwc_sync(const pwc_table *t, void *stream);
  * Serving: a persistent request loop with continuous batching.
  *
  * A scheduler thread owns `max_inflight` HIP streams ("slots") and a cache
- * of resident tables keyed by (L, n2max, mesh).  Submitted requests wait in
- * a FIFO; whenever a slot is free and the request's table plus scratch fit
- * in the HBM budget, the request is admitted: its table is reused or built
- * (least-recently-used tables that no queued or running request holds are
- * evicted to make room) and its kernels are launched on the slot's stream,
- * so work of different requests and tables overlaps on the device.  A
- * request whose table alone exceeds the budget fails with PWC_ERR_NOMEM;
- * otherwise requests wait for memory rather than fail.  Each request runs
- * exactly the kernels of pwc_reconstruct / pwc_energies_ex, so its result
- * does not depend on what else is in flight.
+ * of resident tables keyed by (Lx, Ly, Lz, n2max, mesh).  Submitted requests
+ * wait in a FIFO; whenever a slot is free and the request's table plus
+ * scratch fit in the HBM budget, the request is admitted: its table is
+ * reused or built (least-recently-used tables that no queued or running
+ * request holds are evicted to make room) and its kernels are launched on
+ * the slot's stream, so work of different requests and tables overlaps on
+ * the device.  A small reconstruction (at most the table's direct-kernel
+ * size, pwc_table_set_direct_max: 524288 quadruples for the tables the
+ * server builds) admitted from the head of the queue takes along up to 23
+ * later queued small reconstructions whose tables are resident, and one
+ * launch of the direct kernel serves them all, each with its own table,
+ * precision, buffers and error word.  A request whose table alone exceeds the budget fails with
+ * PWC_ERR_NOMEM; otherwise requests wait for memory rather than fail.  Each
+ * request computes every output with exactly the arithmetic of
+ * pwc_reconstruct / pwc_energies_ex on the same table, so its result does
+ * not depend on what else is in flight.
  *
  * Buffers named in a request (d_idx, d_f, d_out) are owned by the caller and
  * must stay valid and unmodified until pwc_server_wait (or a successful
  * pwc_server_poll) returns for its ticket.  If a kernel sees an index out of
- * range, the request reports PWC_ERR_RANGE (concurrent requests on the same
- * table share its error word, so such a report may also reach a request that
- * ran at the same time on that table).
+ * range, the request reports PWC_ERR_RANGE (requests that run the node
+ * passes or the pair sums share their table's error word, so such a report
+ * may also reach a request that ran at the same time on that table; a
+ * request served by the direct kernel has an error word of its own).
  * ------------------------------------------------------------------------ */
 typedef enum { PWC_REQ_RECONSTRUCT = 0, PWC_REQ_ENERGIES = 1 } pwc_request_kind;
 
