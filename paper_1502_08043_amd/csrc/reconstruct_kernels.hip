@@ -66,6 +66,7 @@ namespace pwc {
 namespace {
 
 constexpr int kThreads = 1024;   // one workgroup per CU when the slab is large
+constexpr int kDepth = 4;        // stream iterations in flight per lane (3-4 measure alike)
 // Quadruples per group and iteration: 4, fewer when each lane reads more
 // words per row (the loads of an iteration must fit in registers).
 template <int G>
@@ -140,6 +141,11 @@ struct Pk32 {
         b = (v >> 10) & 1023u;
         c = (v >> 20) & 1023u;
     }
+    // number of odd entries; the first and last entries swapped (flag kept);
+    // the word sent to lane `lane` of the wave
+    __device__ static int odd(T v) { return __popc(v & 0x100401u); }
+    __device__ static T flip(T v) { return (v & 0xC00FFC00u) | ((v & 1023u) << 20) | ((v >> 20) & 1023u); }
+    __device__ static T send(T v, int lane) { return __builtin_amdgcn_ds_permute(lane << 2, v); }
 };
 struct Pk64 {
     using T = uint2;
@@ -153,6 +159,13 @@ struct Pk64 {
         a = v.x & 0xffffu;
         b = v.x >> 16;
         c = v.y & 0xffffu;
+    }
+    __device__ static int odd(T v) { return __popc(v.x & 0x10001u) + (v.y & 1u); }
+    __device__ static T flip(T v) {
+        return make_uint2((v.x & 0xffff0000u) | (v.y & 0xffffu), (v.y & 0xffff0000u) | (v.x & 0xffffu));
+    }
+    __device__ static T send(T v, int lane) {
+        return make_uint2(__builtin_amdgcn_ds_permute(lane << 2, v.x), __builtin_amdgcn_ds_permute(lane << 2, v.y));
     }
 };
 
@@ -253,12 +266,12 @@ __device__ __forceinline__ void order_by_parity(int &a, int &b, int &c) {
     cx(a, b);
 }
 
-// Packed entries of quadruple v at stream position e; basis and fold map
+// Packed entries of quadruple v in ascending parity; basis and fold map
 // from LDS copies or from global memory.
 template <typename PK>
 __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const int32_t *basis,
                                                      const int16_t *lfold, const int32_t *gfold,
-                                                     int4 v, int64_t e) {
+                                                     int4 v) {
     const unsigned N = static_cast<unsigned>(a.N);
     if (static_cast<unsigned>(v.x) >= N || static_cast<unsigned>(v.y) >= N ||
         static_cast<unsigned>(v.z) >= N || static_cast<unsigned>(v.w) >= N) {
@@ -276,15 +289,17 @@ __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const in
     if (a.ndir == 3) {       // a box: each direction reads its own table's rows
         fy += a.E1;
         fz += 2 * a.E1;
-    } else {                 // a cube: the three entries are interchangeable
-        order_by_parity(fx, fy, fz);
-        if (descending_at(e, a.ord_g)) {
-            const int t = fx;
-            fx = fz;
-            fz = t;
-        }
     }
+    order_by_parity(fx, fy, fz);   // the node term is a product: any order serves
     return PK::pack(fx, fy, fz);
+}
+
+// The word the stream holds for quadruple e: ascending parity for the
+// one-lane passes (which pair their lanes themselves), else ascending or
+// descending by stream position for the lane groups of the passes.
+template <typename PK>
+__device__ __forceinline__ typename PK::T stream_word(typename PK::T v, int64_t e, int ord_g) {
+    return ord_g > 1 && descending_at(e, ord_g) ? PK::flip(v) : v;
 }
 
 template <typename PK, bool LDS_MAPS>
@@ -312,8 +327,9 @@ __global__ __launch_bounds__(kDecodeThreads) void k_decode(PassArgs a, int64_t n
         for (int b = 0; b < kDecodeBatch; ++b) {
             const int64_t e = base + b * kDecodeThreads + threadIdx.x;
             if (e >= n_pad) continue;
-            out[e] = e < a.n ? decode_one<PK>(a, LDS_MAPS ? lbasis : a.basis, LDS_MAPS ? lfold : nullptr,
-                                              a.fold, q[b], e)
+            out[e] = e < a.n ? stream_word<PK>(decode_one<PK>(a, LDS_MAPS ? lbasis : a.basis,
+                                                              LDS_MAPS ? lfold : nullptr, a.fold, q[b]),
+                                               e, a.ord_g)
                              : PK::pack(0, 0, 0);
         }
     }
@@ -340,6 +356,41 @@ __device__ __forceinline__ uint32_t bcast_row(uint32_t v, int r) {
 template <int R>
 __device__ __forceinline__ uint2 bcast_row(uint2 v, int r) {
     return make_uint2(bcast_row<R>(v.x, r), bcast_row<R>(v.y, r));
+}
+
+// Lane pairing of the one-lane layout (G = 1).  Lanes g and g + 8 of a
+// 16-lane phase read the same word position of their rows at every step,
+// so their reads share banks exactly when the two rows have equal parity.
+// A quadruple with c odd entries read in ascending parity and one with
+// 3 - c odd entries read in descending parity meet opposite parities at all
+// three reads.  With random rows most phases would hold such a clash at
+// every read, so the wave's 64 quadruples are dealt to lanes: pairs
+// 0 .. m03 - 1 take classes 0 (low lane) and 3 (high lane), the next m12
+// pairs classes 1 and 2, and the quadruples left over fill the last pairs
+// in order.  Returns the lane that evaluates this lane's quadruple (a
+// permutation of the wave; every lane must take part).
+__device__ __forceinline__ int pair_lane(int cls) {
+    const uint64_t b0 = __builtin_amdgcn_ballot_w64(cls == 0);
+    const uint64_t b1 = __builtin_amdgcn_ballot_w64(cls == 1);
+    const uint64_t b2 = __builtin_amdgcn_ballot_w64(cls == 2);
+    const uint64_t b3 = __builtin_amdgcn_ballot_w64(cls == 3);
+    const int n0 = __popcll(b0), n1 = __popcll(b1), n2 = __popcll(b2), n3 = __popcll(b3);
+    const int m03 = min(n0, n3), m12 = min(n1, n2), l03 = n0 + n3 - 2 * m03;
+    const bool outer = cls == 0 || cls == 3;
+    const uint64_t same = cls == 0 ? b0 : cls == 1 ? b1 : cls == 2 ? b2 : b3;
+    const int r = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(same >> 32),
+                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(same), 0));
+    const int m = outer ? m03 : m12;
+    int pair, side;
+    if (r < m) {                      // a matched pair: classes 0 and 1 low, 2 and 3 high
+        pair = (outer ? 0 : m03) + r;
+        side = cls >= 2;
+    } else {                          // left over: in order, two per pair
+        const int k = (outer ? 0 : l03) + r - m;
+        pair = m03 + m12 + (k >> 1);
+        side = k & 1;
+    }
+    return (pair & 7) | ((pair >> 3) << 4) | (side << 3);
 }
 
 // One node pass.  LDS: the slab [E][G W] of 16-byte words (nodes q0 ..
@@ -389,8 +440,13 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
         const int64_t e = b + own * NG + g;
         if (!FIRST && writer && e < a.n) st.prev = a.out[e];
     };
-    Stream<PK, R> s0{}, s1{};
-    if (base < a.n) load(s0, base);                     // overlaps the slab staging
+    // D stream buffers in turn: the loads for iteration i + D - 1 are issued
+    // before iteration i computes.
+    constexpr int D = DECODE ? 2 : kDepth;
+    Stream<PK, R> st[D]{};
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i)                     // overlaps the slab staging
+        if (base + i * stride < a.n) load(st[i], base + i * stride);
     {
         V *dst = reinterpret_cast<V *>(lds_raw);
         const V *src = static_cast<const V *>(a.tab) + a.q0 / 2;
@@ -413,20 +469,33 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
         T pk[R];
         if (DECODE) {
             const int64_t e = b + rdec * NG + g;
-            const T mine = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, st.q, e)
+            const T mine = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, st.q)
                                    : PK::pack(0, 0, 0);   // padding up to the tile end
-            if (!LAST && s < R) const_cast<T *>(sc)[b + rdec * NG] = mine;
+            if (!LAST && s < R) const_cast<T *>(sc)[b + rdec * NG] = stream_word<PK>(mine, e, a.ord_g);
 #pragma unroll
             for (int r = 0; r < R; ++r) pk[r] = bcast_row<R>(mine, r);
         } else {
 #pragma unroll
             for (int r = 0; r < R; ++r) pk[r] = st.pk[r];
         }
+        // One lane per quadruple: evaluate the quadruple pair_lane deals
+        // this lane, the high lane of each pair in descending parity.  The
+        // decoding pass is bound by its instruction count and skips it.
+        constexpr bool PAIR = G == 1 && !DECODE;
+        int dest = 0;
+        T ev[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ev[r] = pk[r];
+        if (PAIR) {
+            dest = pair_lane(PK::odd(pk[0]));
+            ev[0] = PK::send(pk[0], dest);
+            if (threadIdx.x & 8) ev[0] = PK::flip(ev[0]);
+        }
         V x[R][W], y[R][W], z[R][W];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int f0, f1, f2;
-            PK::unpack(pk[r], f0, f1, f2);
+            PK::unpack(ev[r], f0, f1, f2);
             const uint32_t a0 = f0 * ROWB + lane_b, a1 = f1 * ROWB + lane_b, a2 = f2 * ROWB + lane_b;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
@@ -446,7 +515,10 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
             for (int k = 0; k < W; ++k) A::add2(acc, x[r][k], y[r][k], z[r][k]);
             v[r] = A::value(acc);
         }
-        const double sum = group_reduce<G, R>(v, s);
+        double sum = group_reduce<G, R>(v, s);
+        if (PAIR)   // back to the lane that holds the quadruple's stream slot
+            sum = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest << 2, __double2hiint(sum)),
+                                   __builtin_amdgcn_ds_bpermute(dest << 2, __double2loint(sum)));
         const int64_t e = b + own * NG + g;
         if (writer && e < a.n) {
             double prev;
@@ -462,19 +534,18 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
         }
     };
 
-    // Two stream buffers in turn: the loads for the next iteration are in
-    // flight while this one computes.  A decoding pass covers the whole
-    // padded stream, so the later passes (larger tiles) find every packed
-    // word they read written.
+    // A decoding pass covers the whole padded stream, so the later passes
+    // (larger tiles) find every packed word they read written.
     const int64_t end = DECODE ? a.n_pad : a.n;
     while (base < end) {
-        if (base + stride < end) load(s1, base + stride);
-        body(s0, base);
-        base += stride;
-        if (base >= end) break;
-        if (base + stride < end) load(s0, base + stride);
-        body(s1, base);
-        base += stride;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t ahead = base + (D - 1) * stride;
+            if (ahead < end) load(st[(i + D - 1) % D], ahead);
+            body(st[i], base);
+            base += stride;
+            if (base >= end) break;
+        }
     }
 }
 
