@@ -6,17 +6,22 @@ quadruples (half uniform over the basis, half over the 925-orbital occupied
 sphere |n|^2 <= 36) and the Hartree + exchange energies of that sphere.
 
 One step = one pass of the whole path: table construction (basis, mesh, 1-D
-primitives, table layouts, exchange kernel table), reconstruction of the 1e8
-integrals, and the pair sums with their final reductions.  Inputs are
-resident in HBM before the timed region.  Both precisions are timed; `value`
-is the FP64 path.
+primitives, table layouts, exchange kernel table), the value table (every
+distinct integral by Eq. 14 over all nodes), reconstruction of the 1e8
+integrals by one value read each, and the pair sums with their final
+reductions.  Inputs are resident in HBM before the timed region; every step
+builds its table and value table afresh.  `value` is that FP64 step.  Two more
+legs run the same step without a value table: FP64 node sums
+(`fp64_node_sums`) and split-FP32 node sums (`mixed`).
 
 The JSON line also carries
-  roofline      -- the dominant kernel (the FP64 node-pass kernel of the
-                   reconstruction) against the MI355X FP64 vector peak, its
-                   per-launch time taken live with HIP events between launches;
+  roofline      -- the dominant kernel of the step (the value-table read,
+                   k_rec_values) against the MI355X HBM peak, its launch time
+                   taken live with HIP events; value_build and
+                   node_pass_roofline give the FP64 rates of the value-table
+                   build and of the steady node pass;
   cpu_baseline  -- the FP64 CPU oracle on a sample of the same stream;
-  legs          -- per-precision step and kernel times, pair-sum rates;
+  legs          -- per-leg step and kernel times, pair-sum rates;
   serving       -- p50/p99 latency of a Poisson request stream over many
                    boxes, cutoffs and node counts.
 
@@ -43,8 +48,12 @@ import workloads  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6                     # MI355X FP64 vector, dense
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1502_08043_amd", "csrc", "reconstruct_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rec_pass_lookup_stream_9171pw_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_1502_08043_amd", "csrc")
+# kernel source -> committed counter summary of its kernel on the lookup stream
+SOURCES = {"values": (os.path.join(CSRC, "value_kernels.hip"),
+                      os.path.join(ROOT, "profiles", "k_rec_values_lookup_stream_9171pw_traffic.txt")),
+           "passes": (os.path.join(CSRC, "reconstruct_kernels.hip"),
+                      os.path.join(ROOT, "profiles", "k_rec_pass_lookup_stream_9171pw_traffic.txt"))}
 
 
 def log(*a):
@@ -67,31 +76,32 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_hash():
-    """First 16 hex digits of sha256 of the reconstruction kernels' code, with
-    // comments and blank lines removed (a comment edit keeps the hash)."""
-    with open(KERNEL_SRC) as fh:
+def kernel_hash(which="values"):
+    """First 16 hex digits of sha256 of a kernel file's code, with // comments
+    and blank lines removed (a comment edit keeps the hash)."""
+    with open(SOURCES[which][0]) as fh:
         code = [re.sub(r"\s*//.*$", "", line).rstrip() for line in fh]
     text = "\n".join(line for line in code if line.strip())
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per k_rec_pass launch from the committed counter summary, or
+def recorded_traffic(which="values"):
+    """HBM bytes per launch of a kernel from its committed counter summary, or
     None if the summary is missing or was taken on another kernel source."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(SOURCES[which][1]).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash(which):
         return None
     return float(m_bytes.group(1))
 
 
 def pmc_workload():
-    """A plain copy of known size, then three FP64 reconstructions of the stream."""
+    """A plain copy of known size, three FP64 node-sum reconstructions of the
+    stream, then the value table and three reconstructions that read it."""
     import torch
     import paper_1502_08043_amd as pw
     w = workloads.C4_STREAM
@@ -104,9 +114,13 @@ def pmc_workload():
     out = torch.empty(w.n_quads, dtype=torch.float64, device="cuda")
     for _ in range(3):
         t.reconstruct(q, out, pw.FP64)
+    t.build_values()
+    for _ in range(3):
+        t.reconstruct(q, out, pw.FP64)
     torch.cuda.synchronize()
     t.sync()
-    print(f"pmc workload done; kernel_source_sha256_16: {kernel_hash()}", flush=True)
+    print(f"pmc workload done; kernel_source_sha256_16: values {kernel_hash('values')} "
+          f"passes {kernel_hash('passes')}", flush=True)
 
 
 def serving_leg(pw, n_requests):
@@ -182,7 +196,7 @@ def serving_leg(pw, n_requests):
 def main():
     args = parse()
     if args.kernel_hash:
-        print(kernel_hash())
+        print(f"values {kernel_hash('values')} passes {kernel_hash('passes')}")
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
@@ -210,43 +224,62 @@ def main():
     quads = torch.from_numpy(quads_h).cuda()
     occ = torch.arange(M, dtype=torch.int32, device="cuda")
     occ_all = torch.arange(N, dtype=torch.int32, device="cuda")
-    out = {p: torch.empty(n, dtype=torch.float64, device="cuda") for p in (pw.FP64, pw.MIXED)}
+    LEGS = (("fp64", pw.FP64, True), ("fp64_node_sums", pw.FP64, False), ("mixed", pw.MIXED, False))
+    out = {name: torch.empty(n, dtype=torch.float64, device="cuda") for name, _, _ in LEGS}
     eout = torch.empty(2, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
 
-    def step(prec):
+    def step(prec, values, o):
         t = pw.Table(w.L, w.n2max, w.n_nodes)            # basis, mesh, primitives, layouts
-        t.reconstruct(quads, out[prec], precision=prec)  # decode + node passes
+        if values:
+            t.build_values()                             # every distinct integral, Eq. 14
+        t.reconstruct(quads, o, precision=prec)          # value reads, or decode + node passes
         t.energies_async(occ, None, prec, eout)          # pair sums + reductions
         t.sync()                                         # surfaces kernel errors
         t.close()
 
     legs = {}
-    for prec, name in ((pw.FP64, "fp64"), (pw.MIXED, "mixed")):
+    for name, prec, values in LEGS:
         for _ in range(args.warmup):
-            step(prec)
+            step(prec, values, out[name])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(prec)
+            step(prec, values, out[name])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         legs[name] = {"ms_per_step": dt * 1e3, "integrals_per_s": n / dt}
         log(f"[bench] {name}: {dt * 1e3:.3f} ms/step, {n / dt:.4g} integrals/s")
 
-    t = pw.Table(w.L, w.n2max, w.n_nodes)
-    for prec, name in ((pw.FP64, "fp64"), (pw.MIXED, "mixed")):
-        # whole reconstruction call
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        t.reconstruct(quads, out[prec], precision=prec)
-        ev[0].record(stream)
-        for _ in range(args.kernel_reps):
-            t.reconstruct(quads, out[prec], precision=prec)
-        ev[1].record(stream)
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
         torch.cuda.synchronize()
-        legs[name]["reconstruct_ms"] = ev[0].elapsed_time(ev[1]) / args.kernel_reps
+        return e0.elapsed_time(e1) / reps
+
+    t = pw.Table(w.L, w.n2max, w.n_nodes)
+    # the value table: its build (one launch; the call waits for it) and the reads
+    vb = []
+    for _ in range(args.kernel_reps):
+        t.free_values()
+        vb.append(timed(t.build_values, 1))
+    nvalues = t.values_info()[1] // 8
+    legs["fp64"]["value_build_ms"] = float(np.mean(vb))
+    legs["fp64"]["value_table_bytes"] = nvalues * 8
+    t.reconstruct(quads, out["fp64"])
+    legs["fp64"]["reconstruct_ms"] = timed(lambda: t.reconstruct(quads, out["fp64"]), args.kernel_reps)
+    log(f"[bench] fp64 values: build {legs['fp64']['value_build_ms']:.3f} ms "
+        f"({nvalues} values), reads {legs['fp64']['reconstruct_ms']:.3f} ms")
+    t.free_values()
+    for name, prec, values in LEGS[1:]:
+        t.reconstruct(quads, out[name], precision=prec)
+        legs[name]["reconstruct_ms"] = timed(lambda: t.reconstruct(quads, out[name], precision=prec),
+                                             args.kernel_reps)
         # per launch: decode, then the node passes
-        stages = np.array([t.reconstruct_profile(quads, out[prec], precision=prec)[1]
+        stages = np.array([t.reconstruct_profile(quads, out[name], precision=prec)[1]
                            for _ in range(args.kernel_reps)]).mean(axis=0)
         legs[name]["decode_ms"] = float(stages[0])
         legs[name]["pass_ms"] = [float(v) for v in stages[1:]]
@@ -254,14 +287,8 @@ def main():
         for MM, o, key in ((M, occ, "exchange_M925"), (N, occ_all, "exchange_M9171")):
             for algo, an in ((pw.PAIR_KTABLE, "ktable"), (pw.PAIR_NODESUM, "nodesum")):
                 t.energies_async(o, None, prec, eout, algo=algo)
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 reps = 20 if (MM == M or algo == pw.PAIR_KTABLE) else 3
-                e0.record(stream)
-                for _ in range(reps):
-                    t.energies_async(o, None, prec, eout, algo=algo)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
+                ms = timed(lambda: t.energies_async(o, None, prec, eout, algo=algo), reps)
                 legs[name][f"{key}_{an}_ms"] = ms
                 legs[name][f"{key}_{an}_pairs_per_s"] = MM * MM / (ms * 1e-3)
         t.sync()
@@ -275,30 +302,45 @@ def main():
         pw.Table(w.L, w.n2max, w.n_nodes).close()
     table_ms = (time.perf_counter() - tb0) / 5 * 1e3
     e_fp64 = t.energies(occ)
-    P = len(legs["fp64"]["pass_ms"])
     t.close()
 
-    # Roofline of the dominant kernel, the FP64 node pass.  Algorithmic work
-    # of Eq. 14: 4 flops per node term (three products and one sum), c nodes
-    # per pass and integral.  The steady passes 2..P are the kernel timed;
-    # the first pass also decodes the stream and is reported beside it.
-    lay = legs["fp64"]["layout"]
+    # Roofline of the step's dominant kernel, the value-table read: per
+    # quadruple 16 bytes of indices in, one 8-byte value read, 8 bytes out,
+    # one launch per call.
+    gather_ms = legs["fp64"]["reconstruct_ms"]
+    achieved = 32.0 * n / (gather_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": recorded_traffic("values"),
+                "kernel": "k_rec_values (decode, one value read per quadruple)",
+                "launches_per_call": 1, "algorithmic_bytes_per_launch": 32.0 * n,
+                "avg_launch_ms": gather_ms, "kernel_source_sha256_16": kernel_hash("values")}
+    # The value-table build: E(E+1)(E+2)/6 values of Q node terms each, at the
+    # algorithmic 4 flops per node term of Eq. 14.
+    vb_ms = legs["fp64"]["value_build_ms"]
+    vb_tf = 4.0 * Q * nvalues / (vb_ms * 1e-3) / 1e12
+    value_build = {"kernel": "k_values_build", "values": nvalues, "avg_launch_ms": vb_ms,
+                   "achieved": vb_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": vb_tf / FP64_PEAK_TFLOPS, "bound": "alu"}
+    # The steady FP64 node pass (node sums without a value table).  Algorithmic
+    # work of Eq. 14: 4 flops per node term, c nodes per pass and integral.
+    lay = legs["fp64_node_sums"]["layout"]
     c = lay["nodes_per_pass"]
-    steady = legs["fp64"]["pass_ms"][1:] or legs["fp64"]["pass_ms"]
+    P = len(legs["fp64_node_sums"]["pass_ms"])
+    steady = legs["fp64_node_sums"]["pass_ms"][1:] or legs["fp64_node_sums"]["pass_ms"]
     pass_ms = float(np.mean(steady))
     flops = 4.0 * c * n
-    achieved = flops / (pass_ms * 1e-3) / 1e12
-    traffic = recorded_traffic()
-    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": f"k_rec_pass<F64, G={lay['lanes']}, W={lay['words']}> steady node pass",
-                "launches_per_call": P, "nodes_per_launch": c,
-                "algorithmic_flops_per_launch": flops, "avg_launch_ms": pass_ms,
-                "first_pass_with_decode_ms": legs["fp64"]["pass_ms"][0],
-                "lds_read_TBps": 3 * 8 * c * n / (pass_ms * 1e-3) / 1e12,
-                "hbm_algorithmic_GBps": 20.0 * n / (pass_ms * 1e-3) / 1e9,
-                "whole_call_TFLOPs": 4.0 * Q * n / (legs["fp64"]["reconstruct_ms"] * 1e-3) / 1e12,
-                "kernel_source_sha256_16": kernel_hash()}
+    np_tf = flops / (pass_ms * 1e-3) / 1e12
+    node_pass_roofline = {
+        "bound": "alu", "achieved": np_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": np_tf / FP64_PEAK_TFLOPS, "traffic": recorded_traffic("passes"),
+        "kernel": f"k_rec_pass<F64, G={lay['lanes']}, W={lay['words']}> steady node pass",
+        "launches_per_call": P, "nodes_per_launch": c,
+        "algorithmic_flops_per_launch": flops, "avg_launch_ms": pass_ms,
+        "first_pass_with_decode_ms": legs["fp64_node_sums"]["pass_ms"][0],
+        "lds_read_TBps": 3 * 8 * c * n / (pass_ms * 1e-3) / 1e12,
+        "hbm_algorithmic_GBps": 20.0 * n / (pass_ms * 1e-3) / 1e9,
+        "whole_call_TFLOPs": 4.0 * Q * n / (legs["fp64_node_sums"]["reconstruct_ms"] * 1e-3) / 1e12,
+        "kernel_source_sha256_16": kernel_hash("passes")}
 
     serving = None
     if not args.no_serve:
@@ -333,8 +375,8 @@ def main():
             scale = scale * np.abs(tau[:, m[:, d], mp[:, d]])
         scale = scale.sum(0) / math.sqrt(math.pi)
         errs = {}
-        for k, p in (("fp64", pw.FP64), ("mixed", pw.MIXED)):
-            got = out[p][torch.from_numpy(rows).cuda()].cpu().numpy()
+        for k in ("fp64", "fp64_node_sums", "mixed"):
+            got = out[k][torch.from_numpy(rows).cuda()].cpu().numpy()
             errs[k] = {"max_abs": float(np.max(np.abs(got - ref))),
                        "max_condition_aware": float(np.max(np.abs(got[::100] - ref[::100]) / scale))}
         cpu = {"value": sample / t_rec, "unit": "integrals/s", "cores": threads, "kind": "oracle",
@@ -358,11 +400,14 @@ def main():
         "config": {"workload": w.name, "L": w.L, "n2max": w.n2max, "basis_N": N,
                    "occupied_M": M, "n_nodes": Q, "mesh": "geometric 8x11 + 8 tail",
                    "n_quads": n, "seed": w.seed, "table_device_bytes": table_bytes,
-                   "step": "table build + reconstruct all quads + E_H/E_x at M=925"},
-        "pair_sums_per_s": {"M925_ktable": legs["fp64"]["exchange_M925_ktable_pairs_per_s"],
-                            "M9171_ktable": legs["fp64"]["exchange_M9171_ktable_pairs_per_s"],
-                            "M9171_nodesum": legs["fp64"]["exchange_M9171_nodesum_pairs_per_s"]},
-        "mixed_vs_fp64": {"integrals_per_s_ratio": legs["mixed"]["integrals_per_s"] /
+                   "step": "table build + value table + reconstruct all quads + E_H/E_x at M=925"},
+        "pair_sums_per_s": {
+            "M925_ktable": legs["fp64_node_sums"]["exchange_M925_ktable_pairs_per_s"],
+            "M9171_ktable": legs["fp64_node_sums"]["exchange_M9171_ktable_pairs_per_s"],
+            "M9171_nodesum": legs["fp64_node_sums"]["exchange_M9171_nodesum_pairs_per_s"]},
+        "mixed_vs_fp64": {"integrals_per_s_ratio_node_sums": legs["mixed"]["integrals_per_s"] /
+                          legs["fp64_node_sums"]["integrals_per_s"],
+                          "integrals_per_s_ratio_vs_value_table": legs["mixed"]["integrals_per_s"] /
                           legs["fp64"]["integrals_per_s"]},
         "p99_ms": serving["p99_ms"] if serving else None,
         "legs": legs,
@@ -370,6 +415,8 @@ def main():
         "energies_fp64_M925": {"E_H": e_fp64[0], "E_x": e_fp64[1]},
         "serving": serving,
         "roofline": roofline,
+        "value_build": value_build,
+        "node_pass_roofline": node_pass_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

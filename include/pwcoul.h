@@ -227,6 +227,29 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
 PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
 
 /*
+ * Value table.  <ij|kl> depends on a quadruple only through its three folded
+ * table entries, one per direction (Sec. III: only index differences matter,
+ * and tau_q(m, m') = tau_q(m', m) = tau_q(-m, -m')).  A cube's directions
+ * share one table, so its distinct integrals are indexed by the sorted entry
+ * triple: E (E + 1) (E + 2) / 6 values for E folded entries (E = 729 for
+ * nmax = 13: 6.5e7 values, 0.52 GB); a box has E1^3.
+ * pwc_table_build_values evaluates each of them once by Eq. 14 over all
+ * nodes (FP64, on `stream`, then waits) into a device allocation of its
+ * own.  From then on pwc_reconstruct with PWC_FP64 reads one value per
+ * quadruple instead of summing nodes, for any n; PWC_MIXED keeps its node
+ * sums.  The values agree with the node sums to rounding.  PWC_ERR_NOMEM if
+ * the allocation fails (the table is then unchanged); a second call is a
+ * no-op.  pwc_table_values_info sets *built (1 or 0) and *bytes, the size
+ * the values take or would take (either pointer may be NULL);
+ * pwc_table_free_values releases them (no-op if not built).  While built,
+ * pwc_table_info's device_bytes includes them.  None of these calls may
+ * overlap a reconstruction that uses the same table.
+ */
+PWC_API pwc_status pwc_table_build_values(pwc_table *t, void *stream);
+PWC_API pwc_status pwc_table_values_info(const pwc_table *t, int *built, size_t *bytes);
+PWC_API pwc_status pwc_table_free_values(pwc_table *t);
+
+/*
  * Table persistence.  The 1-D tables of Eq. 8 depend only on the box, the
  * cutoff and the mesh, so a built table can be kept and reused.
  * pwc_table_save writes the mesh nodes and weights and the FP64 tables
@@ -268,13 +291,17 @@ PWC_API pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *strea
  * holding (i, j, k, l) per row, 16-byte aligned; d_out is double [n], 8-byte
  * aligned.  Async on `stream`.  n = 0 is a no-op.  An index outside [0, N)
  * makes that output NaN and sets the table's error word (see pwc_sync).
- * p = PWC_FP64 or PWC_MIXED.
+ * p = PWC_FP64 or PWC_MIXED.  An FP64 call on a table with its value table
+ * built reads one value per quadruple; otherwise lists of at most
+ * direct_max quadruples run the direct kernel and longer ones the node
+ * passes (pwc_table_set_direct_max).
  */
 PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n,
                            double *d_out, pwc_precision p, void *stream);
 
 /*
- * The node-pass reconstruction (whatever the direct-kernel size) that also
+ * The node-pass reconstruction (whatever the direct-kernel size, and with or
+ * without a value table) that also
  * reports how long each of its launches took on `stream` (HIP events
  * between the launches), then waits for the stream.  h_ms[0] is the
  * standalone decode launch (near zero when the first pass decodes the

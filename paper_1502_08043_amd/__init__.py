@@ -77,6 +77,9 @@ def lib():
             "pwc_table_layout": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 5),
             "pwc_table_set_layout": (i32, [vp, i32, i32]),
             "pwc_table_set_direct_max": (i32, [vp, i64]),
+            "pwc_table_build_values": (i32, [vp, vp]),
+            "pwc_table_values_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
+            "pwc_table_free_values": (i32, [vp]),
             "pwc_basis": (i32, [vp, vp]),
             "pwc_mesh_nodes": (i32, [vp, vp, vp]),
             "pwc_table_copy": (i32, [vp, vp, vp]),
@@ -224,6 +227,28 @@ class Table:
     def set_direct_max(self, n):
         """Lists of at most n quadruples skip the node passes (0: never)."""
         _check(lib().pwc_table_set_direct_max(self.handle, int(n)), "pwc_table_set_direct_max")
+
+    def build_values(self, stream=None):
+        """Evaluate every distinct integral once (the value table); FP64
+        reconstructions then read one value per quadruple.  Waits."""
+        _check(lib().pwc_table_build_values(self.handle, _stream(stream)), "pwc_table_build_values")
+        self._refresh_bytes()
+
+    def free_values(self):
+        _check(lib().pwc_table_free_values(self.handle), "pwc_table_free_values")
+        self._refresh_bytes()
+
+    def values_info(self):
+        """(built, bytes): whether the value table is built and its size."""
+        b, n = ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().pwc_table_values_info(self.handle, ctypes.byref(b), ctypes.byref(n)),
+               "pwc_table_values_info")
+        return bool(b.value), n.value
+
+    def _refresh_bytes(self):
+        nb = ctypes.c_size_t()
+        _check(lib().pwc_table_info(self.handle, None, None, None, ctypes.byref(nb)), "pwc_table_info")
+        self.device_bytes = nb.value
 
     def basis(self):
         out = np.empty((self.N, 3), dtype=np.int32)

@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libpwcoul.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "host_mesh.cpp", "server.cpp", "table_kernels.hip",
-           "reconstruct_kernels.hip", "direct_kernels.hip", "pairsum_kernels.hip"]
+           "reconstruct_kernels.hip", "direct_kernels.hip", "value_kernels.hip",
+           "pairsum_kernels.hip"]
 
 # -ffp-contract=off: the split-FP32 arithmetic relies on unfused products; FMAs
 # are written explicitly where they are wanted.  Packed FP32 instructions are

@@ -98,6 +98,9 @@ namespace pwc {
 void free_table(Table &t) {
     if (t.d_block) (void)hipFree(t.d_block);
     t.d_block = nullptr;
+    if (t.d_val) (void)hipFree(t.d_val);
+    t.d_val = nullptr;
+    t.val_bytes = 0;
 }
 
 // Carve the table's single device allocation.  With base == nullptr only the
@@ -458,7 +461,44 @@ pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_node
     if (N) *N = t->t.N;
     if (nmax) *nmax = t->t.nmax;
     if (n_nodes) *n_nodes = t->t.Q;
-    if (device_bytes) *device_bytes = t->t.bytes;
+    if (device_bytes) *device_bytes = t->t.bytes + t->t.val_bytes;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
+    if (!t) return PWC_ERR_ARG;
+    pwc::Table &tb = t->t;
+    if (tb.d_val) return PWC_OK;
+    const size_t bytes = sizeof(double) * static_cast<size_t>(pwc::value_count(tb));
+    double *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return PWC_ERR_NOMEM;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err = pwc::launch_values_build(tb, d, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        (void)hipFree(d);
+        return from_hip(err);
+    }
+    tb.d_val = d;
+    tb.val_bytes = bytes;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_values_info(const pwc_table *t, int *built, size_t *bytes) {
+    if (!t) return PWC_ERR_ARG;
+    if (built) *built = t->t.d_val != nullptr;
+    if (bytes) *bytes = sizeof(double) * static_cast<size_t>(pwc::value_count(t->t));
+    return PWC_OK;
+}
+
+pwc_status pwc_table_free_values(pwc_table *t) {
+    if (!t) return PWC_ERR_ARG;
+    if (t->t.d_val) (void)hipFree(t->t.d_val);
+    t->t.d_val = nullptr;
+    t->t.val_bytes = 0;
     return PWC_OK;
 }
 
@@ -532,7 +572,9 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
-    if (n <= t->t.direct_max) {   // small list: one lane per quadruple, no node passes
+    if (t->t.d_val && p == PWC_FP64)   // every distinct value is at hand: one read each
+        return from_hip(pwc::launch_rec_values(t->t, d_quads, n, d_out, static_cast<hipStream_t>(stream)));
+    if (n <= t->t.direct_max) {   // small list: four lanes per quadruple, no node passes
         pwc::DirectBatch b{};
         b.job[0] = pwc::direct_job(t->t, d_quads, n, d_out, p, nullptr);
         b.njobs = 1;

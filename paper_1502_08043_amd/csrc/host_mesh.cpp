@@ -142,28 +142,34 @@ void build_fold(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps) {
     fold.assign(static_cast<size_t>(nd) * nd, -1);
     reps.clear();
     // Representative of the orbit {(m,m'), (m',m), (-m,-m'), (-m',-m)}: the
-    // lexicographically smallest (m + K, m' + K) pair of the orbit.  Entries
-    // are numbered in the order their representative is met, row by row.
+    // lexicographically smallest (m + K, m' + K) pair of the orbit.
+    auto rep_of = [&](int a, int b) {
+        const int m = a - K, mp = b - K;
+        const int orbit[4][2] = {{m, mp}, {mp, m}, {-m, -mp}, {-mp, -m}};
+        int best = a * nd + b;
+        for (const auto &o : orbit) best = std::min(best, (o[0] + K) * nd + (o[1] + K));
+        return best;
+    };
+    // Orbits are numbered by ascending m^2 + m'^2 (ties in row order): index
+    // differences of a planewave basis are small far more often than large,
+    // so the entries a quadruple stream reads most get the smallest numbers
+    // and the value table's most used part is its first few megabytes.
+    std::vector<int> order;
     for (int a = 0; a < nd; ++a)
-        for (int b = 0; b < nd; ++b) {
-            const int m = a - K, mp = b - K;
-            const int orbit[4][2] = {{m, mp}, {mp, m}, {-m, -mp}, {-mp, -m}};
-            int best = a * nd + b;
-            for (const auto &o : orbit) best = std::min(best, (o[0] + K) * nd + (o[1] + K));
-            if (best == a * nd + b) {
-                fold[best] = static_cast<int32_t>(reps.size() / 2);
-                reps.push_back(m);
-                reps.push_back(mp);
-            }
-        }
+        for (int b = 0; b < nd; ++b)
+            if (rep_of(a, b) == a * nd + b) order.push_back(a * nd + b);
+    auto r2 = [&](int v) {
+        const int m = v / nd - K, mp = v % nd - K;
+        return m * m + mp * mp;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return r2(u) < r2(v); });
+    for (size_t e = 0; e < order.size(); ++e) {
+        fold[order[e]] = static_cast<int32_t>(e);
+        reps.push_back(order[e] / nd - K);
+        reps.push_back(order[e] % nd - K);
+    }
     for (int a = 0; a < nd; ++a)
-        for (int b = 0; b < nd; ++b) {
-            const int m = a - K, mp = b - K;
-            const int orbit[4][2] = {{m, mp}, {mp, m}, {-m, -mp}, {-mp, -m}};
-            int best = a * nd + b;
-            for (const auto &o : orbit) best = std::min(best, (o[0] + K) * nd + (o[1] + K));
-            fold[a * nd + b] = fold[best];
-        }
+        for (int b = 0; b < nd; ++b) fold[a * nd + b] = fold[rep_of(a, b)];
 }
 
 }  // namespace pwc

@@ -105,6 +105,10 @@ struct Table {
     double *d_ktab64 = nullptr;     // [kt_n] K(a, b, c), FP64 node sums
     double *d_ktabMX = nullptr;     // [kt_n] same, split-FP32 node sums
     int *d_err = nullptr;           // kernel error word
+    // Value table (pwc_table_build_values): every distinct integral, FP64,
+    // its own allocation; nullptr until built.
+    double *d_val = nullptr;
+    size_t val_bytes = 0;
 };
 
 // api.cpp: table set-up in two phases.  plan_table forms the basis, mesh,
@@ -155,6 +159,12 @@ struct DirectBatch {
 DirectJob direct_job(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
                      pwc_precision p, int *d_err);
 hipError_t launch_direct(DirectBatch b, hipStream_t s);
+// value_kernels.hip: the value table (E (E + 1) (E + 2) / 6 sorted entry
+// triples of a cube, E1^3 triples of a box) and the reconstruction that reads it.
+int64_t value_count(const Table &t);
+hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s);
+hipError_t launch_rec_values(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
+                             hipStream_t s);
 // pairsum_kernels.hip
 hipError_t launch_ktab_build(Table &t, hipStream_t s);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,

@@ -1,0 +1,296 @@
+// Value table: every distinct integral of a table, each evaluated once.
+//
+// <ij|kl> depends on the quadruple only through the three folded entries
+// (one per direction) that the decode finds (Sec. III: planewave products
+// are planewaves, so only index differences matter, and tau is symmetric
+// under (m, m') -> (m', m) and (m, m') -> (-m, -m')).  For a cube the three
+// entries are interchangeable, so the integral is a function of the sorted
+// triple a <= b <= c of entry numbers:
+//   V(a, b, c) = (1/(sqrt(pi) L)) sum_q T_q(a) T_q(b) T_q(c),
+// T_q = W_q^(1/3) tau_q, which is Eq. 14 for any quadruple with those
+// entries.  There are E (E + 1) (E + 2) / 6 such triples: 6.5e7 (0.52 GB in
+// FP64) for the 9171-planewave basis, against N^4 = 7e15 integrals.  A box
+// reads one table per direction and keeps every (x, y, z) triple, E1^3
+// values.
+//
+// Layout.  Pairs (a, b) are numbered p = b (b + 1) / 2 + a (a <= b; a box
+// uses p = a E1 + b), and V(a, b, c) sits at c (c + 1) (c + 2) / 6 + p (a box:
+// c E1^2 + p): for each c the pairs are contiguous.
+//
+// Build.  For fixed c the values are a matrix product: V[p][c] =
+// sum_q P_q(p) T_q(c) with P_q(p) = T_q(a) T_q(b).  A workgroup takes 64
+// pairs and 64 values of c, stages 32 nodes of P and T at a time in LDS and
+// keeps a 4 x 4 block of sums per lane; node terms are added in node order.
+// Blocks whose every c lies below every b of their pairs are skipped (a
+// cube keeps c >= b only).
+//
+// Reconstruction.  Decode each quadruple (basis and fold map in LDS), sort
+// the cube's entries, read one value.  HBM traffic per quadruple: 16 bytes
+// of indices, 8 of the value, 8 out.  Orbits are numbered by ascending
+// m^2 + m'^2, so the values a stream reads most sit in the table's first
+// megabytes and mostly hit in L2; the quadruple and output streams are
+// loaded and stored non-temporally so that they do not evict them.
+#include <cmath>
+
+#include "pwc_internal.h"
+
+namespace pwc {
+namespace {
+
+constexpr int kVbThreads = 256;
+constexpr int kVbTile = 64;      // pairs and values of c per block
+constexpr int kVbChunk = 32;     // nodes per LDS stage
+
+struct ValBuildArgs {
+    const double *tab;    // [rows][Qp] folded W^(1/3) tau (a box: x, y, z tables stacked)
+    int Qp;
+    int E1;
+    int box;
+    int64_t npairs;
+    int ctiles;           // ceil(E1 / kVbTile)
+    double pref;
+    double *val;
+};
+
+__device__ __forceinline__ int64_t tri2(int64_t b) { return b * (b + 1) / 2; }
+__device__ __forceinline__ int64_t tri3(int64_t c) { return c * (c + 1) * (c + 2) / 6; }
+
+// The b of pair p (cube numbering p = b (b + 1) / 2 + a, 0 <= a <= b).
+__device__ __forceinline__ int pair_b(int64_t p) {
+    int b = static_cast<int>((sqrt(8.0 * static_cast<double>(p) + 1.0) - 1.0) * 0.5);
+    while (tri2(b + 1) <= p) ++b;       // guard the rounding of the square root
+    while (tri2(b) > p) --b;
+    return b;
+}
+
+// Lane (tx, ty) of a block owns pairs p0 + {2 tx, 2 tx + 1, 32 + 2 tx,
+// 33 + 2 tx} and values c0 + {2 ty, 2 ty + 1, 32 + 2 ty, 33 + 2 ty}, so that
+// each 128-bit LDS read of a 16-lane phase covers 256 contiguous bytes.
+__device__ __forceinline__ int sub_of(int t, int i) { return 2 * t + (i & 1) + 32 * (i >> 1); }
+
+__global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
+    __shared__ double2 Ps[kVbChunk][kVbTile / 2];
+    __shared__ double2 Cs[kVbChunk][kVbTile / 2];
+    const int64_t pt = blockIdx.x / a.ctiles;
+    const int ct = blockIdx.x % a.ctiles;
+    const int64_t p0 = pt * kVbTile;
+    const int c0 = ct * kVbTile;
+    if (!a.box && c0 + kVbTile - 1 < pair_b(p0)) return;   // every c below every b
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+
+    // Staging roles: lane tid loads pair / value sp = tid / 4, nodes
+    // (tid % 4) * 8 .. + 7 of each chunk.
+    const int sp = tid / 4, sq = (tid % 4) * 8;
+    const int64_t myp = p0 + sp;
+    const double *ra = nullptr, *rb = nullptr, *rc = nullptr;
+    if (myp < a.npairs) {
+        int pa, pb;
+        if (a.box) {
+            pa = static_cast<int>(myp / a.E1);
+            pb = a.E1 + static_cast<int>(myp % a.E1);
+        } else {
+            pb = pair_b(myp);
+            pa = static_cast<int>(myp - tri2(pb));
+        }
+        ra = a.tab + static_cast<size_t>(pa) * a.Qp;
+        rb = a.tab + static_cast<size_t>(pb) * a.Qp;
+    }
+    if (c0 + sp < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sp) * a.Qp;
+
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    double *ps = reinterpret_cast<double *>(Ps), *cs = reinterpret_cast<double *>(Cs);
+    for (int q0 = 0; q0 < a.Qp; q0 += kVbChunk) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = q0 + sq + k;
+            ps[(sq + k) * kVbTile + sp] = ra ? ra[q] * rb[q] : 0.0;
+            cs[(sq + k) * kVbTile + sp] = rc ? rc[q] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < kVbChunk; ++q) {
+            const double2 p01 = Ps[q][tx], p23 = Ps[q][16 + tx];
+            const double2 c01 = Cs[q][ty], c23 = Cs[q][16 + ty];
+            const double pv[4] = {p01.x, p01.y, p23.x, p23.y};
+            const double cv[4] = {c01.x, c01.y, c23.x, c23.y};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(pv[i], cv[j], acc[i][j]);
+        }
+    }
+
+    // The b of each of this lane's pairs (a box keeps every c): step up
+    // from the block's first pair, 64 pairs span few values of b.
+    int pb[4] = {0, 0, 0, 0};
+    if (!a.box) {
+        int b = pair_b(p0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = p0 + sub_of(tx, i);
+            while (tri2(b + 1) <= p) ++b;
+            pb[i] = b;
+        }
+    }
+    const int64_t E2 = static_cast<int64_t>(a.E1) * a.E1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = c0 + sub_of(ty, j);
+        if (c >= a.E1) continue;
+        const int64_t base = a.box ? c * E2 : tri3(c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = p0 + sub_of(tx, i);
+            if (p >= a.npairs || pb[i] > c) continue;
+            a.val[base + p] = acc[i][j] * a.pref;
+        }
+    }
+}
+
+constexpr int kVrThreads = 1024, kVrBatch = 4;
+
+struct RecValArgs {
+    const int4 *quads;
+    int64_t n;
+    const int32_t *basis;
+    int N;
+    const int32_t *fold;
+    int K, nd, E1, box;
+    const double *val;
+    double *out;
+    int *err;
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int bx(int v) { return (v << 24) >> 24; }
+__device__ __forceinline__ int by(int v) { return (v << 16) >> 24; }
+__device__ __forceinline__ int bz(int v) { return (v << 8) >> 24; }
+
+template <bool LDS_MAPS>
+__global__ __launch_bounds__(kVrThreads) void k_rec_values(RecValArgs a) {
+    extern __shared__ int32_t lds_maps[];
+    const int32_t *basis = a.basis;
+    const int16_t *lfold = reinterpret_cast<const int16_t *>(lds_maps + a.N);
+    if (LDS_MAPS) {
+        int16_t *f16 = reinterpret_cast<int16_t *>(lds_maps + a.N);
+        for (int i = threadIdx.x; i < a.N; i += kVrThreads) lds_maps[i] = a.basis[i];
+        for (int i = threadIdx.x; i < a.nd * a.nd; i += kVrThreads) f16[i] = static_cast<int16_t>(a.fold[i]);
+        __syncthreads();
+        basis = lds_maps;
+    }
+    const unsigned N = static_cast<unsigned>(a.N);
+    const int K = a.K, nd = a.nd;
+    const int64_t E2 = static_cast<int64_t>(a.E1) * a.E1;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kVrThreads * kVrBatch;
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kVrThreads * kVrBatch; b0 < a.n; b0 += stride) {
+        int4 q[kVrBatch];
+#pragma unroll
+        for (int k = 0; k < kVrBatch; ++k) {
+            const int64_t e = b0 + k * kVrThreads + threadIdx.x;
+            if (e < a.n) {   // streamed once
+                const v4i t = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
+                q[k] = make_int4(t.x, t.y, t.z, t.w);
+            }
+        }
+        double v[kVrBatch];
+#pragma unroll
+        for (int k = 0; k < kVrBatch; ++k) {
+            const int64_t e = b0 + k * kVrThreads + threadIdx.x;
+            v[k] = NAN;
+            if (e >= a.n) continue;
+            const int4 t = q[k];
+            if (static_cast<unsigned>(t.x) >= N || static_cast<unsigned>(t.y) >= N ||
+                static_cast<unsigned>(t.z) >= N || static_cast<unsigned>(t.w) >= N) {
+                atomicOr(a.err, 1);
+                continue;
+            }
+            const int ni = basis[t.x], nj = basis[t.y], nk = basis[t.z], nl = basis[t.w];
+            const int ix = (bx(nk) - bx(ni) + K) * nd + (bx(nl) - bx(nj) + K);
+            const int iy = (by(nk) - by(ni) + K) * nd + (by(nl) - by(nj) + K);
+            const int iz = (bz(nk) - bz(ni) + K) * nd + (bz(nl) - bz(nj) + K);
+            int fx = LDS_MAPS ? lfold[ix] : a.fold[ix];
+            int fy = LDS_MAPS ? lfold[iy] : a.fold[iy];
+            int fz = LDS_MAPS ? lfold[iz] : a.fold[iz];
+            int64_t idx;
+            if (a.box) {
+                idx = fz * E2 + static_cast<int64_t>(fx) * a.E1 + fy;
+            } else {
+                const int lo = min(fx, min(fy, fz)), hi = max(fx, max(fy, fz));
+                const int mid = fx + fy + fz - lo - hi;
+                idx = tri3(hi) + tri2(mid) + lo;
+            }
+            v[k] = a.val[idx];
+        }
+#pragma unroll
+        for (int k = 0; k < kVrBatch; ++k) {
+            const int64_t e = b0 + k * kVrThreads + threadIdx.x;
+            if (e < a.n) __builtin_nontemporal_store(v[k], a.out + e);
+        }
+    }
+}
+
+}  // namespace
+
+int64_t value_count(const Table &t) {
+    const int64_t e = t.E1;
+    return t.ndir == 3 ? e * e * e : e * (e + 1) * (e + 2) / 6;
+}
+
+hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
+    ValBuildArgs a{};
+    a.tab = t.d_tauF;
+    a.Qp = t.fl.Qp;
+    a.E1 = t.E1;
+    a.box = t.ndir == 3;
+    a.npairs = a.box ? static_cast<int64_t>(t.E1) * t.E1 : static_cast<int64_t>(t.E1) * (t.E1 + 1) / 2;
+    a.ctiles = (t.E1 + kVbTile - 1) / kVbTile;
+    a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
+    a.val = d_val;
+    const int64_t blocks = (a.npairs + kVbTile - 1) / kVbTile * a.ctiles;
+    if (blocks > int64_t(0x7fffffff) || a.Qp % kVbChunk) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_values_build, dim3(static_cast<unsigned>(blocks)), dim3(kVbThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_values(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    RecValArgs a{};
+    a.quads = reinterpret_cast<const int4 *>(d_quads);
+    a.n = n;
+    a.basis = t.d_basis;
+    a.N = static_cast<int>(t.N);
+    a.fold = t.d_fold;
+    a.K = t.K;
+    a.nd = t.nd;
+    a.E1 = t.E1;
+    a.box = t.ndir == 3;
+    a.val = t.d_val;
+    a.out = d_out;
+    a.err = t.d_err;
+    const size_t maps = sizeof(int32_t) * static_cast<size_t>(t.N) + sizeof(int16_t) * static_cast<size_t>(t.nd) * t.nd;
+    const size_t lds = (maps + 15) / 16 * 16;
+    const bool lds_maps = lds <= static_cast<size_t>(kLdsMax);
+    const int per_cu = lds_maps ? std::max(1, std::min(2, static_cast<int>(kLdsMax / lds))) : 2;
+    const int64_t tiles = (n + kVrThreads * kVrBatch - 1) / (kVrThreads * kVrBatch);
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>(tiles, int64_t(t.n_cu) * per_cu));
+    if (lds_maps) {
+        const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_rec_values<true>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   static_cast<int>(lds));
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_rec_values<true>, dim3(grid), dim3(kVrThreads), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(k_rec_values<false>, dim3(grid), dim3(kVrThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pwc

@@ -1,0 +1,188 @@
+"""The value table (pwc_table_build_values): every distinct integral evaluated
+once, then one read per quadruple.  Checked against the FP64 oracle and
+against the node-sum paths of the same table."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pw():
+    import torch
+    import paper_1502_08043_amd as pw
+    assert torch.cuda.is_available()
+    pw.lib()
+    return pw
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _entries(n2max):
+    # orbits of the (m, m') plane, nd = 4 nmax + 1, under the four-element
+    # fold group (Burnside: (nd^2 + 2 nd + 1) / 4 = (2 nmax + 1)^2)
+    return (2 * math.isqrt(n2max) + 1) ** 2
+
+
+@pytest.mark.parametrize("n2max,Q,n", [(9, 48, 60001), (40, 64, 200003), (169, 96, 2_000_001)])
+def test_values_match_oracle_and_node_sums(pw, n2max, Q, n):
+    import torch
+    o = P.setup(n2max, Q)
+    E = _entries(n2max)
+    with pw.Table(1.0, n2max, Q) as t:
+        built, nbytes = t.values_info()
+        assert not built and nbytes == 8 * E * (E + 1) * (E + 2) // 6
+        base = t.device_bytes
+        quads = workloads.lookup_stream(len(o["basis"]), min(len(o["basis"]), 925), n, seed=n2max)
+        dq = _dev(quads, torch.int32)
+        t.set_direct_max(0)
+        passes = t.reconstruct(dq)
+        t.set_direct_max(1 << 19)
+        direct = t.reconstruct(dq[:100_000])
+        t.build_values()
+        assert t.values_info() == (True, nbytes) and t.device_bytes == base + nbytes
+        got = t.reconstruct(dq)
+        mixed = t.reconstruct(dq, precision=pw.MIXED)    # node sums, not the values
+        t.sync()
+        rows = workloads.sample_rows(n, min(n, 20000), seed=3)
+        ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads[rows])
+        cs = P.cond_scale(o["tau"], o["W"], o["basis"], quads[rows])
+        err = P.worst_cond_err(got.cpu().numpy()[rows], ref, cs)
+        say(f"[values] n2max={n2max} Q={Q} E={E}: {nbytes / 2**20:.1f} MiB, n={n}, "
+            f"oracle err {err:.2e} (condition-aware)")
+        assert err < P.TOL_FP64
+        assert P.worst_cond_err(mixed.cpu().numpy()[rows], ref, cs) < P.TOL_MIXED
+        # every output against the node passes and the direct kernel
+        top = passes.abs().max().item()
+        assert (got - passes).abs().max().item() <= 1e-13 * top
+        assert (got[:100_000] - direct).abs().max().item() <= 1e-13 * top
+
+
+def test_values_rebuild_is_bitwise_and_free_falls_back(pw):
+    import torch
+    quads = workloads.uniform_quads(1045, 300_000, seed=9)
+    dq = _dev(quads, torch.int32)
+    with pw.Table(1.0, 40, 64) as t:
+        t.build_values()
+        t.build_values()                      # no-op
+        a = t.reconstruct(dq)
+        t.free_values()
+        assert t.values_info()[0] is False
+        b = t.reconstruct(dq)                 # node sums again
+        t.build_values()
+        c = t.reconstruct(dq)
+        t.sync()
+    assert torch.equal(a, c)
+    assert (a - b).abs().max().item() <= 1e-13 * b.abs().max().item()
+
+
+@pytest.mark.parametrize("n", [0, 1, 1023, 1025, 2048, 2049, 4097])
+def test_values_ragged_lengths(pw, n):
+    import torch
+    o = P.setup(9, 48)
+    quads = workloads.uniform_quads(123, max(n, 1), seed=n)[:n]
+    with pw.Table(1.0, 9, 48) as t:
+        t.build_values()
+        out = torch.full((n + 3,), -7.0, dtype=torch.float64, device="cuda")
+        if n:
+            t.reconstruct(_dev(quads, torch.int32), out=out[:n])
+        else:
+            t.reconstruct(torch.empty((0, 4), dtype=torch.int32, device="cuda"), out=out[:0])
+        t.sync()
+        got = out.cpu().numpy()
+    assert np.all(got[n:] == -7.0)            # nothing written past the end
+    if n:
+        ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads)
+        cs = P.cond_scale(o["tau"], o["W"], o["basis"], quads)
+        assert P.worst_cond_err(got[:n], ref, cs) < P.TOL_FP64
+
+
+def test_values_out_of_range_index(pw):
+    import torch
+    quads = workloads.uniform_quads(123, 5000, seed=2)
+    bad = quads.copy()
+    bad[17, 2] = 123
+    bad[4000, 0] = -1
+    with pw.Table(1.0, 9, 48) as t:
+        t.build_values()
+        ref = t.reconstruct(_dev(quads, torch.int32))
+        t.sync()
+        got = t.reconstruct(_dev(bad, torch.int32))
+        with pytest.raises(pw.PwcError) as ei:
+            t.sync()
+        assert ei.value.status == pw.ERR_RANGE
+        t.sync()                               # the error word was cleared
+    g = got.cpu().numpy()
+    assert np.isnan(g[17]) and np.isnan(g[4000])
+    keep = np.ones(5000, bool)
+    keep[[17, 4000]] = False
+    assert np.array_equal(g[keep], ref.cpu().numpy()[keep])
+
+
+@pytest.mark.parametrize("n2max,Q,sides", [(9, 48, (1.0, 1.3, 0.8)), (40, 64, (2.0, 1.0, 0.5))])
+def test_values_box(pw, n2max, Q, sides):
+    import torch
+    b = oracle.enumerate_basis(n2max)
+    beta, W, _ = oracle.default_mesh(Q)
+    L0, rho, taus = oracle.box_tables(beta, 2 * math.isqrt(n2max), sides)
+    E1 = _entries(n2max)
+    quads = workloads.uniform_quads(len(b), 100_001, seed=5)
+    with pw.Table.box(*sides, n2max, Q) as t:
+        assert t.values_info()[1] == 8 * E1 ** 3
+        t.set_direct_max(0)
+        passes = t.reconstruct(_dev(quads, torch.int32))
+        t.build_values()
+        got = t.reconstruct(_dev(quads, torch.int32))
+        t.sync()
+    rows = workloads.sample_rows(len(quads), 20000, seed=4)
+    ref = oracle.reconstruct(taus, W, b, quads[rows], L=L0)
+    K = 2 * math.isqrt(n2max)
+    q = quads[rows].astype(np.int64)
+    m, mp = b[q[:, 2]] - b[q[:, 0]] + K, b[q[:, 3]] - b[q[:, 1]] + K
+    prod = np.abs(W)[:, None] * np.ones((1, len(q)))
+    for d in range(3):
+        prod = prod * np.abs(taus[d][:, m[:, d], mp[:, d]])
+    cs = prod.sum(axis=0) / (math.sqrt(math.pi) * L0)
+    err = P.worst_cond_err(got.cpu().numpy()[rows], ref, cs)
+    say(f"[values] box {sides} n2max={n2max}: oracle err {err:.2e}")
+    assert err < P.TOL_FP64
+    assert (got - passes).abs().max().item() <= 1e-13 * passes.abs().max().item()
+
+
+def test_values_full_size_lookup_stream(pw):
+    """The 1e8-quadruple stream on the 9171-planewave table: sampled outputs
+    against the oracle, every output against the node passes."""
+    import torch
+    w = workloads.C4_STREAM
+    o = P.setup(w.n2max, w.n_nodes)
+    N = len(o["basis"])
+    M = int(((o["basis"].astype(np.int64) ** 2).sum(1) <= w.n2occ).sum())
+    assert (N, M) == (9171, 925)
+    quads = workloads.lookup_stream(N, M, w.n_quads, w.seed)
+    dq = _dev(quads, torch.int32)
+    with pw.Table(w.L, w.n2max, w.n_nodes) as t:
+        passes = t.reconstruct(dq)
+        t.build_values()
+        got = t.reconstruct(dq)
+        t.sync()
+    rows = workloads.sample_rows(w.n_quads, 20000, seed=11)
+    ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads[rows], L=w.L)
+    cs = P.cond_scale(o["tau"], o["W"], o["basis"], quads[rows], L=w.L)
+    err = P.worst_cond_err(got[torch.from_numpy(rows).cuda()].cpu().numpy(), ref, cs)
+    dev = (got - passes).abs().max().item() / passes.abs().max().item()
+    say(f"[values] C4 1e8: oracle err {err:.2e}, max |values - passes| / max {dev:.1e}")
+    assert err < P.TOL_FP64 and dev <= 1e-13
