@@ -151,6 +151,18 @@ PWC_API pwc_status pwc_mesh_default(int n_nodes, pwc_mesh *out);
 PWC_API pwc_status pwc_mesh_count(const pwc_mesh *mesh, int *n_nodes);
 
 /*
+ * Host-only set-up, no device needed.  pwc_mesh_build writes the nodes
+ * beta_q and weights W_q (q = 0..Q-1, FP64, Eqs. 11-13: Gauss-Legendre in
+ * beta on interval 1, in t = beta^{-1/2} on the tail) that a table of box side
+ * L (the reference length of a box) built with `mesh` uses; PWC_ERR_ARG for an
+ * invalid mesh or L <= 0.  pwc_basis_enumerate writes *N and, unless h_n is
+ * NULL, the canonical basis |n|^2 <= n2max ([N][3] int32, ascending
+ * (|n|^2, n_x, n_y, n_z)); 1 <= n2max <= PWC_MAX_N2MAX.
+ */
+PWC_API pwc_status pwc_mesh_build(const pwc_mesh *mesh, double L, double *h_beta, double *h_W);
+PWC_API pwc_status pwc_basis_enumerate(int n2max, int32_t *h_n, int64_t *N);
+
+/*
  * Build the tables for a cube of side L > 0 (pwc_table_create_box for a
  * rectangular box) and the basis |n|^2 <= n2max
  * (1 <= n2max <= PWC_MAX_N2MAX) on the mesh `mesh` (NULL: the default mesh

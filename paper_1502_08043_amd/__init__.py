@@ -78,6 +78,8 @@ def lib():
             "pwc_table_set_layout": (i32, [vp, i32, i32]),
             "pwc_table_set_direct_max": (i32, [vp, i64]),
             "pwc_table_build_values": (i32, [vp, vp]),
+            "pwc_mesh_build": (i32, [ctypes.POINTER(Mesh), dbl, vp, vp]),
+            "pwc_basis_enumerate": (i32, [i32, vp, ctypes.POINTER(i64)]),
             "pwc_table_values_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
             "pwc_table_free_values": (i32, [vp]),
             "pwc_basis": (i32, [vp, vp]),
@@ -124,6 +126,26 @@ def _dev_ptr(t, dtype, name):
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def mesh_points(mesh, L=1.0):
+    """Host-only: the (beta, W) nodes and weights a table of side L uses with this mesh."""
+    Q = ctypes.c_int()
+    _check(lib().pwc_mesh_count(ctypes.byref(mesh), ctypes.byref(Q)), "pwc_mesh_count")
+    beta, W = np.empty(Q.value), np.empty(Q.value)
+    _check(lib().pwc_mesh_build(ctypes.byref(mesh), float(L), beta.ctypes.data_as(ctypes.c_void_p),
+                                W.ctypes.data_as(ctypes.c_void_p)), "pwc_mesh_build")
+    return beta, W
+
+
+def enumerate_basis(n2max):
+    """Host-only: the canonical basis |n|^2 <= n2max, int32 [N, 3]."""
+    N = ctypes.c_int64()
+    _check(lib().pwc_basis_enumerate(int(n2max), None, ctypes.byref(N)), "pwc_basis_enumerate")
+    out = np.empty((N.value, 3), dtype=np.int32)
+    _check(lib().pwc_basis_enumerate(int(n2max), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(N)),
+           "pwc_basis_enumerate")
+    return out
 
 
 def mesh_default(n_nodes):

@@ -465,6 +465,24 @@ pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int *n_node
     return PWC_OK;
 }
 
+pwc_status pwc_mesh_build(const pwc_mesh *mesh, double L, double *h_beta, double *h_W) {
+    if (!mesh || !(L > 0.0) || !std::isfinite(L) || !h_beta || !h_W) return PWC_ERR_ARG;
+    std::vector<double> beta, W;
+    int n1 = 0;
+    if (!pwc::build_mesh(*mesh, L, beta, W, &n1)) return PWC_ERR_ARG;
+    std::copy(beta.begin(), beta.end(), h_beta);
+    std::copy(W.begin(), W.end(), h_W);
+    return PWC_OK;
+}
+
+pwc_status pwc_basis_enumerate(int n2max, int32_t *h_n, int64_t *N) {
+    if (n2max < 1 || n2max > PWC_MAX_N2MAX || !N) return PWC_ERR_ARG;
+    const std::vector<int32_t> b = pwc::enumerate_basis(n2max);
+    *N = static_cast<int64_t>(b.size() / 3);
+    if (h_n) std::copy(b.begin(), b.end(), h_n);
+    return PWC_OK;
+}
+
 pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
     if (!t) return PWC_ERR_ARG;
     pwc::Table &tb = t->t;

@@ -10,22 +10,28 @@ namespace pwc {
 
 std::vector<int32_t> enumerate_basis(int n2max) {
     // Sec. II: keep every product planewave below the cutoff, |n|^2 <= n2max.
+    // The loops meet the vectors in ascending (x, y, z); a stable counting
+    // sort by |n|^2 then gives the canonical order (|n|^2, x, y, z).
     const int r = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
-    std::vector<std::array<int32_t, 4>> pts;
+    std::vector<int32_t> shell_start(static_cast<size_t>(n2max) + 2, 0);
     for (int x = -r; x <= r; ++x)
         for (int y = -r; y <= r; ++y)
             for (int z = -r; z <= r; ++z) {
                 const int n2 = x * x + y * y + z * z;
-                if (n2 <= n2max) pts.push_back({n2, x, y, z});
+                if (n2 <= n2max) ++shell_start[n2 + 1];
             }
-    std::sort(pts.begin(), pts.end());
-    std::vector<int32_t> out;
-    out.reserve(pts.size() * 3);
-    for (const auto &p : pts) {
-        out.push_back(p[1]);
-        out.push_back(p[2]);
-        out.push_back(p[3]);
-    }
+    for (int k = 0; k <= n2max; ++k) shell_start[k + 1] += shell_start[k];
+    std::vector<int32_t> out(static_cast<size_t>(shell_start[n2max + 1]) * 3);
+    for (int x = -r; x <= r; ++x)
+        for (int y = -r; y <= r; ++y)
+            for (int z = -r; z <= r; ++z) {
+                const int n2 = x * x + y * y + z * z;
+                if (n2 > n2max) continue;
+                int32_t *o = &out[static_cast<size_t>(shell_start[n2]++) * 3];
+                o[0] = x;
+                o[1] = y;
+                o[2] = z;
+            }
     return out;
 }
 
@@ -59,11 +65,14 @@ static void gauss_legendre_ext(int q, ext a, ext b, std::vector<ext> &x, std::ve
         // cos(pi (i + 3/4) / (q + 1/2)) and refined by Newton's method.
         ext z = std::cos(static_cast<ext>(M_PI) * (i + 0.75L) / (q + 0.5L));
         ext p = 0.0L, dp = 1.0L;
-        for (int it = 0; it < 100; ++it) {
+        // Newton converges quadratically: two more steps after the step has
+        // dropped below 1e-12 |z| reach the extended-precision root.
+        for (int it = 0, extra = -1; it < 100 && extra != 0; ++it) {
             legendre(q, z, &p, &dp);
             const ext step = p / dp;
             z -= step;
-            if (std::fabs(step) <= 1e-21L * std::fabs(z) + 1e-300L) break;
+            if (extra > 0) --extra;
+            else if (extra < 0 && std::fabs(step) <= 1e-12L * std::fabs(z) + 1e-300L) extra = 2;
         }
         if (q % 2 == 1 && i == q / 2) z = 0.0L;   // the middle root is exactly 0
         legendre(q, z, &p, &dp);

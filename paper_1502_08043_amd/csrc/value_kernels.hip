@@ -20,9 +20,10 @@
 // Build.  For fixed c the values are a matrix product: V[p][c] =
 // sum_q P_q(p) T_q(c) with P_q(p) = T_q(a) T_q(b).  A workgroup takes 64
 // pairs and 64 values of c, stages 32 nodes of P and T at a time in LDS and
-// keeps a 4 x 4 block of sums per lane; node terms are added in node order.
-// Blocks whose every c lies below every b of their pairs are skipped (a
-// cube keeps c >= b only).
+// runs the node sums on the FP64 matrix cores, four nodes per step in node
+// order.
+// A cube keeps c >= b only: blocks whose every c lies below every b of
+// their pairs are not launched.
 //
 // Reconstruction.  Decode each quadruple (basis and fold map in LDS), sort
 // the cube's entries, read one value.  HBM traffic per quadruple: 16 bytes
@@ -30,6 +31,7 @@
 // m^2 + m'^2, so the values a stream reads most sit in the table's first
 // megabytes and mostly hit in L2; the quadruple and output streams are
 // loaded and stored non-temporally so that they do not evict them.
+#include <algorithm>
 #include <cmath>
 
 #include "pwc_internal.h"
@@ -41,6 +43,8 @@ constexpr int kVbThreads = 256;
 constexpr int kVbTile = 64;      // pairs and values of c per block
 constexpr int kVbChunk = 32;     // nodes per LDS stage
 
+constexpr int kVbMaxCtiles = 64;    // c tiles of the largest table (E1 <= 4096)
+
 struct ValBuildArgs {
     const double *tab;    // [rows][Qp] folded W^(1/3) tau (a box: x, y, z tables stacked)
     int Qp;
@@ -48,6 +52,10 @@ struct ValBuildArgs {
     int box;
     int64_t npairs;
     int ctiles;           // ceil(E1 / kVbTile)
+    // Blocks are numbered c tile by c tile: c tile ct owns blocks
+    // first[ct] .. first[ct + 1] - 1, one per pair tile that has a pair with
+    // b <= the tile's last c (every pair tile for a box).
+    int first[kVbMaxCtiles + 1];
     double pref;
     double *val;
 };
@@ -63,20 +71,25 @@ __device__ __forceinline__ int pair_b(int64_t p) {
     return b;
 }
 
-// Lane (tx, ty) of a block owns pairs p0 + {2 tx, 2 tx + 1, 32 + 2 tx,
-// 33 + 2 tx} and values c0 + {2 ty, 2 ty + 1, 32 + 2 ty, 33 + 2 ty}, so that
-// each 128-bit LDS read of a 16-lane phase covers 256 contiguous bytes.
-__device__ __forceinline__ int sub_of(int t, int i) { return 2 * t + (i & 1) + 32 * (i >> 1); }
+using f64x4 = double __attribute__((ext_vector_type(4)));
 
+// Each of the block's four waves computes 32 values of c by 32 pairs as
+// 2 x 2 tiles of v_mfma_f64_16x16x4f64, D[i][j] += sum_k A[i][k] B[k][j]
+// over 4 nodes k per step: A = T rows of c (i), B = pair products of p (j).
+// Lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[4 r + l / 16][l % 16] in register r = 0..3: each output register of a
+// 16-lane group covers 16 consecutive pairs of one c, contiguous in the
+// table.
 __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
-    __shared__ double2 Ps[kVbChunk][kVbTile / 2];
-    __shared__ double2 Cs[kVbChunk][kVbTile / 2];
-    const int64_t pt = blockIdx.x / a.ctiles;
-    const int ct = blockIdx.x % a.ctiles;
-    const int64_t p0 = pt * kVbTile;
+    __shared__ double Ps[kVbChunk][kVbTile];
+    __shared__ double Cs[kVbChunk][kVbTile];
+    int ct = 0;
+    while (static_cast<int>(blockIdx.x) >= a.first[ct + 1]) ++ct;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x - a.first[ct]) * kVbTile;
     const int c0 = ct * kVbTile;
-    if (!a.box && c0 + kVbTile - 1 < pair_b(p0)) return;   // every c below every b
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wp = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int li = lane % 16, lk = lane / 16;
 
     // Staging roles: lane tid loads pair / value sp = tid / 4, nodes
     // (tid % 4) * 8 .. + 7 of each chunk.
@@ -97,60 +110,73 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
     }
     if (c0 + sp < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sp) * a.Qp;
 
-    double acc[4][4];
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    double *ps = reinterpret_cast<double *>(Ps), *cs = reinterpret_cast<double *>(Cs);
+    // The next chunk's rows are loaded into registers (8 nodes of each, as
+    // 16-byte reads) while the matrix cores work on the current one.
+    double2 xa[4], xb[4], xc[4];
+    auto fetch = [&](int q0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = q0 + sq + 2 * k;
+            xa[k] = ra ? *reinterpret_cast<const double2 *>(ra + q) : double2{0.0, 0.0};
+            xb[k] = ra ? *reinterpret_cast<const double2 *>(rb + q) : double2{0.0, 0.0};
+            xc[k] = rc ? *reinterpret_cast<const double2 *>(rc + q) : double2{0.0, 0.0};
+        }
+    };
+    fetch(0);
     for (int q0 = 0; q0 < a.Qp; q0 += kVbChunk) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int q = q0 + sq + k;
-            ps[(sq + k) * kVbTile + sp] = ra ? ra[q] * rb[q] : 0.0;
-            cs[(sq + k) * kVbTile + sp] = rc ? rc[q] : 0.0;
+        for (int k = 0; k < 4; ++k) {
+            Ps[sq + 2 * k][sp] = xa[k].x * xb[k].x;
+            Ps[sq + 2 * k + 1][sp] = xa[k].y * xb[k].y;
+            Cs[sq + 2 * k][sp] = xc[k].x;
+            Cs[sq + 2 * k + 1][sp] = xc[k].y;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < kVbChunk; ++q) {
-            const double2 p01 = Ps[q][tx], p23 = Ps[q][16 + tx];
-            const double2 c01 = Cs[q][ty], c23 = Cs[q][16 + ty];
-            const double pv[4] = {p01.x, p01.y, p23.x, p23.y};
-            const double cv[4] = {c01.x, c01.y, c23.x, c23.y};
+        if (q0 + kVbChunk < a.Qp) fetch(q0 + kVbChunk);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(pv[i], cv[j], acc[i][j]);
+        for (int k0 = 0; k0 < kVbChunk; k0 += 4) {
+            const double a0 = Cs[k0 + lk][wc + li], a1 = Cs[k0 + lk][wc + 16 + li];
+            const double b0 = Ps[k0 + lk][wp + li], b1 = Ps[k0 + lk][wp + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
 
-    // The b of each of this lane's pairs (a box keeps every c): step up
-    // from the block's first pair, 64 pairs span few values of b.
-    int pb[4] = {0, 0, 0, 0};
+    // This lane's two pairs and, for a cube, their b (values with c < b are
+    // not kept).
+    int64_t pp[2];
+    int pb[2] = {0, 0};
+    pp[0] = p0 + wp + li;
+    pp[1] = pp[0] + 16;
     if (!a.box) {
-        int b = pair_b(p0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t p = p0 + sub_of(tx, i);
-            while (tri2(b + 1) <= p) ++b;
-            pb[i] = b;
-        }
+        int b = pair_b(pp[0]);
+        pb[0] = b;
+        while (tri2(b + 1) <= pp[1]) ++b;
+        pb[1] = b;
     }
     const int64_t E2 = static_cast<int64_t>(a.E1) * a.E1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int c = c0 + sub_of(ty, j);
-        if (c >= a.E1) continue;
-        const int64_t base = a.box ? c * E2 : tri3(c);
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t p = p0 + sub_of(tx, i);
-            if (p >= a.npairs || pb[i] > c) continue;
-            a.val[base + p] = acc[i][j] * a.pref;
+        for (int r = 0; r < 4; ++r) {
+            const int c = c0 + wc + 16 * u + 4 * r + lk;
+            if (c >= a.E1) continue;
+            const int64_t base = a.box ? c * E2 : tri3(c);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                if (pp[v] >= a.npairs || pb[v] > c) continue;
+                a.val[base + pp[v]] = acc[u][v][r] * a.pref;
+            }
         }
-    }
 }
 
 constexpr int kVrThreads = 1024, kVrBatch = 4;
@@ -189,16 +215,26 @@ __global__ __launch_bounds__(kVrThreads) void k_rec_values(RecValArgs a) {
     const int K = a.K, nd = a.nd;
     const int64_t E2 = static_cast<int64_t>(a.E1) * a.E1;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kVrThreads * kVrBatch;
-    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * kVrThreads * kVrBatch; b0 < a.n; b0 += stride) {
-        int4 q[kVrBatch];
+    // The next batch's quadruples are loaded while this batch is decoded
+    // and its values read.
+    int4 qn[kVrBatch];
+    auto fetch = [&](int64_t b0) {
 #pragma unroll
         for (int k = 0; k < kVrBatch; ++k) {
             const int64_t e = b0 + k * kVrThreads + threadIdx.x;
             if (e < a.n) {   // streamed once
                 const v4i t = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
-                q[k] = make_int4(t.x, t.y, t.z, t.w);
+                qn[k] = make_int4(t.x, t.y, t.z, t.w);
             }
         }
+    };
+    int64_t b0 = static_cast<int64_t>(blockIdx.x) * kVrThreads * kVrBatch;
+    if (b0 < a.n) fetch(b0);
+    for (; b0 < a.n; b0 += stride) {
+        int4 q[kVrBatch];
+#pragma unroll
+        for (int k = 0; k < kVrBatch; ++k) q[k] = qn[k];
+        if (b0 + stride < a.n) fetch(b0 + stride);
         double v[kVrBatch];
 #pragma unroll
         for (int k = 0; k < kVrBatch; ++k) {
@@ -253,8 +289,17 @@ hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
     a.ctiles = (t.E1 + kVbTile - 1) / kVbTile;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.val = d_val;
-    const int64_t blocks = (a.npairs + kVbTile - 1) / kVbTile * a.ctiles;
-    if (blocks > int64_t(0x7fffffff) || a.Qp % kVbChunk) return hipErrorInvalidValue;
+    if (a.ctiles > kVbMaxCtiles || a.Qp % kVbChunk) return hipErrorInvalidValue;
+    int64_t blocks = 0;
+    for (int ct = 0; ct < a.ctiles; ++ct) {
+        a.first[ct] = static_cast<int>(blocks);
+        // pairs with b <= last c of the tile: p < (c_last + 1)(c_last + 2) / 2
+        const int64_t c_last = std::min<int64_t>((ct + 1) * kVbTile, t.E1) - 1;
+        const int64_t np = a.box ? a.npairs : std::min<int64_t>(a.npairs, (c_last + 1) * (c_last + 2) / 2);
+        blocks += (np + kVbTile - 1) / kVbTile;
+        if (blocks > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+    }
+    for (int ct = a.ctiles; ct <= kVbMaxCtiles; ++ct) a.first[ct] = static_cast<int>(blocks);
     hipLaunchKernelGGL(k_values_build, dim3(static_cast<unsigned>(blocks)), dim3(kVbThreads), 0, s, a);
     return hipGetLastError();
 }

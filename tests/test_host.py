@@ -1,0 +1,72 @@
+"""Host-side set-up of the library (no device): the canonical basis and the
+Laplace meshes, through pwc_basis_enumerate and pwc_mesh_build, against the
+oracle's independent implementations (oracle.enumerate_basis; Gauss-Legendre
+rules from mpmath at 34 digits)."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+@pytest.fixture(scope="module")
+def pw():
+    import paper_1502_08043_amd as pw
+    from paper_1502_08043_amd import build
+    import os
+    if not os.path.exists(pw.LIB_PATH):
+        build.build()
+    pw.lib()
+    return pw
+
+
+@pytest.mark.parametrize("n2max", [1, 2, 9, 36, 40, 169, 400, 624])
+def test_library_basis_is_the_oracle_basis(pw, n2max):
+    got = pw.enumerate_basis(n2max)
+    assert np.array_equal(got, oracle.enumerate_basis(n2max))
+
+
+def test_library_basis_shell_closings(pw):
+    # occupied spheres of Sec. III: basis sizes at the shell closings
+    closings = {1: 7, 2: 19, 3: 27, 4: 33, 9: 123, 36: 925, 169: 9171}
+    for n2, N in closings.items():
+        assert len(pw.enumerate_basis(n2)) == N
+
+
+# (kind, parameters) -> oracle rule; the library rounds an extended-precision
+# rule once, the oracle a 34-digit one, so they agree to within one ulp.
+@pytest.mark.parametrize("Q", [16, 48, 64, 96, 128, 176])
+def test_library_default_mesh_matches_oracle(pw, Q):
+    beta, W = pw.mesh_points(pw.mesh_default(Q))
+    rb, rw, _ = oracle.default_mesh(Q)
+    assert np.max(np.abs(beta - rb) / rb) <= 2.3e-16
+    assert np.max(np.abs(W - rw) / rw) <= 2.3e-16
+
+
+@pytest.mark.parametrize("q", [20, 90, 180])
+def test_library_two_interval_mesh_matches_oracle(pw, q):
+    beta, W = pw.mesh_points(pw.Mesh.two_interval(q))
+    rb, rw, _ = oracle.mesh1(q)
+    assert np.max(np.abs(beta - rb) / rb) <= 2.5e-16
+    assert np.max(np.abs(W - rw) / rw) <= 2.5e-16
+
+
+def test_library_fixed_alpha_mesh_scales_with_the_box(pw):
+    # alpha_c = 0.25 bohr^2 in a box of side 2: beta_c = 4 alpha_c / L^2 = 0.25
+    beta, W = pw.mesh_points(pw.Mesh.geometric(5, 8, alpha_c=0.25), L=2.0)
+    rb, rw, _ = oracle.mesh2(5, 8, beta_c=0.25)
+    assert np.max(np.abs(beta - rb) / rb) <= 2.3e-16
+    assert np.max(np.abs(W - rw) / rw) <= 2.3e-16
+
+
+def test_host_entry_points_reject_bad_arguments(pw):
+    import ctypes
+    N = ctypes.c_int64()
+    for n2 in (0, -1, 625):
+        assert pw.lib().pwc_basis_enumerate(n2, None, ctypes.byref(N)) == pw.ERR_ARG
+    m = pw.mesh_default(96)
+    out = np.empty(96)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    assert pw.lib().pwc_mesh_build(ctypes.byref(m), 0.0, p, p) == pw.ERR_ARG
+    bad = pw.Mesh.geometric(5, 8)
+    bad.ratio = 1.0
+    assert pw.lib().pwc_mesh_build(ctypes.byref(bad), 1.0, p, p) == pw.ERR_ARG
