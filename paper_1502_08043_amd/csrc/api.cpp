@@ -111,24 +111,26 @@ size_t carve(Table &t, size_t n_reps, char *base) {
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    // Host-formed inputs first (one upload covers them and the error words),
+    // then the kernel-written layouts; tauF .. diagHL hold zero padding.
     const size_t o_basis = take(sizeof(int32_t) * t.N);
     const size_t o_fold = take(sizeof(int32_t) * nd * nd);
     const size_t o_reps = take(sizeof(int32_t) * n_reps);
     const size_t o_beta = take(sizeof(double) * D * Q);
     const size_t o_W = take(sizeof(double) * Q);
     const size_t o_gl = take(sizeof(double) * 2 * kGlPanelPoints);
+    const size_t o_Wcbrt = take(sizeof(double) * Q);
+    const size_t o_Wdiag = take(sizeof(double) * Qd);
+    const size_t o_WdiagHL = take(sizeof(float2) * Qd);
+    const size_t o_err = take(sizeof(int) * 64);
     const size_t o_prim = take(sizeof(double) * D * Q * 2 * (K + 1));
     const size_t o_tau = take(sizeof(double) * D * Q * nd * nd);
     const size_t o_tauF = take(sizeof(double) * Qp * E);
     const size_t o_tauHL = take(sizeof(float2) * Qp * E);
-    const size_t o_Wcbrt = take(sizeof(double) * Q);
     const size_t o_diag = take(sizeof(double) * Qd * D * (K + 1));
     const size_t o_diagHL = take(sizeof(float2) * Qd * D * (K + 1));
-    const size_t o_Wdiag = take(sizeof(double) * Qd);
-    const size_t o_WdiagHL = take(sizeof(float2) * Qd);
     const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
     const size_t o_ktMX = take(sizeof(double) * static_cast<size_t>(t.kt_n));
-    const size_t o_err = take(sizeof(int) * 64);
     if (base) {
         t.d_basis = reinterpret_cast<int32_t *>(base + o_basis);
         t.d_fold = reinterpret_cast<int32_t *>(base + o_fold);
@@ -229,30 +231,35 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
         Wdiag[q] = t.h_W[q];
         WdiagHL[q] = split_hilo(t.h_W[q]);
     }
-    pwc_status st = PWC_OK;
-    auto up = [&](void *dst, const void *src, size_t bytes) {
-        if (st == PWC_OK && bytes)
-            st = from_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
-    };
-    // Padding slots of the node-chunked layouts must read as zero.
-    if (st == PWC_OK)
-        st = from_hip(hipMemsetAsync(t.d_tauF, 0,
-                                     reinterpret_cast<char *>(t.d_Wdiag) -
-                                         reinterpret_cast<char *>(t.d_tauF), s));
-    if (st == PWC_OK) st = from_hip(hipMemsetAsync(t.d_err, 0, sizeof(int) * 64, s));
-    up(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
-    up(t.d_fold, su.fold.data(), sizeof(int32_t) * su.fold.size());
-    up(t.d_reps, su.reps.data(), sizeof(int32_t) * su.reps.size());
     std::vector<double> beta_d(static_cast<size_t>(t.ndir) * Q);   // node of each direction
     for (int d = 0; d < t.ndir; ++d)
         for (int q = 0; q < Q; ++q) beta_d[static_cast<size_t>(d) * Q + q] = t.h_beta[q] / (t.rho[d] * t.rho[d]);
-    up(t.d_beta, beta_d.data(), sizeof(double) * beta_d.size());
-    up(t.d_W, t.h_W.data(), sizeof(double) * Q);
-    up(t.d_gl, gl.data(), sizeof(double) * gl.size());
-    up(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
-    up(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
-    up(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
-    if (h_tau) up(t.d_tau, h_tau, sizeof(double) * static_cast<size_t>(t.ndir) * Q * t.nd * t.nd);
+    // One host image of the input region (basis .. error words, zeros in the
+    // alignment gaps and the error words) and one upload.
+    char *dev0 = static_cast<char *>(t.d_block);
+    const size_t in_bytes = static_cast<size_t>(reinterpret_cast<char *>(t.d_prim) - dev0);
+    std::vector<char> img(in_bytes, 0);
+    auto put = [&](const void *dst, const void *src, size_t bytes) {
+        std::memcpy(img.data() + (static_cast<const char *>(dst) - dev0), src, bytes);
+    };
+    put(t.d_basis, packed.data(), sizeof(int32_t) * t.N);
+    put(t.d_fold, su.fold.data(), sizeof(int32_t) * su.fold.size());
+    put(t.d_reps, su.reps.data(), sizeof(int32_t) * su.reps.size());
+    put(t.d_beta, beta_d.data(), sizeof(double) * beta_d.size());
+    put(t.d_W, t.h_W.data(), sizeof(double) * Q);
+    put(t.d_gl, gl.data(), sizeof(double) * gl.size());
+    put(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
+    put(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
+    put(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
+    pwc_status st = from_hip(hipMemcpyAsync(dev0, img.data(), in_bytes, hipMemcpyHostToDevice, s));
+    // Padding slots of the node-chunked layouts (tauF .. diagHL) must read
+    // as zero; the exchange kernel tables after them are written whole.
+    char *pad_end = t.d_ktab64 ? reinterpret_cast<char *>(t.d_ktab64) : dev0 + t.bytes;
+    if (st == PWC_OK)
+        st = from_hip(hipMemsetAsync(t.d_tauF, 0, static_cast<size_t>(pad_end - reinterpret_cast<char *>(t.d_tauF)), s));
+    if (h_tau && st == PWC_OK)
+        st = from_hip(hipMemcpyAsync(t.d_tau, h_tau, sizeof(double) * static_cast<size_t>(t.ndir) * Q * t.nd * t.nd,
+                                     hipMemcpyHostToDevice, s));
     if (st == PWC_OK) st = from_hip(launch_table_build(t, s, h_tau != nullptr));
     if (st == PWC_OK) st = from_hip(launch_ktab_build(t, s));
     // The host staging vectors die with this frame: wait for the stream.
