@@ -193,8 +193,14 @@ PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_
 PWC_API pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int n_nodes,
                                         const pwc_mesh *mesh, void *stream, pwc_table **out);
 
-/* Free a table and its device memory.  NULL is accepted. */
+/*
+ * Free a table.  NULL is accepted.  Its device blocks (and its value table)
+ * go to a per-device cache of the library, after a wait for the device, and
+ * later tables of the same device reuse them; the cache keeps at most 4 GiB
+ * and pwc_release_cached_memory returns all of it to the device.
+ */
 PWC_API pwc_status pwc_table_destroy(pwc_table *t);
+PWC_API pwc_status pwc_release_cached_memory(void);
 
 /*
  * Sizes of a table: basis size N, nmax = floor(sqrt(n2max)), node count Q and

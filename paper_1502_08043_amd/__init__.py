@@ -82,6 +82,7 @@ def lib():
             "pwc_basis_enumerate": (i32, [i32, vp, ctypes.POINTER(i64)]),
             "pwc_table_values_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
             "pwc_table_free_values": (i32, [vp]),
+            "pwc_release_cached_memory": (i32, []),
             "pwc_basis": (i32, [vp, vp]),
             "pwc_mesh_nodes": (i32, [vp, vp, vp]),
             "pwc_table_copy": (i32, [vp, vp, vp]),
@@ -126,6 +127,11 @@ def _dev_ptr(t, dtype, name):
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def release_cached_memory():
+    """Return the device blocks the library keeps from freed tables."""
+    _check(lib().pwc_release_cached_memory(), "pwc_release_cached_memory")
 
 
 def mesh_points(mesh, L=1.0):

@@ -95,12 +95,88 @@ float2 split_hilo(double v) {
 
 namespace pwc {
 
+// Device blocks of released tables and value tables are kept for later
+// tables of the same device: allocating and releasing a 0.5 GB value table
+// costs about 0.1 ms each way.  At most kCacheBytes are kept; a block is
+// reused for a request of at least half its size.
+namespace {
+std::mutex g_cache_mu;
+struct CachedBlock {
+    int device;
+    void *p;
+    size_t bytes;
+};
+std::vector<CachedBlock> g_cache;   // oldest first
+size_t g_cache_total = 0;
+constexpr size_t kCacheBytes = size_t(4) << 30;
+
+void release_cached(int device) {   // device < 0: every device; caller holds the lock
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+        if (device >= 0 && it->device != device) {
+            ++it;
+            continue;
+        }
+        (void)hipFree(it->p);
+        g_cache_total -= it->bytes;
+        it = g_cache.erase(it);
+    }
+}
+}  // namespace
+
+hipError_t dev_alloc(size_t bytes, void **p, size_t *got) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto best = g_cache.end();
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
+            if (it->device == dev && it->bytes >= bytes && it->bytes / 2 <= bytes &&
+                (best == g_cache.end() || it->bytes < best->bytes))
+                best = it;
+        if (best != g_cache.end()) {
+            *p = best->p;
+            *got = best->bytes;
+            g_cache_total -= best->bytes;
+            g_cache.erase(best);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {   // give the cached blocks back and try once more
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            release_cached(dev);
+        }
+        e = hipMalloc(p, bytes);
+    }
+    *got = bytes;
+    return e;
+}
+
+void dev_release(void *p, size_t bytes) {
+    if (!p) return;
+    // Work in flight may still read the block: wait for the device first, as
+    // hipFree would.
+    (void)hipDeviceSynchronize();
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.push_back({dev, p, bytes});
+    g_cache_total += bytes;
+    while (g_cache_total > kCacheBytes && !g_cache.empty()) {
+        (void)hipFree(g_cache.front().p);
+        g_cache_total -= g_cache.front().bytes;
+        g_cache.erase(g_cache.begin());
+    }
+}
+
 void free_table(Table &t) {
-    if (t.d_block) (void)hipFree(t.d_block);
+    dev_release(t.d_block, t.block_bytes);
     t.d_block = nullptr;
-    if (t.d_val) (void)hipFree(t.d_val);
+    dev_release(t.d_val, t.val_alloc);
     t.d_val = nullptr;
-    t.val_bytes = 0;
+    t.val_bytes = t.val_alloc = 0;
 }
 
 // Carve the table's single device allocation.  With base == nullptr only the
@@ -200,7 +276,7 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
 }
 
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau) {
-    hipError_t e = hipMalloc(&t.d_block, t.bytes);
+    hipError_t e = dev_alloc(t.bytes, &t.d_block, &t.block_bytes);
     if (e != hipSuccess) {
         t.d_block = nullptr;
         return from_hip(e);
@@ -495,20 +571,22 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
     pwc::Table &tb = t->t;
     if (tb.d_val) return PWC_OK;
     const size_t bytes = sizeof(double) * static_cast<size_t>(pwc::value_count(tb));
-    double *d = nullptr;
-    if (hipMalloc(&d, bytes) != hipSuccess) {
+    void *d = nullptr;
+    size_t got = 0;
+    if (pwc::dev_alloc(bytes, &d, &got) != hipSuccess) {
         (void)hipGetLastError();
         return PWC_ERR_NOMEM;
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t err = pwc::launch_values_build(tb, d, s);
+    hipError_t err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
-        (void)hipFree(d);
+        pwc::dev_release(d, got);
         return from_hip(err);
     }
-    tb.d_val = d;
+    tb.d_val = static_cast<double *>(d);
     tb.val_bytes = bytes;
+    tb.val_alloc = got;
     return PWC_OK;
 }
 
@@ -521,9 +599,15 @@ pwc_status pwc_table_values_info(const pwc_table *t, int *built, size_t *bytes) 
 
 pwc_status pwc_table_free_values(pwc_table *t) {
     if (!t) return PWC_ERR_ARG;
-    if (t->t.d_val) (void)hipFree(t->t.d_val);
+    pwc::dev_release(t->t.d_val, t->t.val_alloc);
     t->t.d_val = nullptr;
-    t->t.val_bytes = 0;
+    t->t.val_bytes = t->t.val_alloc = 0;
+    return PWC_OK;
+}
+
+pwc_status pwc_release_cached_memory(void) {
+    std::lock_guard<std::mutex> lk(pwc::g_cache_mu);
+    pwc::release_cached(-1);
     return PWC_OK;
 }
 

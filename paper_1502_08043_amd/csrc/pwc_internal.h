@@ -109,6 +109,8 @@ struct Table {
     // its own allocation; nullptr until built.
     double *d_val = nullptr;
     size_t val_bytes = 0;
+    size_t val_alloc = 0;           // bytes of the block holding the values (may be larger)
+    size_t block_bytes = 0;         // bytes of the block holding d_block
 };
 
 // api.cpp: table set-up in two phases.  plan_table forms the basis, mesh,
@@ -123,6 +125,10 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
 // then not recomputed), or nullptr.
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau = nullptr);
 void free_table(Table &t);
+// Device blocks of tables and value tables, through a small per-device cache
+// of released blocks (dev_release waits for the device first).
+hipError_t dev_alloc(size_t bytes, void **p, size_t *got);
+void dev_release(void *p, size_t bytes);
 
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau);

@@ -186,3 +186,29 @@ def test_values_full_size_lookup_stream(pw):
     dev = (got - passes).abs().max().item() / passes.abs().max().item()
     say(f"[values] C4 1e8: oracle err {err:.2e}, max |values - passes| / max {dev:.1e}")
     assert err < P.TOL_FP64 and dev <= 1e-13
+
+
+def test_cached_blocks_are_reused_safely(pw):
+    """Freed tables leave their device blocks to later tables; a table built
+    into a reused block gives bitwise the same results."""
+    import torch
+    quads = _dev(workloads.lookup_stream(9171, 925, 500_000, seed=21), torch.int32)
+    with pw.Table(1.0, 169, 96) as t:
+        t.build_values()
+        first = t.reconstruct(quads)
+        t.sync()
+    with pw.Table(1.0, 40, 64) as s:           # another table in between
+        s.build_values()
+        s.reconstruct(quads[:1000] % 1045)
+        s.sync()
+    with pw.Table(2.0, 169, 96) as t:          # same sizes: reuses the blocks
+        t.build_values()
+        half = t.reconstruct(quads)
+        t.sync()
+    with pw.Table(1.0, 169, 96) as t:
+        t.build_values()
+        again = t.reconstruct(quads)
+        t.sync()
+    pw.release_cached_memory()
+    assert torch.equal(first, again)
+    assert (2.0 * half - first).abs().max().item() <= 1e-15 * first.abs().max().item()
