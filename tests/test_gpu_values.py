@@ -212,3 +212,68 @@ def test_cached_blocks_are_reused_safely(pw):
     pw.release_cached_memory()
     assert torch.equal(first, again)
     assert (2.0 * half - first).abs().max().item() <= 1e-15 * first.abs().max().item()
+
+
+def test_values_largest_cutoff_wide_indices_and_global_maps(pw):
+    """n2max = 624 (65,117 PW, E = 2401): 2.3e9 values (18.5 GB) indexed past
+    2^31, and a basis too large for LDS, so the decode reads its maps from
+    global memory.  Quadruples with (m, m') = (48, 48) in x read the table's
+    last entries."""
+    import torch
+    o = P.setup(624, 16)
+    b = o["basis"]
+    where = {tuple(v): i for i, v in enumerate(b.tolist())}
+    far = [where[(-24, 0, 0)], where[(24, 0, 0)], where[(0, 0, 0)], where[(0, 7, 0)]]
+    # n_k - n_i = (48, 0, 0) and n_l - n_j = (48, 0, 0): the last orbit in x
+    crafted = np.array([[far[0], far[0], far[1], far[1]],
+                        [far[0], far[2], far[1], far[3]],
+                        [far[2], far[0], far[3], far[1]]], dtype=np.int32)
+    quads = np.concatenate([workloads.uniform_quads(len(b), 200_000, seed=77), crafted])
+    E = _entries(624)
+    dq = _dev(quads, torch.int32)
+    with pw.Table(1.0, 624, 16) as t:
+        nvals = t.values_info()[1] // 8
+        assert nvals == E * (E + 1) * (E + 2) // 6 and nvals > 2 ** 31
+        t.set_direct_max(0)
+        passes = t.reconstruct(dq)
+        t.build_values()
+        got = t.reconstruct(dq)
+        t.sync()
+    rows = np.concatenate([workloads.sample_rows(200_000, 5000, seed=5), np.arange(200_000, 200_003)])
+    ref = oracle.reconstruct(o["tau"], o["W"], b, quads[rows])
+    cs = P.cond_scale(o["tau"], o["W"], b, quads[rows])
+    g = got.cpu().numpy()
+    err = P.worst_cond_err(g[rows], ref, cs)
+    say(f"[values] n2max=624 Q=16 E={E}: {nvals} values, oracle err {err:.2e}")
+    assert err < P.TOL_FP64
+    assert (got - passes).abs().max().item() <= 1e-13 * passes.abs().max().item()
+
+
+def test_values_full_size_box(pw):
+    """A 9171-planewave box: all 729^3 direction triples (3.1 GB)."""
+    import torch
+    sides = (1.0, 1.5, 0.75)
+    b = oracle.enumerate_basis(169)
+    beta, W, _ = oracle.default_mesh(96)
+    L0, rho, taus = oracle.box_tables(beta, 26, sides)
+    quads = workloads.lookup_stream(9171, 925, 1_000_000, seed=6)
+    dq = _dev(quads, torch.int32)
+    with pw.Table.box(*sides, 169, 96) as t:
+        assert t.values_info()[1] == 8 * 729 ** 3
+        t.set_direct_max(0)
+        passes = t.reconstruct(dq)
+        t.build_values()
+        got = t.reconstruct(dq)
+        t.sync()
+    rows = workloads.sample_rows(len(quads), 10000, seed=8)
+    ref = oracle.reconstruct(taus, W, b, quads[rows], L=L0)
+    q = quads[rows].astype(np.int64)
+    m, mp = b[q[:, 2]] - b[q[:, 0]] + 26, b[q[:, 3]] - b[q[:, 1]] + 26
+    prod = np.abs(W)[:, None] * np.ones((1, len(q)))
+    for d in range(3):
+        prod = prod * np.abs(taus[d][:, m[:, d], mp[:, d]])
+    cs = prod.sum(axis=0) / (math.sqrt(math.pi) * L0)
+    err = P.worst_cond_err(got.cpu().numpy()[rows], ref, cs)
+    say(f"[values] box {sides} 9171 PW: oracle err {err:.2e}")
+    assert err < P.TOL_FP64
+    assert (got - passes).abs().max().item() <= 1e-13 * passes.abs().max().item()
