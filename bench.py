@@ -47,6 +47,7 @@ import numpy as np  # noqa: E402
 import workloads  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6                     # MI355X FP64 vector, dense
+FP32_PEAK_TFLOPS = 157.3                    # MI355X FP32 vector, dense
 HBM_PEAK_GBPS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1502_08043_amd", "csrc")
 # kernel source -> committed counter summary of its kernel on the lookup stream
@@ -341,6 +342,18 @@ def main():
         "hbm_algorithmic_GBps": 20.0 * n / (pass_ms * 1e-3) / 1e9,
         "whole_call_TFLOPs": 4.0 * Q * n / (legs["fp64_node_sums"]["reconstruct_ms"] * 1e-3) / 1e12,
         "kernel_source_sha256_16": kernel_hash("passes")}
+    # The split-FP32 steady pass, counted the same way (4 algorithmic flops per
+    # node term) against the FP32 vector peak; a float-float node term takes
+    # about 16 FP32 instructions.
+    mlay = legs["mixed"]["layout"]
+    msteady = legs["mixed"]["pass_ms"][1:] or legs["mixed"]["pass_ms"]
+    mpass_ms = float(np.mean(msteady))
+    mflops = 4.0 * mlay["nodes_per_pass"] * n
+    m_tf = mflops / (mpass_ms * 1e-3) / 1e12
+    mixed_pass = {"kernel": f"k_rec_pass<FF, G={mlay['lanes']}, W={mlay['words']}> steady node pass",
+                  "achieved": m_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": m_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": mpass_ms,
+                  "lds_read_TBps": 3 * 8 * mlay["nodes_per_pass"] * n / (mpass_ms * 1e-3) / 1e12}
 
     serving = None
     if not args.no_serve:
@@ -417,6 +430,7 @@ def main():
         "roofline": roofline,
         "value_build": value_build,
         "node_pass_roofline": node_pass_roofline,
+        "mixed_pass": mixed_pass,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
