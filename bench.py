@@ -124,6 +124,59 @@ def pmc_workload():
           f"passes {kernel_hash('passes')}", flush=True)
 
 
+def fixed_error_leg(pw, w, quads, n, steps, warmup, target=1e-9):
+    """Throughput at equal total error: the smallest default-mesh Q whose
+    integrals are within `target` (absolute, L = 1) of the converged mesh
+    (Q = 176, 8 x 21 + 8 nodes) on a sample of the stream, then both
+    precisions timed at that Q.  Rounding (about 1e-13 on either path) is far
+    below the target, so the quadrature error decides Q."""
+    import torch
+    half = n // 2
+    rows = torch.cat([torch.arange(500_000), half + torch.arange(500_000)]).cuda()
+    sample = quads[rows].contiguous()
+    with pw.Table(w.L, w.n2max, 176) as t:
+        t.build_values()
+        ref = t.reconstruct(sample)
+        t.sync()
+    errs = {}
+    q_star = None
+    for Q in (48, 56, 64, 72, 80, 88, 96, 112, 128):
+        with pw.Table(w.L, w.n2max, Q) as t:
+            t.build_values()
+            got = t.reconstruct(sample)
+            t.sync()
+        errs[Q] = (got - ref).abs().max().item()
+        if q_star is None and errs[Q] <= target:
+            q_star = Q
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    occ = torch.arange(925, dtype=torch.int32, device="cuda")
+    eout = torch.empty(2, dtype=torch.float64, device="cuda")
+    rates = {}
+    for name, prec, values in (("fp64", pw.FP64, True), ("mixed", pw.MIXED, False)):
+        def step():
+            t = pw.Table(w.L, w.n2max, q_star)
+            if values:
+                t.build_values()
+            t.reconstruct(quads, out, precision=prec)
+            t.energies_async(occ, None, prec, eout)
+            t.sync()
+            t.close()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        rates[name] = n * steps / (time.perf_counter() - t0)
+    return {"target_abs_error": target, "reference_Q": 176,
+            "sample": "1e6 quadruples of the stream (first 5e5 of each half)",
+            "max_abs_error_vs_Q176": {str(k): v for k, v in errs.items()}, "Q": q_star,
+            "fp64_value_table_integrals_per_s": rates["fp64"],
+            "mixed_node_sums_integrals_per_s": rates["mixed"],
+            "mixed_vs_fp64": rates["mixed"] / rates["fp64"]}
+
+
 def serving_leg(pw, n_requests):
     """Poisson request stream over (L, cutoff, Q) keys; p50/p99 at 80% load."""
     import torch
@@ -355,6 +408,11 @@ def main():
                   "frac": m_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": mpass_ms,
                   "lds_read_TBps": 3 * 8 * mlay["nodes_per_pass"] * n / (mpass_ms * 1e-3) / 1e12}
 
+    fixed_error = fixed_error_leg(pw, w, quads, n, args.steps, args.warmup)
+    log(f"[bench] fixed error 1e-9: Q = {fixed_error['Q']}, FP64 value table "
+        f"{fixed_error['fp64_value_table_integrals_per_s']:.4g}/s, mixed "
+        f"{fixed_error['mixed_node_sums_integrals_per_s']:.4g}/s; errors {fixed_error['max_abs_error_vs_Q176']}")
+
     serving = None
     if not args.no_serve:
         log(f"[bench] serving leg: {args.serve_requests} requests")
@@ -392,6 +450,15 @@ def main():
             got = out[k][torch.from_numpy(rows).cuda()].cpu().numpy()
             errs[k] = {"max_abs": float(np.max(np.abs(got - ref))),
                        "max_condition_aware": float(np.max(np.abs(got[::100] - ref[::100]) / scale))}
+        # quadrature error of the timed mesh: the oracle on the converged mesh
+        # (Q = 176) for a subsample, against the FP64 result
+        sub2 = rows[:: max(1, len(rows) // 20000)]
+        beta_c, W_c, _ = oracle.default_mesh(176)
+        tau_c = oracle.tau_table(beta_c, 2 * int(math.isqrt(w.n2max)))
+        ref_c = oracle.reconstruct(tau_c, W_c, basis64, quads_h[sub2], nthreads=threads)
+        got_c = out["fp64"][torch.from_numpy(sub2).cuda()].cpu().numpy()
+        errs["fp64_vs_converged_Q176"] = {"max_abs": float(np.max(np.abs(got_c - ref_c))),
+                                          "sample": len(sub2)}
         cpu = {"value": sample / t_rec, "unit": "integrals/s", "cores": threads, "kind": "oracle",
                "sample": f"{sample} quadruples of the stream (first {sample // 2} of each half)",
                "table_build_s": t_tab, "gpu_error_vs_oracle": errs}
@@ -431,6 +498,7 @@ def main():
         "value_build": value_build,
         "node_pass_roofline": node_pass_roofline,
         "mixed_pass": mixed_pass,
+        "fixed_error": fixed_error,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
