@@ -21,9 +21,9 @@
 // sum_q P_q(p) T_q(c) with P_q(p) = T_q(a) T_q(b).  A workgroup takes 64
 // pairs and 64 values of c, stages 32 nodes of P and T at a time in LDS and
 // runs the node sums on the FP64 matrix cores, four nodes per step in node
-// order.
-// A cube keeps c >= b only: blocks whose every c lies below every b of
-// their pairs are not launched.
+// order; the next chunk's rows are read into registers while they work.  A
+// cube keeps c >= b only: blocks whose every c lies below every b of their
+// pairs are not launched.
 //
 // Reconstruction.  Decode each quadruple (basis and fold map in LDS), sort
 // the cube's entries, read one value.  HBM traffic per quadruple: 16 bytes
