@@ -3,12 +3,31 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "pwc_internal.h"
 
 namespace pwc {
 
+namespace {
+// The basis, the fold map and the Gauss-Legendre unit rules are pure
+// functions of n2max, K and q; tables of one process mostly share them, so
+// each is formed once and copied out afterwards.
+std::mutex g_memo_mu;
+std::map<int, std::vector<int32_t>> g_basis_memo;
+}  // namespace
+
+static std::vector<int32_t> enumerate_basis_uncached(int n2max);
+
 std::vector<int32_t> enumerate_basis(int n2max) {
+    std::lock_guard<std::mutex> lk(g_memo_mu);
+    auto it = g_basis_memo.find(n2max);
+    if (it == g_basis_memo.end()) it = g_basis_memo.emplace(n2max, enumerate_basis_uncached(n2max)).first;
+    return it->second;
+}
+
+static std::vector<int32_t> enumerate_basis_uncached(int n2max) {
     // Sec. II: keep every product planewave below the cutoff, |n|^2 <= n2max.
     // The loops meet the vectors in ascending (x, y, z); a stable counting
     // sort by |n|^2 then gives the canonical order (|n|^2, x, y, z).
@@ -55,11 +74,13 @@ static void legendre(int q, ext z, ext *p, ext *dp) {
     *dp = q * (z * pk - pkm1) / ((z - 1.0L) * (z + 1.0L));   // (z^2 - 1) P' = q (z P_q - P_{q-1})
 }
 
-// q-point rule on [a, b] in extended precision, ascending nodes.
-static void gauss_legendre_ext(int q, ext a, ext b, std::vector<ext> &x, std::vector<ext> &w) {
-    x.assign(q, 0.0L);
-    w.assign(q, 0.0L);
-    const ext half = 0.5L * (b - a);
+// Roots z_i of P_q counted from z = 1 (i < (q + 1) / 2) and the weights
+// 2 / ((1 - z^2) P_q'(z)^2), extended precision.
+struct UnitRule {
+    std::vector<ext> z, w;
+};
+static UnitRule unit_rule(int q) {
+    UnitRule r;
     for (int i = 0; i < (q + 1) / 2; ++i) {
         // Root i of P_q counted from z = 1, started from the Tricomi estimate
         // cos(pi (i + 3/4) / (q + 1/2)) and refined by Newton's method.
@@ -76,7 +97,27 @@ static void gauss_legendre_ext(int q, ext a, ext b, std::vector<ext> &x, std::ve
         }
         if (q % 2 == 1 && i == q / 2) z = 0.0L;   // the middle root is exactly 0
         legendre(q, z, &p, &dp);
-        const ext wi = 2.0L / ((1.0L - z) * (1.0L + z) * dp * dp);
+        r.z.push_back(z);
+        r.w.push_back(2.0L / ((1.0L - z) * (1.0L + z) * dp * dp));
+    }
+    return r;
+}
+
+// q-point rule on [a, b] in extended precision, ascending nodes.
+static void gauss_legendre_ext(int q, ext a, ext b, std::vector<ext> &x, std::vector<ext> &w) {
+    static std::map<int, UnitRule> memo;   // guarded by g_memo_mu
+    UnitRule r;
+    {
+        std::lock_guard<std::mutex> lk(g_memo_mu);
+        auto it = memo.find(q);
+        if (it == memo.end()) it = memo.emplace(q, unit_rule(q)).first;
+        r = it->second;
+    }
+    x.assign(q, 0.0L);
+    w.assign(q, 0.0L);
+    const ext half = 0.5L * (b - a);
+    for (int i = 0; i < (q + 1) / 2; ++i) {
+        const ext z = r.z[i], wi = r.w[i];
         // Each node measured from its nearer end: a + h (1 - z) and b - h (1 - z).
         x[i] = a + half * (1.0L - z);
         x[q - 1 - i] = b - half * (1.0L - z);
@@ -146,7 +187,22 @@ bool build_mesh(const pwc_mesh &m, double L, std::vector<double> &beta, std::vec
     return static_cast<int>(beta.size()) == Q;
 }
 
+static void build_fold_uncached(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps);
+
 void build_fold(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps) {
+    static std::map<int, std::pair<std::vector<int32_t>, std::vector<int32_t>>> memo;   // g_memo_mu
+    std::lock_guard<std::mutex> lk(g_memo_mu);
+    auto it = memo.find(K);
+    if (it == memo.end()) {
+        std::vector<int32_t> f, r;
+        build_fold_uncached(K, f, r);
+        it = memo.emplace(K, std::make_pair(std::move(f), std::move(r))).first;
+    }
+    fold = it->second.first;
+    reps = it->second.second;
+}
+
+static void build_fold_uncached(int K, std::vector<int32_t> &fold, std::vector<int32_t> &reps) {
     const int nd = 2 * K + 1;
     fold.assign(static_cast<size_t>(nd) * nd, -1);
     reps.clear();
