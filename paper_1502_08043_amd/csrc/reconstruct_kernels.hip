@@ -41,10 +41,13 @@
 //           phase clash when their entry indices have equal parity;
 //   G = 1, W = 8: one lane per quadruple, word k ^ (g mod 8) at step k;
 //           lanes g and g + 8 of a phase clash on equal parity.
-// The groups that may clash hold quadruples of different stream position
-// (bit log2(8 / G) of their stream position e), so the decode
-// stores the entries of a quadruple in ascending parity for one of them and
-// descending for the other, which puts opposite halves together where it can.
+// The decode stores each quadruple's entries in ascending parity.  With
+// several lanes per quadruple, the groups that may clash hold quadruples of
+// different stream position (bit log2(8 / G) of e), and the stream word of
+// one of them is stored in descending order instead, which puts opposite
+// halves together where it can.  The one-lane passes pair their lanes
+// themselves (pair_lane): a wave's quadruples are dealt so that lanes g and
+// g + 8 hold complementary parity counts.
 // Each lane accumulates one partial sum per quadruple of its group (R); a
 // butterfly of DPP exchanges inside the 16-lane row halves the set at each
 // step, so that after log2(G) steps lane s holds the full sum of one
@@ -54,7 +57,8 @@
 // quadruple's packed word depends on its stream position only, so the first
 // pass of such a table runs in the one-lane layout (G = 1, W = 8) and
 // decodes the stream itself, the basis and fold map sitting in LDS beside
-// the slab; the later passes use the table's layout, for whose lane groups
+// the slab (without the lane pairing: that pass is bound by its instruction
+// count); the later passes use the table's layout, for whose lane groups
 // the decode orders the entries.  Other tables decode in k_decode first.
 #include <algorithm>
 #include <cmath>
