@@ -422,8 +422,8 @@ def test_concurrent_streams_share_one_table(pw, tables):
 @pytest.mark.parametrize("n2max,mesh", [(169, ("geometric", 11, 8)), (25, ("two_interval", 20))])
 def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
     """A saved and reloaded table has the same mesh and FP64 tables and gives
-    bitwise the same integrals (both paths, both precisions) and energies;
-    a damaged file is refused."""
+    bitwise the same integrals (value table, direct kernel and node passes;
+    both precisions) and energies; a damaged file is refused."""
     import torch
     m = pw.Mesh.geometric(mesh[1], mesh[2]) if mesh[0] == "geometric" else pw.Mesh.two_interval(mesh[1])
     path = tmp_path / "t.tab"
@@ -439,6 +439,8 @@ def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
         t.set_direct_max(DIRECT_DEFAULT)
         e_ref = t.energies(occ)
         tau_ref, mesh_ref = t.copy_tables(), t.mesh_nodes()
+        t.build_values()
+        v_ref = t.reconstruct(quads)
         t.sync()
     with pw.Table.load(path) as u:
         assert (u.L, u.n2max, u.Q) == (1.0, n2max, sum(1 for _ in mesh_ref[0]))
@@ -452,6 +454,8 @@ def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
                 assert torch.equal(got, ref[dm, prec])
         u.set_direct_max(DIRECT_DEFAULT)
         assert np.array_equal(u.energies(occ), e_ref)
+        u.build_values()                       # values are derived, not stored
+        assert torch.equal(u.reconstruct(quads), v_ref)
         u.sync()
     raw = bytearray(path.read_bytes())
     raw[200] ^= 1
