@@ -52,6 +52,10 @@ struct ValBuildArgs {
     int box;
     int64_t npairs;
     int ctiles;           // ceil(E1 / kVbTile)
+    // c tiles end at E1: tile ct covers c0 .. c0 + 63, c0 = c_off + 64 ct,
+    // c_off = E1 - 64 ctiles <= 0, so the one partial tile is the first,
+    // which the fewest pairs reach (a cube keeps c >= b).
+    int c_off;
     // Blocks are numbered c tile by c tile: c tile ct owns blocks
     // first[ct] .. first[ct + 1] - 1, one per pair tile that has a pair with
     // b <= the tile's last c (every pair tile for a box).
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
     int ct = 0;
     while (static_cast<int>(blockIdx.x) >= a.first[ct + 1]) ++ct;
     const int64_t p0 = static_cast<int64_t>(blockIdx.x - a.first[ct]) * kVbTile;
-    const int c0 = ct * kVbTile;
+    const int c0 = a.c_off + ct * kVbTile;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int wp = (wave & 1) * 32, wc = (wave >> 1) * 32;
     const int li = lane % 16, lk = lane / 16;
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
         ra = a.tab + static_cast<size_t>(pa) * a.Qp;
         rb = a.tab + static_cast<size_t>(pb) * a.Qp;
     }
-    if (c0 + sp < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sp) * a.Qp;
+    if (c0 + sp >= 0 && c0 + sp < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sp) * a.Qp;
 
     f64x4 acc[2][2];
 #pragma unroll
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = c0 + wc + 16 * u + 4 * r + lk;
-            if (c >= a.E1) continue;
+            if (c < 0 || c >= a.E1) continue;
             const int64_t base = a.box ? c * E2 : tri3(c);
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
@@ -290,11 +294,12 @@ hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.val = d_val;
     if (a.ctiles > kVbMaxCtiles || a.Qp % kVbChunk) return hipErrorInvalidValue;
+    a.c_off = t.E1 - a.ctiles * kVbTile;
     int64_t blocks = 0;
     for (int ct = 0; ct < a.ctiles; ++ct) {
         a.first[ct] = static_cast<int>(blocks);
         // pairs with b <= last c of the tile: p < (c_last + 1)(c_last + 2) / 2
-        const int64_t c_last = std::min<int64_t>((ct + 1) * kVbTile, t.E1) - 1;
+        const int64_t c_last = a.c_off + (ct + 1) * kVbTile - 1;
         const int64_t np = a.box ? a.npairs : std::min<int64_t>(a.npairs, (c_last + 1) * (c_last + 2) / 2);
         blocks += (np + kVbTile - 1) / kVbTile;
         if (blocks > int64_t(0x7fffffff)) return hipErrorInvalidValue;
