@@ -126,13 +126,14 @@ def test_bad_request_inside_a_batch_fails_alone(pw):
     good = torch.from_numpy(workloads.uniform_quads(123, 3000, seed=4)).cuda()
     bad = good.clone()
     bad[1234, 3] = 10 ** 6
-    big = torch.from_numpy(workloads.uniform_quads(9171, 4_000_000, seed=5)).cuda()
+    # long enough (about 1 ms) that the three small requests queue behind it
+    big = torch.from_numpy(workloads.uniform_quads(9171, 16_000_000, seed=5)).cuda()
     big_out = torch.empty(big.shape[0], dtype=torch.float64, device="cuda")
     outs = [torch.empty(3000, dtype=torch.float64, device="cuda") for _ in range(3)]
     with pw.Server(1 << 30, max_inflight=1) as srv:
         t0 = srv.submit_reconstruct(1.0, 9, good, torch.empty_like(outs[0]), n_nodes=48)
         srv.wait(t0)                                     # the 123-PW table is resident
-        tb = srv.submit_reconstruct(1.0, 169, big, big_out, n_nodes=96)   # build + 4e6 quads
+        tb = srv.submit_reconstruct(1.0, 169, big, big_out, n_nodes=96)   # build + 1.6e7 quads
         ts = [srv.submit_reconstruct(1.0, 9, q, o, n_nodes=48) for q, o in zip((good, bad, good), outs)]
         sts = [srv.wait(x).status for x in ts]
         assert srv.wait(tb).status == pw.OK
