@@ -390,10 +390,10 @@ PWC_API pwc_status pwc_sync(const pwc_table *t, void *stream);
  * Buffers named in a request (d_idx, d_f, d_out) are owned by the caller and
  * must stay valid and unmodified until pwc_server_wait (or a successful
  * pwc_server_poll) returns for its ticket.  If a kernel sees an index out of
- * range, the request reports PWC_ERR_RANGE (requests that run the node
- * passes or the pair sums share their table's error word, so such a report
- * may also reach a request that ran at the same time on that table; a
- * request served by the direct kernel has an error word of its own).
+ * range, the request reports PWC_ERR_RANGE.  Every request has an error word
+ * of its own (the table's word, which pwc_sync reads, is not touched), so
+ * the report reaches only the request that held the bad index, whatever
+ * else ran at the same time on that table.
  * ------------------------------------------------------------------------ */
 typedef enum { PWC_REQ_RECONSTRUCT = 0, PWC_REQ_ENERGIES = 1 } pwc_request_kind;
 

@@ -402,13 +402,20 @@ hipError_t launch_ktab_build(Table &t, hipStream_t s) {
 }
 
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f, int64_t M,
-                           pwc_precision p, pwc_pair_algo algo, double *d_out, hipStream_t s) {
+                           pwc_precision p, pwc_pair_algo algo, double *d_out, hipStream_t s,
+                           int *d_err) {
     if (M <= 0) {
         hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, d_out);
         return hipGetLastError();
     }
     const double pref = 1.0 / (std::sqrt(M_PI) * t.L);
+    int *const err_word = d_err ? d_err : t.d_err;
     hipError_t err;
+    // The partials are freed on every path once the kernels are enqueued.
+    auto finish = [&](double *partial, hipError_t e) {
+        const hipError_t ef = hipFreeAsync(partial, s);
+        return e != hipSuccess ? e : ef;
+    };
     if (algo != PWC_PAIR_NODESUM && t.kt_n > 0) {
         KtArgs a{};
         a.occ = d_occ;
@@ -421,7 +428,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         a.box = t.ndir == 3;
         a.n1 = t.K + 1;
         a.nT = static_cast<int>((M + kKtTile - 1) / kKtTile);
-        a.err = t.d_err;
+        a.err = err_word;
         const size_t lds = sizeof(double) * static_cast<size_t>(t.kt_n);
         const int per_cu = std::max(1, std::min(8, static_cast<int>((kLdsMax - 4096) / std::max<size_t>(lds, 1))));
         const int64_t upper = static_cast<int64_t>(a.nT) * (a.nT + 1) / 2;
@@ -430,13 +437,17 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         err = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * 2 * grid, s);
         if (err != hipSuccess) return err;
         a.partial = partial;
-        if ((err = set_lds(k_pair_ktab, lds)) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_pair_ktab, dim3(grid), dim3(kThreads), lds, s, a);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, grid, a.ktab,
-                           t.d_diag, t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, t.ndir, pref, d_out);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        return hipFreeAsync(partial, s);
+        err = set_lds(k_pair_ktab, lds);
+        if (err == hipSuccess) {
+            hipLaunchKernelGGL(k_pair_ktab, dim3(grid), dim3(kThreads), lds, s, a);
+            err = hipGetLastError();
+        }
+        if (err == hipSuccess) {
+            hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, grid, a.ktab,
+                               t.d_diag, t.d_Wdiag, t.K, t.dl.c, t.dl.nchunk, t.ndir, pref, d_out);
+            err = hipGetLastError();
+        }
+        return finish(partial, err);
     }
     if (algo == PWC_PAIR_KTABLE) return hipErrorInvalidValue;   // table too large for LDS
     PairArgs a{};
@@ -450,7 +461,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     a.nchunk = t.dl.nchunk;
     a.ndir = t.ndir;
     a.nT = static_cast<int>((M + kTile - 1) / kTile);
-    a.err = t.d_err;
+    a.err = err_word;
     const int nblk = a.nT * a.nT;
     double *partial = nullptr;
     err = hipMallocAsync(reinterpret_cast<void **>(&partial),
@@ -462,20 +473,22 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
     if (p == PWC_MIXED) {
         a.diag = t.d_diagHL;
         a.w = t.d_WdiagHL;
-        if ((err = set_lds(k_pair_mixed, lds)) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_pair_mixed, grid, dim3(kThreads), lds, s, a);
+        err = set_lds(k_pair_mixed, lds);
+        if (err == hipSuccess) hipLaunchKernelGGL(k_pair_mixed, grid, dim3(kThreads), lds, s, a);
     } else {
         a.diag = t.d_diag;
         a.w = t.d_Wdiag;
-        if ((err = set_lds(k_pair_f64, lds)) != hipSuccess) return err;
-        hipLaunchKernelGGL(k_pair_f64, grid, dim3(kThreads), lds, s, a);
+        err = set_lds(k_pair_f64, lds);
+        if (err == hipSuccess) hipLaunchKernelGGL(k_pair_f64, grid, dim3(kThreads), lds, s, a);
     }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, nblk,
-                       static_cast<const double *>(nullptr), t.d_diag, t.d_Wdiag, t.K, t.dl.c,
-                       t.dl.nchunk, t.ndir, pref, d_out);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    return hipFreeAsync(partial, s);
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(kThreads), 0, s, partial, nblk,
+                           static_cast<const double *>(nullptr), t.d_diag, t.d_Wdiag, t.K, t.dl.c,
+                           t.dl.nchunk, t.ndir, pref, d_out);
+        err = hipGetLastError();
+    }
+    return finish(partial, err);
 }
 
 }  // namespace pwc

@@ -137,9 +137,11 @@ hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau);
 int packed_entry_bytes(int E);
 // stage_ev: optional array of nchunk + 2 events (decode start, decode end,
 // end of every node pass), recorded for the first slab.
+// Every launch_* that checks indices raises d_err when given, else the
+// table's own error word.
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               double *d_out, pwc_precision p, hipStream_t s,
-                              hipEvent_t *stage_ev = nullptr);
+                              hipEvent_t *stage_ev = nullptr, int *d_err = nullptr);
 // direct_kernels.hip: small quadruple lists, up to kDirectMaxJobs requests
 // (any tables and precisions) per launch, jobs passed by value.
 struct DirectJob {
@@ -175,7 +177,7 @@ hipError_t launch_rec_values(const Table &t, const int32_t *d_quads, int64_t n, 
 hipError_t launch_ktab_build(Table &t, hipStream_t s);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,
                            int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
-                           hipStream_t s);
+                           hipStream_t s, int *d_err = nullptr);
 
 }  // namespace pwc
 

@@ -656,7 +656,7 @@ hipError_t run_layout(const PassArgs &a, const Table &t, const FoldLayout &fl, h
 int packed_entry_bytes(int E) { return E <= Pk32::kMaxE ? 4 : 8; }
 
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
-                              pwc_precision p, hipStream_t s, hipEvent_t *stage_ev) {
+                              pwc_precision p, hipStream_t s, hipEvent_t *stage_ev, int *d_err) {
     if (n <= 0) return hipSuccess;
     PassArgs a{};
     a.quads = reinterpret_cast<const int4 *>(d_quads);
@@ -673,7 +673,7 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.ord_g = (p == PWC_MIXED ? t.flm : t.fl).G;
     a.out = d_out;
-    a.err = t.d_err;
+    a.err = d_err ? d_err : t.d_err;
     const int64_t slab = std::min<int64_t>(n, kRecSlab);
     const size_t bytes = static_cast<size_t>(packed_entry_bytes(t.fl.E)) *
                          static_cast<size_t>((slab + kStreamPad - 1) / kStreamPad * kStreamPad);

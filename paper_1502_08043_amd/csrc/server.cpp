@@ -81,7 +81,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     double *h_e = nullptr;     // pinned [2]
     int *h_err = nullptr;      // pinned [kDirectMaxJobs]: error word per member
-    int *d_err = nullptr;      // device [kDirectMaxJobs]: the direct jobs' error words
+    int *d_err = nullptr;      // device [kDirectMaxJobs]: error word per member
     bool busy = false;
     bool direct = false;       // members share one direct-kernel launch
     std::vector<Member> members;
@@ -197,14 +197,7 @@ bool pwc_server::reap() {
             Member &m = s.members[i];
             pwc_result res{};
             res.status = from_hip(q);
-            if (res.status == PWC_OK && s.h_err[i]) {
-                res.status = PWC_ERR_RANGE;
-                if (!s.direct) {   // the node-pass kernels raise the table's own word
-                    const int zero = 0;
-                    (void)hipMemcpyAsync(m.tab->t->t.d_err, &zero, sizeof(int), hipMemcpyHostToDevice, s.stream);
-                    (void)hipStreamSynchronize(s.stream);
-                }
-            }
+            if (res.status == PWC_OK && s.h_err[i]) res.status = PWC_ERR_RANGE;
             if (m.r.kind == PWC_REQ_ENERGIES) {
                 res.e_h = s.h_e[0];
                 res.e_x = s.h_e[1];
@@ -366,19 +359,24 @@ bool pwc_server::admit() {
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int) * b.njobs, hipMemcpyDeviceToHost, s.stream);
         } else {
+            // The slot's own error word, not the table's: requests on one
+            // table may run in several slots at once.
             wait_ready(p.r);
+            if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int), s.stream);
             if (e == hipSuccess && p.r.kind == PWC_REQ_RECONSTRUCT) {
                 e = pwc::launch_reconstruct(t, p.r.d_idx, p.r.n, p.r.d_out,
-                                            static_cast<pwc_precision>(p.r.prec), s.stream);
+                                            static_cast<pwc_precision>(p.r.prec), s.stream,
+                                            nullptr, s.d_err);
             } else if (e == hipSuccess) {
                 e = pwc::launch_energies(t, p.r.d_idx, p.r.d_f, p.r.n,
                                          static_cast<pwc_precision>(p.r.prec),
-                                         static_cast<pwc_pair_algo>(p.r.algo), p.r.d_out, s.stream);
+                                         static_cast<pwc_pair_algo>(p.r.algo), p.r.d_out, s.stream,
+                                         s.d_err);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(s.h_e, p.r.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
             }
             if (e == hipSuccess)
-                e = hipMemcpyAsync(s.h_err, t.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
+                e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e == hipSuccess) {

@@ -195,3 +195,38 @@ def test_box_requests_match_the_library(pw):
         assert torch.equal(outs["cube"], tc.reconstruct(q))
         assert np.array_equal(e_box.cpu().numpy(), np.array(tb.energies(occ)))
         assert not torch.equal(outs["box"], outs["cube"])
+
+
+def test_bad_request_beside_a_good_one_on_the_same_table(pw):
+    """Two node-pass requests (above the direct-kernel size) on one table run
+    in two slots at once; the one with a bad index fails and the other does
+    not, as each slot raises its own error word."""
+    import torch
+    n = 700_000
+    good = torch.from_numpy(workloads.uniform_quads(1045, n, seed=21)).cuda()
+    bad = good.clone()
+    bad[n // 2, 0] = -5
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    occ = torch.arange(123, dtype=torch.int32, device="cuda")
+    occ_bad = occ.clone()
+    occ_bad[7] = 5000
+    e_good = torch.empty(2, dtype=torch.float64, device="cuda")
+    e_bad = torch.empty(2, dtype=torch.float64, device="cuda")
+    with pw.Server(1 << 30, max_inflight=4) as srv:
+        ts = [srv.submit_reconstruct(1.0, 40, q, o, n_nodes=64)
+              for q, o in zip((bad, good, bad, good), outs)]
+        te = [srv.submit_energies(1.0, 40, x, e, n_nodes=64, algo=pw.PAIR_NODESUM)
+              for x, e in ((occ_bad, e_bad), (occ, e_good))]
+        sts = [srv.wait(x).status for x in ts]
+        ste = [srv.wait(x).status for x in te]
+    assert sts == [pw.ERR_RANGE, pw.OK, pw.ERR_RANGE, pw.OK]
+    assert ste == [pw.ERR_RANGE, pw.OK]
+    with pw.Table(1.0, 40, 64) as tab:
+        ref = tab.reconstruct(good).cpu().numpy()
+        e_ref = np.array(tab.energies(occ, algo=pw.PAIR_NODESUM))
+    assert np.array_equal(outs[1].cpu().numpy(), ref) and np.array_equal(outs[3].cpu().numpy(), ref)
+    got = outs[0].cpu().numpy()
+    assert np.isnan(got[n // 2])
+    keep = np.arange(n) != n // 2
+    assert np.array_equal(got[keep], ref[keep])
+    assert np.array_equal(e_good.cpu().numpy(), e_ref)
