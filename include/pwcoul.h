@@ -453,7 +453,9 @@ PWC_API pwc_status pwc_server_submit(pwc_server *s, const pwc_request *r, uint64
  * PWC_ERR_BUSY if not yet, PWC_ERR_STATE for an unknown ticket. */
 PWC_API pwc_status pwc_server_poll(pwc_server *s, uint64_t ticket, pwc_result *res);
 
-/* Block until the request has finished; then as pwc_server_poll. */
+/* Block until the request has finished; then as pwc_server_poll.  Each
+ * ticket is collected once: a second thread waiting on the same ticket gets
+ * PWC_ERR_STATE when the first collects it. */
 PWC_API pwc_status pwc_server_wait(pwc_server *s, uint64_t ticket, pwc_result *res);
 
 /* Counters and latency percentiles since creation (or the last reset). */

@@ -459,7 +459,7 @@ pwc_status pwc_server_create(size_t hbm_budget_bytes, int max_inflight, pwc_serv
 pwc_status pwc_server_submit(pwc_server *s, const pwc_request *r, uint64_t *ticket) {
     if (!s || !r || !ticket) return PWC_ERR_ARG;
     if (r->kind != PWC_REQ_RECONSTRUCT && r->kind != PWC_REQ_ENERGIES) return PWC_ERR_ARG;
-    if (!(r->L > 0.0) || r->n2max < 1 || r->n2max > PWC_MAX_N2MAX || r->n < 0) return PWC_ERR_ARG;
+    if (!(r->L > 0.0) || !std::isfinite(r->L) || r->n2max < 1 || r->n2max > PWC_MAX_N2MAX || r->n < 0) return PWC_ERR_ARG;
     if (!(r->Ly >= 0.0) || !(r->Lz >= 0.0) || !std::isfinite(r->Ly) || !std::isfinite(r->Lz))
         return PWC_ERR_ARG;
     if (r->prec != PWC_FP64 && r->prec != PWC_MIXED) return PWC_ERR_ARG;
@@ -508,6 +508,7 @@ pwc_status pwc_server_poll(pwc_server *s, uint64_t ticket, pwc_result *res) {
     *res = it->second;
     s->finished.erase(it);
     s->known.erase(ticket);
+    s->cv_done.notify_all();
     return PWC_OK;
 }
 
@@ -515,10 +516,13 @@ pwc_status pwc_server_wait(pwc_server *s, uint64_t ticket, pwc_result *res) {
     if (!s || !res) return PWC_ERR_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
     if (!s->known.count(ticket)) return PWC_ERR_STATE;
-    s->cv_done.wait(lk, [&] { return s->finished.count(ticket) != 0; });
+    // A second waiter on the same ticket wakes when the first collects it.
+    s->cv_done.wait(lk, [&] { return s->finished.count(ticket) != 0 || !s->known.count(ticket); });
+    if (!s->known.count(ticket)) return PWC_ERR_STATE;
     *res = s->finished[ticket];
     s->finished.erase(ticket);
     s->known.erase(ticket);
+    s->cv_done.notify_all();
     return PWC_OK;
 }
 

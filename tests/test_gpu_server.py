@@ -230,3 +230,29 @@ def test_bad_request_beside_a_good_one_on_the_same_table(pw):
     keep = np.arange(n) != n // 2
     assert np.array_equal(got[keep], ref[keep])
     assert np.array_equal(e_good.cpu().numpy(), e_ref)
+
+
+def test_two_waiters_on_one_ticket(pw):
+    """A ticket is collected once; a second thread waiting on it returns
+    ERR_STATE instead of waiting forever."""
+    import threading
+    import torch
+    q = torch.from_numpy(workloads.uniform_quads(123, 1000, seed=3)).cuda()
+    out = torch.empty(1000, dtype=torch.float64, device="cuda")
+    got = []
+    with pw.Server(1 << 30, max_inflight=1) as srv:
+        t = srv.submit_reconstruct(1.0, 9, q, out, n_nodes=48)
+
+        def waiter():
+            try:
+                got.append(srv.wait(t).status)
+            except pw.PwcError as e:
+                got.append(e.status)
+
+        th = [threading.Thread(target=waiter) for _ in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join(timeout=60)
+        assert not any(x.is_alive() for x in th)
+    assert sorted(got) == sorted([pw.OK, pw.ERR_STATE])
