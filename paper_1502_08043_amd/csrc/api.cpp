@@ -98,7 +98,8 @@ namespace pwc {
 // Device blocks of released tables and value tables are kept for later
 // tables of the same device: allocating and releasing a 0.5 GB value table
 // costs about 0.1 ms each way.  At most kCacheBytes are kept; a block is
-// reused for a request of at least half its size.
+// reused for a request at most 1/8 smaller than it, so a table never holds
+// much more memory than it needs.
 namespace {
 std::mutex g_cache_mu;
 struct CachedBlock {
@@ -130,7 +131,7 @@ hipError_t dev_alloc(size_t bytes, void **p, size_t *got) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto best = g_cache.end();
         for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
-            if (it->device == dev && it->bytes >= bytes && it->bytes / 2 <= bytes &&
+            if (it->device == dev && it->bytes >= bytes && it->bytes - bytes <= bytes / 8 &&
                 (best == g_cache.end() || it->bytes < best->bytes))
                 best = it;
         if (best != g_cache.end()) {

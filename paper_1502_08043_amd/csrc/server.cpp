@@ -277,12 +277,17 @@ bool pwc_server::admit() {
                 any = true;
                 continue;
             }
+            // The block may be a cached one up to 1/8 larger than planned:
+            // count what the table holds, and evict for the difference.
             Cached c;
             c.t = h;
-            c.bytes = h->t.bytes;
+            c.bytes = std::max(h->t.bytes, h->t.block_bytes);
             it = cache.emplace(key, c).first;
             used += c.bytes;
             built = 1;
+            it->second.refs += 1;
+            if (used > budget) (void)make_room(0);
+            it->second.refs -= 1;
             publish_residency();
             std::lock_guard<std::mutex> lk(mu);
             ++builds;
