@@ -18,12 +18,14 @@
 // c E1^2 + p): for each c the pairs are contiguous.
 //
 // Build.  For fixed c the values are a matrix product: V[p][c] =
-// sum_q P_q(p) T_q(c) with P_q(p) = T_q(a) T_q(b).  A workgroup takes 64
-// pairs and 64 values of c, stages 32 nodes of P and T at a time in LDS and
+// sum_q P_q(p) T_q(c) with P_q(p) = T_q(a) T_q(b).  A workgroup takes 128
+// pairs and 64 values of c, stages 8 nodes of P and T at a time in LDS and
 // runs the node sums on the FP64 matrix cores, four nodes per step in node
-// order; the next chunk's rows are read into registers while they work.  A
-// cube keeps c >= b only: blocks whose every c lies below every b of their
-// pairs are not launched.
+// order; the next chunk's rows are read into registers while they work.
+// Short chunks keep the registers at four waves per SIMD, which the
+// matrix cores need to stay busy across the barriers.  A cube keeps c >= b
+// only: blocks whose every c lies below every b of their pairs are not
+// launched.
 //
 // Reconstruction.  Decode each quadruple (basis and fold map in LDS), sort
 // the cube's entries, read one value.  HBM traffic per quadruple: 16 bytes
@@ -40,8 +42,9 @@ namespace pwc {
 namespace {
 
 constexpr int kVbThreads = 256;
-constexpr int kVbTile = 64;      // pairs and values of c per block
-constexpr int kVbChunk = 32;     // nodes per LDS stage
+constexpr int kVbTile = 64;      // values of c per block
+constexpr int kVbTileP = 128;    // pairs per block
+constexpr int kVbChunk = 8;      // nodes per LDS stage
 
 constexpr int kVbMaxCtiles = 64;    // c tiles of the largest table (E1 <= 4096)
 
@@ -57,8 +60,8 @@ struct ValBuildArgs {
     // which the fewest pairs reach (a cube keeps c >= b).
     int c_off;
     // Blocks are numbered c tile by c tile: c tile ct owns blocks
-    // first[ct] .. first[ct + 1] - 1, one per pair tile that has a pair with
-    // b <= the tile's last c (every pair tile for a box).
+    // first[ct] .. first[ct + 1] - 1, one per tile of 128 pairs that has a
+    // pair with b <= the tile's last c (every pair tile for a box).
     int first[kVbMaxCtiles + 1];
     double pref;
     double *val;
@@ -77,27 +80,29 @@ __device__ __forceinline__ int pair_b(int64_t p) {
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
-// Each of the block's four waves computes 32 values of c by 32 pairs as
-// 2 x 2 tiles of v_mfma_f64_16x16x4f64, D[i][j] += sum_k A[i][k] B[k][j]
+// Each of the block's four waves computes 32 values of c by 64 pairs as
+// 2 x 4 tiles of v_mfma_f64_16x16x4f64, D[i][j] += sum_k A[i][k] B[k][j]
 // over 4 nodes k per step: A = T rows of c (i), B = pair products of p (j).
 // Lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16] and receives
 // D[4 r + l / 16][l % 16] in register r = 0..3: each output register of a
 // 16-lane group covers 16 consecutive pairs of one c, contiguous in the
 // table.
-__global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
-    __shared__ double Ps[kVbChunk][kVbTile];
+__global__ __launch_bounds__(kVbThreads, 4) void k_values_build(ValBuildArgs a) {
+    __shared__ double Ps[kVbChunk][kVbTileP];
     __shared__ double Cs[kVbChunk][kVbTile];
     int ct = 0;
     while (static_cast<int>(blockIdx.x) >= a.first[ct + 1]) ++ct;
-    const int64_t p0 = static_cast<int64_t>(blockIdx.x - a.first[ct]) * kVbTile;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x - a.first[ct]) * kVbTileP;
     const int c0 = a.c_off + ct * kVbTile;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wp = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int wp = (wave & 1) * 64, wc = (wave >> 1) * 32;
     const int li = lane % 16, lk = lane / 16;
 
-    // Staging roles: lane tid loads pair / value sp = tid / 4, nodes
-    // (tid % 4) * 8 .. + 7 of each chunk.
-    const int sp = tid / 4, sq = (tid % 4) * 8;
+    // Staging roles for each chunk: lane tid forms the products of pair
+    // sp = tid / 2 at nodes sq .. sq + 3, sq = (tid % 2) * 4, and copies row
+    // sc = tid / 4 of the c tile at nodes scq, scq + 1, scq = (tid % 4) * 2.
+    const int sp = tid / 2, sq = (tid % 2) * 4;
+    const int sc = tid / 4, scq = (tid % 4) * 2;
     const int64_t myp = p0 + sp;
     const double *ra = nullptr, *rb = nullptr, *rc = nullptr;
     if (myp < a.npairs) {
@@ -112,60 +117,69 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
         ra = a.tab + static_cast<size_t>(pa) * a.Qp;
         rb = a.tab + static_cast<size_t>(pb) * a.Qp;
     }
-    if (c0 + sp >= 0 && c0 + sp < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sp) * a.Qp;
+    if (c0 + sc >= 0 && c0 + sc < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sc) * a.Qp;
 
-    f64x4 acc[2][2];
+    f64x4 acc[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 4; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    // The next chunk's rows are loaded into registers (8 nodes of each, as
-    // 16-byte reads) while the matrix cores work on the current one.
-    double2 xa[4], xb[4], xc[4];
+    // The next chunk's rows are loaded into registers (16-byte reads) while
+    // the matrix cores work on the current one.
+    double2 xa[2], xb[2], xc;
     auto fetch = [&](int q0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 2; ++k) {
             const int q = q0 + sq + 2 * k;
             xa[k] = ra ? *reinterpret_cast<const double2 *>(ra + q) : double2{0.0, 0.0};
             xb[k] = ra ? *reinterpret_cast<const double2 *>(rb + q) : double2{0.0, 0.0};
-            xc[k] = rc ? *reinterpret_cast<const double2 *>(rc + q) : double2{0.0, 0.0};
         }
+        xc = rc ? *reinterpret_cast<const double2 *>(rc + q0 + scq) : double2{0.0, 0.0};
     };
     fetch(0);
     for (int q0 = 0; q0 < a.Qp; q0 += kVbChunk) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 2; ++k) {
             Ps[sq + 2 * k][sp] = xa[k].x * xb[k].x;
             Ps[sq + 2 * k + 1][sp] = xa[k].y * xb[k].y;
-            Cs[sq + 2 * k][sp] = xc[k].x;
-            Cs[sq + 2 * k + 1][sp] = xc[k].y;
         }
+        Cs[scq][sc] = xc.x;
+        Cs[scq + 1][sc] = xc.y;
         __syncthreads();
         if (q0 + kVbChunk < a.Qp) fetch(q0 + kVbChunk);
 #pragma unroll
         for (int k0 = 0; k0 < kVbChunk; k0 += 4) {
-            const double a0 = Cs[k0 + lk][wc + li], a1 = Cs[k0 + lk][wc + 16 + li];
-            const double b0 = Ps[k0 + lk][wp + li], b1 = Ps[k0 + lk][wp + 16 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            double av[2], bv[4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) av[u] = Cs[k0 + lk][wc + 16 * u + li];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bv[v] = Ps[k0 + lk][wp + 16 * v + li];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
         }
     }
 
-    // This lane's two pairs and, for a cube, their b (values with c < b are
+    // This lane's four pairs and, for a cube, their b (values with c < b are
     // not kept).
-    int64_t pp[2];
-    int pb[2] = {0, 0};
-    pp[0] = p0 + wp + li;
-    pp[1] = pp[0] + 16;
+    int64_t pp[4];
+    int pb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        pp[v] = p0 + wp + 16 * v + li;
+        pb[v] = 0;
+    }
     if (!a.box) {
         int b = pair_b(pp[0]);
-        pb[0] = b;
-        while (tri2(b + 1) <= pp[1]) ++b;
-        pb[1] = b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            while (tri2(b + 1) <= pp[v]) ++b;
+            pb[v] = b;
+        }
     }
     const int64_t E2 = static_cast<int64_t>(a.E1) * a.E1;
 #pragma unroll
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(kVbThreads) void k_values_build(ValBuildArgs a) {
             if (c < 0 || c >= a.E1) continue;
             const int64_t base = a.box ? c * E2 : tri3(c);
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
+            for (int v = 0; v < 4; ++v) {
                 if (pp[v] >= a.npairs || pb[v] > c) continue;
                 a.val[base + pp[v]] = acc[u][v][r] * a.pref;
             }
@@ -301,7 +315,7 @@ hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
         // pairs with b <= last c of the tile: p < (c_last + 1)(c_last + 2) / 2
         const int64_t c_last = a.c_off + (ct + 1) * kVbTile - 1;
         const int64_t np = a.box ? a.npairs : std::min<int64_t>(a.npairs, (c_last + 1) * (c_last + 2) / 2);
-        blocks += (np + kVbTile - 1) / kVbTile;
+        blocks += (np + kVbTileP - 1) / kVbTileP;
         if (blocks > int64_t(0x7fffffff)) return hipErrorInvalidValue;
     }
     for (int ct = a.ctiles; ct <= kVbMaxCtiles; ++ct) a.first[ct] = static_cast<int>(blocks);
