@@ -315,7 +315,7 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     t = pw.Table(w.L, w.n2max, w.n_nodes)
-    # the value table: its build (one launch; the call waits for it) and the reads
+    # the value table: its build (one launch) and the reads
     vb = []
     for _ in range(args.kernel_reps):
         t.free_values()

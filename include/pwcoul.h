@@ -253,8 +253,10 @@ PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
  * triple: E (E + 1) (E + 2) / 6 values for E folded entries (E = 729 for
  * nmax = 13: 6.5e7 values, 0.52 GB); a box has E1^3.
  * pwc_table_build_values evaluates each of them once by Eq. 14 over all
- * nodes (FP64, on `stream`, then waits) into a device allocation of its
- * own.  From then on pwc_reconstruct with PWC_FP64 reads one value per
+ * nodes (FP64) into a device allocation of its own, asynchronously on
+ * `stream`: work queued after it on that stream sees the values, work on
+ * another stream must wait for it first (an event or a synchronize).  From
+ * then on pwc_reconstruct with PWC_FP64 reads one value per
  * quadruple instead of summing nodes, for any n; PWC_MIXED keeps its node
  * sums.  The values agree with the node sums to rounding.  PWC_ERR_NOMEM if
  * the allocation fails (the table is then unchanged); a second call is a

@@ -258,7 +258,8 @@ class Table:
 
     def build_values(self, stream=None):
         """Evaluate every distinct integral once (the value table); FP64
-        reconstructions then read one value per quadruple.  Waits."""
+        reconstructions then read one value per quadruple.  Asynchronous on
+        the stream: later work on it sees the values."""
         _check(lib().pwc_table_build_values(self.handle, _stream(stream)), "pwc_table_build_values")
         self._refresh_bytes()
 

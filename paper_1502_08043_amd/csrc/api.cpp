@@ -579,8 +579,8 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
         return PWC_ERR_NOMEM;
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    // Stream-ordered: work queued after this call on `stream` sees the values.
+    const hipError_t err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
     if (err != hipSuccess) {
         pwc::dev_release(d, got);
         return from_hip(err);

@@ -277,3 +277,25 @@ def test_values_full_size_box(pw):
     say(f"[values] box {sides} 9171 PW: oracle err {err:.2e}")
     assert err < P.TOL_FP64
     assert (got - passes).abs().max().item() <= 1e-13 * passes.abs().max().item()
+
+
+def test_values_build_is_stream_ordered(pw):
+    """The build is asynchronous on its stream: a reconstruction queued after
+    it on the same stream, or on another stream that waits for it, reads the
+    finished values."""
+    import torch
+    quads = _dev(workloads.lookup_stream(1045, 123, 200_000, seed=31), torch.int32)
+    with pw.Table(1.0, 40, 64) as t:
+        ref = t.reconstruct(quads)                # node sums
+        t.sync()
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            t.build_values(stream=side)
+            same = t.reconstruct(quads, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        other = t.reconstruct(quads)
+        t.sync()
+        torch.cuda.synchronize()
+    tol = 1e-14 * ref.abs().max().item()
+    assert (same - ref).abs().max().item() <= tol
+    assert torch.equal(same, other)
