@@ -250,41 +250,66 @@ __device__ __forceinline__ int ktab_index(int a, int b, int c) {
     return c * (c + 1) * (c + 2) / 6 + b * (b + 1) / 2 + a;
 }
 
-// One thread per (a, b, c) of the cube.  A cube's directions share one
-// diagonal table, so only sorted triples are kept (a = the x entry); a box
-// keeps every triple, a from the x table, b from y and c from z, at
-// (a (K+1) + b) (K+1) + c.
+// kKtLanes lanes per kernel-table entry (a, b, c): lane j sums the node
+// slots j * per .. (j + 1) * per - 1 in node order, and a fixed butterfly
+// over the 16 lanes adds the partial sums; lane 0 writes.  A cube's
+// directions share one diagonal table, so only sorted triples are kept
+// (entry tri3(c) + tri2(b) + a); a box keeps every triple, a from the x
+// table, b from y and c from z, at (a (K+1) + b) (K+1) + c.
+constexpr int kKtLanes = 16;
+
 __global__ __launch_bounds__(kThreads) void k_ktab_build(const double *__restrict__ diag,
                                                         const float2 *__restrict__ diagHL,
                                                         const double *__restrict__ wd,
                                                         const float2 *__restrict__ wdHL, int K,
-                                                        int dc, int nchunk, int ndir,
+                                                        int dc, int nchunk, int ndir, int kt_n,
                                                         double *__restrict__ k64,
                                                         double *__restrict__ kmx) {
     const int n1 = K + 1;
-    const int id = blockIdx.x * kThreads + threadIdx.x;
-    if (id >= n1 * n1 * n1) return;
-    const int c = id / (n1 * n1), b = (id / n1) % n1, a = id % n1;
+    const int gid = blockIdx.x * kThreads + threadIdx.x;
+    const int e = gid / kKtLanes, j = gid % kKtLanes;
+    if (e >= kt_n) return;                    // whole 16-lane groups leave together
     const bool box = ndir == 3;
-    if (!box && (a > b || b > c)) return;
+    int a, b, c;
+    if (box) {
+        a = e / (n1 * n1);
+        b = (e / n1) % n1;
+        c = e % n1;
+    } else {
+        c = 0;
+        while (ktab_index(0, 0, c + 1) <= e) ++c;
+        const int r = e - ktab_index(0, 0, c);
+        b = 0;
+        while ((b + 1) * (b + 2) / 2 <= r) ++b;
+        a = r - b * (b + 1) / 2;
+    }
     const int ry = box ? n1 : 0, rz = box ? 2 * n1 : 0;   // direction rows in a chunk
+    const int slots = dc * nchunk;
+    const int per = (slots + kKtLanes - 1) / kKtLanes;
+    const int g1 = min(slots, (j + 1) * per);
     double s64 = 0.0;
     float sh = 0.0f, sl = 0.0f;
-    for (int ch = 0; ch < nchunk; ++ch) {
+    for (int g = j * per; g < g1; ++g) {
+        const int ch = g / dc, q = g % dc;
         const size_t row = static_cast<size_t>(ch) * ndir * n1;
-        for (int q = 0; q < dc; ++q) {
-            const double da = diag[(row + a) * dc + q], db = diag[(row + ry + b) * dc + q];
-            const double dcv = diag[(row + rz + c) * dc + q];
-            s64 = fma(da * db * dcv, wd[ch * dc + q], s64);
-            const float2 ha = diagHL[(row + a) * dc + q], hb = diagHL[(row + ry + b) * dc + q];
-            const float2 hc = diagHL[(row + rz + c) * dc + q], hw = wdHL[ch * dc + q];
-            ff_acc(sh, sl, ff_mul(ff_mul(ff_mul(ff{ha.x, ha.y}, ff{hb.x, hb.y}), ff{hc.x, hc.y}),
-                                  ff{hw.x, hw.y}));
-        }
+        const double da = diag[(row + a) * dc + q], db = diag[(row + ry + b) * dc + q];
+        const double dcv = diag[(row + rz + c) * dc + q];
+        s64 = fma(da * db * dcv, wd[g], s64);
+        const float2 ha = diagHL[(row + a) * dc + q], hb = diagHL[(row + ry + b) * dc + q];
+        const float2 hc = diagHL[(row + rz + c) * dc + q], hw = wdHL[g];
+        ff_acc(sh, sl, ff_mul(ff_mul(ff_mul(ff{ha.x, ha.y}, ff{hb.x, hb.y}), ff{hc.x, hc.y}),
+                              ff{hw.x, hw.y}));
     }
-    const int idx = box ? (a * n1 + b) * n1 + c : ktab_index(a, b, c);
-    k64[idx] = s64;
-    kmx[idx] = ff_to_double(sh, sl);
+#pragma unroll
+    for (int off = kKtLanes / 2; off > 0; off >>= 1) {
+        s64 += __shfl_xor(s64, off, kKtLanes);
+        const float oh = __shfl_xor(sh, off, kKtLanes), ol = __shfl_xor(sl, off, kKtLanes);
+        ff_acc(sh, sl, ff{oh, ol});
+    }
+    if (j == 0) {
+        k64[e] = s64;
+        kmx[e] = ff_to_double(sh, sl);
+    }
 }
 
 constexpr int kKtTile = 64;                      // 64 x 64 pairs per tile
@@ -393,11 +418,11 @@ hipError_t set_lds(Kern k, size_t bytes) {
 
 hipError_t launch_ktab_build(Table &t, hipStream_t s) {
     if (t.kt_n == 0) return hipSuccess;
-    const int n1 = t.K + 1;
-    const int blocks = (n1 * n1 * n1 + kThreads - 1) / kThreads;
+    const int64_t threads = static_cast<int64_t>(t.kt_n) * kKtLanes;
+    const int blocks = static_cast<int>((threads + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_ktab_build, dim3(blocks), dim3(kThreads), 0, s, t.d_diag, t.d_diagHL,
-                       t.d_Wdiag, t.d_WdiagHL, t.K, t.dl.c, t.dl.nchunk, t.ndir, t.d_ktab64,
-                       t.d_ktabMX);
+                       t.d_Wdiag, t.d_WdiagHL, t.K, t.dl.c, t.dl.nchunk, t.ndir, t.kt_n,
+                       t.d_ktab64, t.d_ktabMX);
     return hipGetLastError();
 }
 
