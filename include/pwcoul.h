@@ -169,9 +169,12 @@ PWC_API pwc_status pwc_basis_enumerate(int n2max, int32_t *h_n, int64_t *N);
  * for n_nodes).  If mesh is given, n_nodes must be 0 or equal its node count.
  * Basis, mesh and index maps are formed on the host in FP64; the 1-D
  * primitives and every table layout are computed by HIP kernels on `stream`
- * (FP64).  The call returns after the tables are complete.  The handle owns
- * all of its device memory (see pwc_table_info) and must be released with
- * pwc_table_destroy.  *out is NULL on failure.
+ * (FP64).  The call returns once that work is queued: every later call that
+ * takes the table and a stream first makes that stream wait for the table's
+ * construction, so the table may be used on any stream at once, with no
+ * synchronization by the caller.  The handle owns all of its device memory
+ * (see pwc_table_info) and must be released with pwc_table_destroy.  *out is
+ * NULL on failure.
  */
 PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_mesh *mesh,
                             void *stream, pwc_table **out);

@@ -173,11 +173,14 @@ void dev_release(void *p, size_t bytes) {
 }
 
 void free_table(Table &t) {
-    dev_release(t.d_block, t.block_bytes);
+    dev_release(t.d_block, t.block_bytes);   // waits for the device: the upload is done
     t.d_block = nullptr;
     dev_release(t.d_val, t.val_alloc);
     t.d_val = nullptr;
     t.val_bytes = t.val_alloc = 0;
+    if (t.ready) (void)hipEventDestroy(t.ready);
+    t.ready = nullptr;
+    t.h_img.reset();
 }
 
 // Carve the table's single device allocation.  With base == nullptr only the
@@ -315,7 +318,8 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
     // alignment gaps and the error words) and one upload.
     char *dev0 = static_cast<char *>(t.d_block);
     const size_t in_bytes = static_cast<size_t>(reinterpret_cast<char *>(t.d_prim) - dev0);
-    std::vector<char> img(in_bytes, 0);
+    auto img_p = std::make_shared<std::vector<char>>(in_bytes, 0);
+    std::vector<char> &img = *img_p;
     auto put = [&](const void *dst, const void *src, size_t bytes) {
         std::memcpy(img.data() + (static_cast<const char *>(dst) - dev0), src, bytes);
     };
@@ -328,6 +332,9 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
     put(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
     put(t.d_Wdiag, Wdiag.data(), sizeof(double) * Qd);
     put(t.d_WdiagHL, WdiagHL.data(), sizeof(float2) * Qd);
+    // The image stays with the table until pwc_table_destroy, which waits for
+    // the device, so the copy may still be in flight when this returns.
+    t.h_img = img_p;
     pwc_status st = from_hip(hipMemcpyAsync(dev0, img.data(), in_bytes, hipMemcpyHostToDevice, s));
     // Padding slots of the node-chunked layouts (tauF .. diagHL) must read
     // as zero; the exchange kernel tables after them are written whole.
@@ -339,10 +346,14 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
                                      hipMemcpyHostToDevice, s));
     if (st == PWC_OK) st = from_hip(launch_table_build(t, s, h_tau != nullptr));
     if (st == PWC_OK) st = from_hip(launch_ktab_build(t, s));
-    // The host staging vectors die with this frame: wait for the stream.
-    const pwc_status st_sync = from_hip(hipStreamSynchronize(s));
-    if (st == PWC_OK) st = st_sync;
-    if (st != PWC_OK) free_table(t);
+    if (st == PWC_OK) st = from_hip(hipEventCreateWithFlags(&t.ready, hipEventDisableTiming));
+    if (st == PWC_OK) st = from_hip(hipEventRecord(t.ready, s));
+    // h_tau is the caller's buffer: a loaded table waits for its copy.
+    if (st == PWC_OK && h_tau) st = from_hip(hipStreamSynchronize(s));
+    if (st != PWC_OK) {
+        (void)hipStreamSynchronize(s);
+        free_table(t);
+    }
     return st;
 }
 
@@ -450,8 +461,9 @@ pwc_status pwc_table_save(const pwc_table *t, const char *path) {
     std::vector<double> payload(2 * static_cast<size_t>(tb.Q) + ntau);
     std::memcpy(payload.data(), tb.h_beta.data(), sizeof(double) * tb.Q);
     std::memcpy(payload.data() + tb.Q, tb.h_W.data(), sizeof(double) * tb.Q);
-    const hipError_t e = hipMemcpy(payload.data() + 2 * tb.Q, tb.d_tau, sizeof(double) * ntau,
-                                   hipMemcpyDeviceToHost);
+    hipError_t e = tb.ready ? hipEventSynchronize(tb.ready) : hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpy(payload.data() + 2 * tb.Q, tb.d_tau, sizeof(double) * ntau, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
     TableFileHeader h{};
     std::memcpy(h.magic, kTableMagic, sizeof(h.magic));
@@ -580,7 +592,8 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     // Stream-ordered: work queued after this call on `stream` sees the values.
-    const hipError_t err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
+    hipError_t err = pwc::wait_ready(tb, s);
+    if (err == hipSuccess) err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
     if (err != hipSuccess) {
         pwc::dev_release(d, got);
         return from_hip(err);
@@ -671,8 +684,10 @@ pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_W) {
 pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
     if (!t || !d_dst) return PWC_ERR_ARG;
     const size_t bytes = sizeof(double) * t->t.ndir * t->t.Q * t->t.nd * t->t.nd;
-    return from_hip(hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice,
-                                   static_cast<hipStream_t>(stream)));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = pwc::wait_ready(t->t, s);
+    if (e != hipSuccess) return from_hip(e);
+    return from_hip(hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice, s));
 }
 
 pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n, double *d_out,
@@ -682,6 +697,8 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
+    const hipError_t ew = pwc::wait_ready(t->t, static_cast<hipStream_t>(stream));
+    if (ew != hipSuccess) return from_hip(ew);
     if (t->t.d_val && p == PWC_FP64)   // every distinct value is at hand: one read each
         return from_hip(pwc::launch_rec_values(t->t, d_quads, n, d_out, static_cast<hipStream_t>(stream)));
     if (n <= t->t.direct_max) {   // small list: four lanes per quadruple, no node passes
@@ -712,7 +729,7 @@ pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, i
     if (max_stages < stages) return PWC_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<hipEvent_t> ev(stages + 1, nullptr);
-    hipError_t e = hipSuccess;
+    hipError_t e = pwc::wait_ready(t->t, s);
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s, ev.data());
@@ -738,8 +755,10 @@ pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const doubl
     if (M > (1 << 17)) return PWC_ERR_ARG;   // pair-tile grid (M/32)^2 workgroups
     if ((reinterpret_cast<uintptr_t>(d_out) & 7) || (d_f && (reinterpret_cast<uintptr_t>(d_f) & 7)))
         return PWC_ERR_ARG;
-    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, algo, d_out,
-                                         static_cast<hipStream_t>(stream)));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = pwc::wait_ready(t->t, s);
+    if (e != hipSuccess) return from_hip(e);
+    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, algo, d_out, s));
 }
 
 pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
@@ -768,7 +787,8 @@ pwc_status pwc_sync(const pwc_table *t, void *stream) {
     if (!t) return PWC_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int flag = 0;
-    hipError_t e = hipMemcpyAsync(&flag, t->t.d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e = pwc::wait_ready(t->t, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, t->t.d_err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return from_hip(e);
     if (flag) {

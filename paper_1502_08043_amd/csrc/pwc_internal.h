@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -111,11 +112,23 @@ struct Table {
     size_t val_bytes = 0;
     size_t val_alloc = 0;           // bytes of the block holding the values (may be larger)
     size_t block_bytes = 0;         // bytes of the block holding d_block
+    // Recorded on the creating stream after the table kernels; every call
+    // that queues work on a stream waits for it first (wait_ready), so a
+    // table may be used on any stream as soon as pwc_table_create returns.
+    hipEvent_t ready = nullptr;
+    std::shared_ptr<const std::vector<char>> h_img;   // upload source, alive until destroy
 };
+
+// Order work queued next on stream s after the table's construction.
+inline hipError_t wait_ready(const Table &t, hipStream_t s) {
+    return t.ready ? hipStreamWaitEvent(s, t.ready, 0) : hipSuccess;
+}
 
 // api.cpp: table set-up in two phases.  plan_table forms the basis, mesh,
 // fold map and layouts on the host and sets t.bytes; build_table allocates,
-// uploads and runs the table kernels (waits for the stream).
+// uploads and queues the table kernels on the stream and records t.ready
+// (a loaded table, whose FP64 tables come from the caller's buffer, also
+// waits for the stream).
 struct TableSetup {
     std::vector<int32_t> fold, reps;
 };

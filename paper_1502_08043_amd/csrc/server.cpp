@@ -326,8 +326,10 @@ bool pwc_server::admit() {
         const pwc::Table &t = c.t->t;
         s.direct = p.r.kind == PWC_REQ_RECONSTRUCT && p.r.n <= t.direct_max;
         hipError_t e = hipSuccess;
-        // The caller's pending work on the request's buffers comes first.
-        auto wait_ready = [&](const pwc_request &r) {
+        // The table's construction (queued on the build stream) and the
+        // caller's pending work on the request's buffers come first.
+        auto wait_ready = [&](const pwc_request &r, const pwc::Table &tab) {
+            if (e == hipSuccess) e = pwc::wait_ready(tab, s.stream);
             if (e == hipSuccess && r.ready_event)
                 e = hipStreamWaitEvent(s.stream, static_cast<hipEvent_t>(r.ready_event), 0);
         };
@@ -357,7 +359,7 @@ bool pwc_server::admit() {
                 const Member &m = s.members[i];
                 b.job[i] = pwc::direct_job(m.tab->t->t, m.r.d_idx, m.r.n, m.r.d_out,
                                            static_cast<pwc_precision>(m.r.prec), s.d_err + i);
-                wait_ready(m.r);
+                wait_ready(m.r, m.tab->t->t);
             }
             if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int) * b.njobs, s.stream);
             if (e == hipSuccess) e = pwc::launch_direct(b, s.stream);
@@ -366,7 +368,7 @@ bool pwc_server::admit() {
         } else {
             // The slot's own error word, not the table's: requests on one
             // table may run in several slots at once.
-            wait_ready(p.r);
+            wait_ready(p.r, t);
             if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int), s.stream);
             if (e == hipSuccess && p.r.kind == PWC_REQ_RECONSTRUCT) {
                 e = pwc::launch_reconstruct(t, p.r.d_idx, p.r.n, p.r.d_out,

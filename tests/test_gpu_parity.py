@@ -419,6 +419,38 @@ def test_concurrent_streams_share_one_table(pw, tables):
     assert (b - ref).abs().max().item() < 1e-12
 
 
+def test_table_built_on_one_stream_is_used_at_once_on_others(pw, tables):
+    """pwc_table_create returns once its kernels are queued; each later call
+    makes its own stream wait for them, so a table created on a side stream
+    gives the same results on other streams with no synchronization between."""
+    import torch
+    ref_t = tables(169, 96)
+    q = _dev(workloads.lookup_stream(9171, 925, 1_000_000, seed=13), torch.int32)
+    occ = torch.arange(925, dtype=torch.int32, device="cuda")
+    ref = ref_t.reconstruct(q)
+    e_ref = np.array(ref_t.energies(occ))
+    torch.cuda.synchronize()
+    side, other = torch.cuda.Stream(), torch.cuda.Stream()
+    for values in (False, True):
+        with torch.cuda.stream(side):
+            t = pw.Table(1.0, 169, 96, stream=side)
+        with torch.cuda.stream(other):
+            if values:
+                t.build_values(stream=other)
+            a = t.reconstruct(q, stream=other)
+            e = torch.empty(2, dtype=torch.float64, device="cuda")
+            t.energies_async(occ, out=e, stream=other)
+        if values:                                 # the value build is ordered on `other` only
+            torch.cuda.current_stream().wait_stream(other)
+        b = t.reconstruct(q)                       # the default stream
+        torch.cuda.synchronize()
+        t.sync()
+        tol = 0.0 if not values else 1e-14 * ref.abs().max().item()
+        assert (a - ref).abs().max().item() <= tol and torch.equal(a, b)
+        assert np.array_equal(e.cpu().numpy(), e_ref)
+        t.close()
+
+
 @pytest.mark.parametrize("n2max,mesh", [(169, ("geometric", 11, 8)), (25, ("two_interval", 20))])
 def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
     """A saved and reloaded table has the same mesh and FP64 tables and gives
