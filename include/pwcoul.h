@@ -255,8 +255,10 @@ PWC_API pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words);
  * share one table, so its distinct integrals are indexed by the sorted entry
  * triple: E (E + 1) (E + 2) / 6 values for E folded entries (E = 729 for
  * nmax = 13: 6.5e7 values, 0.52 GB); a box has E1^3.
- * pwc_table_build_values evaluates each of them once by Eq. 14 over all
- * nodes (FP64) into a device allocation of its own, asynchronously on
+ * pwc_table_build_values evaluates once by Eq. 14 over all nodes (FP64)
+ * each of them that a quadruple of the basis can read (with m = n_k - n_i,
+ * m' = n_l - n_j: |m|^2 + |m'|^2 <= 8 n2max, about half of them; the others
+ * are left unwritten) into a device allocation of its own, asynchronously on
  * `stream`: work queued after it on that stream sees the values, work on
  * another stream must wait for it first (an event or a synchronize).  From
  * then on pwc_reconstruct with PWC_FP64 reads one value per

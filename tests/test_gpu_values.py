@@ -299,3 +299,45 @@ def test_values_build_is_stream_ordered(pw):
     tol = 1e-14 * ref.abs().max().item()
     assert (same - ref).abs().max().item() <= tol
     assert torch.equal(same, other)
+
+
+@pytest.mark.parametrize("sides,n2max,Q", [((1.0,), 169, 96), ((1.0,), 40, 64), ((1.0, 1.3, 0.8), 40, 64)])
+def test_values_at_the_edge_of_the_reachable_set(pw, sides, n2max, Q):
+    """The build skips values no quadruple can reach (orbit sizes summing past
+    8 n2max).  Quadruples on the outer shells, many of them antipodal
+    (k = -i, l = -j: |m|^2 + |m'|^2 = 8 n2max on the outermost shell), read the
+    values nearest that edge; each must equal the node passes of the table."""
+    import torch
+    make = (lambda: pw.Table(sides[0], n2max, Q)) if len(sides) == 1 else \
+        (lambda: pw.Table.box(*sides, n2max, Q))
+    with make() as t:
+        b = t.basis().astype(np.int64)
+        where = {tuple(v): k for k, v in enumerate(b)}
+        neg = np.array([where[tuple(-v)] for v in b])
+        r2 = (b * b).sum(1)
+        outer = np.flatnonzero(r2 >= max(1, n2max - 12))
+        g = workloads.rng(7)
+        n = 600_000
+        i = outer[g.integers(0, len(outer), n)]
+        j = outer[g.integers(0, len(outer), n)]
+        k = outer[g.integers(0, len(outer), n)]
+        l = outer[g.integers(0, len(outer), n)]
+        anti = np.arange(n) % 3 == 0                 # k = -i, l = -j
+        k[anti], l[anti] = neg[i[anti]], neg[j[anti]]
+        half = np.arange(n) % 3 == 1                 # k = -i only
+        k[half] = neg[i[half]]
+        q = _dev(np.stack([i, j, k, l], 1).astype(np.int32), torch.int32)
+        m = b[k] - b[i]
+        mp = b[l] - b[j]
+        edge = int(((m * m).sum(1) + (mp * mp).sum(1)).max())
+        t.set_direct_max(0)
+        ref = t.reconstruct(q)
+        t.build_values()
+        got = t.reconstruct(q)
+        t.sync()
+    top = ref.abs().max().item()
+    err = (got - ref).abs().max().item()
+    say(f"[values] edge n2max={n2max} sides={sides}: max |m|^2+|m'|^2 = {edge} "
+        f"(bound {8 * n2max}), max diff {err:.2e} of {top:.3g}")
+    assert edge == 8 * n2max
+    assert err <= 1e-13 * top
