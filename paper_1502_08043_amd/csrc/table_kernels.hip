@@ -35,41 +35,60 @@ __device__ inline void sincos_2pi_mu(int m, double u, double *s, double *c) {
     *c = fma(-pda, sa, ca);
 }
 
-// Grid (K + 1, Q, ndir): direction d of a box has its own node beta[d][q].
+// kPrimM values of m per block share the Gaussian factor of each point.
+// Grid (ceil((K + 1) / kPrimM), Q, ndir): direction d of a box has its own
+// node beta[d][q].  For every m each lane sums its points in order and a
+// fixed tree combines the lanes.
+constexpr int kPrimM = 3;
+
 __global__ __launch_bounds__(kThreads) void k_prim(const double *__restrict__ beta,
                                                   const double *__restrict__ gl, int K,
                                                   double *__restrict__ prim) {
-    const int m = blockIdx.x;
+    const int m0 = blockIdx.x * kPrimM;
     const int q = blockIdx.y + blockIdx.z * gridDim.y;   // (direction, node) flat
+    const int nm = min(kPrimM, K + 1 - m0);
     const double b = beta[q];
     const double up = fmin(1.0, 8.0 * sqrt(b));
     const double h = up / kGlPanels;
-    double s = 0.0, d = 0.0;
+    double s[kPrimM], d[kPrimM];
+#pragma unroll
+    for (int j = 0; j < kPrimM; ++j) s[j] = d[j] = 0.0;
     for (int p = threadIdx.x; p < kGlPanels * kGlPanelPoints; p += kThreads) {
         const int panel = p / kGlPanelPoints, k = p % kGlPanelPoints;
         const double u = (panel + gl[k]) * h;
         const double wt = gl[kGlPanelPoints + k] * h;
         const double g = exp(-(u * u) / b);
-        double sn, cs;
-        sincos_2pi_mu(m, u, &sn, &cs);
-        s = fma(wt * g, sn, s);
-        d = fma(wt * (1.0 - u) * g, cs, d);
+        const double ws = wt * g, wd = wt * (1.0 - u) * g;
+#pragma unroll
+        for (int j = 0; j < kPrimM; ++j) {
+            if (j >= nm) break;
+            double sn, cs;
+            sincos_2pi_mu(m0 + j, u, &sn, &cs);
+            s[j] = fma(ws, sn, s[j]);
+            d[j] = fma(wd, cs, d[j]);
+        }
     }
-    // Fixed-order tree reduction over the block.
-    __shared__ double rs[kThreads], rd[kThreads];
-    rs[threadIdx.x] = s;
-    rd[threadIdx.x] = d;
+    __shared__ double rs[kPrimM][kThreads], rd[kPrimM][kThreads];
+#pragma unroll
+    for (int j = 0; j < kPrimM; ++j) {
+        rs[j][threadIdx.x] = s[j];
+        rd[j][threadIdx.x] = d[j];
+    }
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
-            rs[threadIdx.x] += rs[threadIdx.x + w];
-            rd[threadIdx.x] += rd[threadIdx.x + w];
+#pragma unroll
+            for (int j = 0; j < kPrimM; ++j) {
+                rs[j][threadIdx.x] += rs[j][threadIdx.x + w];
+                rd[j][threadIdx.x] += rd[j][threadIdx.x + w];
+            }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        prim[(static_cast<size_t>(q) * 2 + 0) * (K + 1) + m] = (m == 0) ? 0.0 : rs[0];
-        prim[(static_cast<size_t>(q) * 2 + 1) * (K + 1) + m] = rd[0];
+    if (threadIdx.x < nm) {
+        const int j = threadIdx.x, m = m0 + j;
+        prim[(static_cast<size_t>(q) * 2 + 0) * (K + 1) + m] = (m == 0) ? 0.0 : rs[j][0];
+        prim[(static_cast<size_t>(q) * 2 + 1) * (K + 1) + m] = rd[j][0];
     }
 }
 
@@ -142,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
 
 hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau) {
     if (!from_tau) {
-        dim3 gp(t.K + 1, t.Q, t.ndir);
+        dim3 gp((t.K + 1 + kPrimM - 1) / kPrimM, t.Q, t.ndir);
         hipLaunchKernelGGL(k_prim, gp, dim3(kThreads), 0, s, t.d_beta, t.d_gl, t.K, t.d_prim);
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
