@@ -338,7 +338,11 @@ __device__ __forceinline__ void sort3(int &a, int &b, int &c) {
 }
 
 // Persistent workgroups walk the upper-triangle tiles of the pair matrix in
-// a fixed order; the kernel table is staged in LDS once per workgroup.
+// a fixed order; the kernel table is staged in LDS once per workgroup.  The
+// 128 row and column vectors of a tile come through a two-stage pipeline:
+// while tile t is summed, the basis vectors of the next tile (whose
+// occupied indices are at hand) and the occupied indices of the one after
+// are in flight.
 __global__ __launch_bounds__(kThreads) void k_pair_ktab(KtArgs a) {
     extern __shared__ uint4 lds_raw[];
     double *lk = reinterpret_cast<double *>(lds_raw);
@@ -346,58 +350,131 @@ __global__ __launch_bounds__(kThreads) void k_pair_ktab(KtArgs a) {
     __shared__ double fi_s[kKtTile], fj_s[kKtTile];
     __shared__ double red[kThreads / 64];
     for (int i = threadIdx.x; i < a.kt_n; i += kThreads) lk[i] = a.ktab[i];
-    double sx = 0.0, sh = 0.0;
+    double sx = 0.0, sh = 0.0;   // diagonal and partial tiles, coefficients applied
+    double so = 0.0, ho = 0.0;   // full tiles above the diagonal, coefficient 2 pending
     const int jl = threadIdx.x % kKtTile, i0 = (threadIdx.x / kKtTile) * kKtRows;
-    const int ntile = a.nT * a.nT;
-    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int ntile = a.nT * a.nT, G = gridDim.x;
+    // The first tile at or after t on this workgroup's stride with ti <= tj.
+    auto valid_from = [&](int t) {
+        while (t < ntile && t / a.nT > t % a.nT) t += G;
+        return t;
+    };
+    // Lanes 0..63 stage the tile's rows, 64..127 its columns.
+    const bool stager = threadIdx.x < 2 * kKtTile, row = threadIdx.x < kKtTile;
+    const int l = row ? threadIdx.x : threadIdx.x - kKtTile;
+    // Stage 2: this lane's occupied index and weight in tile t.
+    auto load_occ = [&](int t, bool &have, int &o, double &w) {
+        have = false;
+        o = 0;
+        w = 0.0;
+        if (!stager || t >= ntile) return;
         const int ti = t / a.nT, tj = t - ti * a.nT;
-        if (ti > tj) continue;                       // uniform across the workgroup
-        __syncthreads();                              // previous tile's vectors consumed
-        if (threadIdx.x < 2 * kKtTile) {
-            const bool row = threadIdx.x < kKtTile;
-            const int l = row ? threadIdx.x : threadIdx.x - kKtTile;
-            const int idx = (row ? ti : tj) * kKtTile + l;
-            int v = 0;
-            double w = 0.0;
-            if (idx < a.M) {
-                const int o = a.occ[idx];
-                if (static_cast<unsigned>(o) < static_cast<unsigned>(a.N)) {
-                    v = a.basis[o];
-                    w = a.f ? a.f[idx] : 1.0;
-                } else {
-                    atomicOr(a.err, 1);
-                    w = NAN;                          // poisons the energies
-                }
-            }
-            if (row) { vi_s[l] = v; fi_s[l] = w; } else { vj_s[l] = v; fj_s[l] = w; }
+        const int idx = (row ? ti : tj) * kKtTile + l;
+        if (idx >= a.M) return;
+        have = true;
+        o = a.occ[idx];
+        w = a.f ? a.f[idx] : 1.0;
+    };
+    // Stage 1: its basis vector (a bad index poisons the energies).
+    auto load_vec = [&](bool have, int o, double w, int &v, double &wv) {
+        v = 0;
+        wv = 0.0;
+        if (!have) return;
+        if (static_cast<unsigned>(o) < static_cast<unsigned>(a.N)) {
+            v = a.basis[o];
+            wv = w;
+        } else {
+            atomicOr(a.err, 1);
+            wv = NAN;
         }
-        __syncthreads();
+    };
+    int t = valid_from(blockIdx.x);
+    bool h1;
+    int o1, cv;
+    double w1, cw;
+    load_occ(t, h1, o1, w1);
+    load_vec(h1, o1, w1, cv, cw);
+    int t1 = valid_from(t + G);
+    load_occ(t1, h1, o1, w1);
+    while (t < ntile) {
+        const int ti = t / a.nT, tj = t - ti * a.nT;
+        __syncthreads();                              // previous tile's vectors consumed
+        if (stager) {
+            if (row) {
+                vi_s[l] = cv;
+                fi_s[l] = cw;
+            } else {
+                vj_s[l] = cv;
+                fj_s[l] = cw;
+            }
+        }
+        // (a tile holding a bad index takes the weighted path, whose NaN
+        // weight poisons the energies)
+        const bool poisoned = __syncthreads_or(stager && isnan(cw));
+        int nv;
+        double nw;
+        load_vec(h1, o1, w1, nv, nw);                 // tile t1's vectors
+        const int t2 = valid_from(t1 + G);
+        load_occ(t2, h1, o1, w1);                     // tile t2's indices
         const int vj = vj_s[jl];
         const double fj = fj_s[jl];
         const int j = tj * kKtTile + jl;
         const int jx = (vj << 24) >> 24, jy = (vj << 16) >> 24, jz = (vj << 8) >> 24;
+        if (ti < tj && (tj + 1) * kKtTile <= a.M && !poisoned) {
+            // A full tile above the diagonal: every pair has i < j, so its
+            // coefficient 2 is applied once at the end.  Row il is the same
+            // for all lanes of a wave.
 #pragma unroll 4
-        for (int k = 0; k < kKtRows; ++k) {
-            const int il = i0 + k, i = ti * kKtTile + il;
-            const int vi = vi_s[il];
-            int dx = jx - ((vi << 24) >> 24), dy = jy - ((vi << 16) >> 24), dz = jz - ((vi << 8) >> 24);
-            dx = dx < 0 ? -dx : dx;
-            dy = dy < 0 ? -dy : dy;
-            dz = dz < 0 ? -dz : dz;
-            int kidx;
-            if (a.box) {
-                kidx = (dx * a.n1 + dy) * a.n1 + dz;
-            } else {
-                sort3(dx, dy, dz);
-                kidx = ktab_index(dx, dy, dz);
+            for (int k = 0; k < kKtRows; ++k) {
+                const int il = i0 + k;
+                const int vi = __builtin_amdgcn_readfirstlane(vi_s[il]);
+                const int dx = abs(jx - ((vi << 24) >> 24));
+                const int dy = abs(jy - ((vi << 16) >> 24));
+                const int dz = abs(jz - ((vi << 8) >> 24));
+                int kidx;
+                if (a.box) {
+                    kidx = (dx * a.n1 + dy) * a.n1 + dz;
+                } else {
+                    const int lo = min(min(dx, dy), dz), hi = max(max(dx, dy), dz);
+                    kidx = ktab_index(lo, dx + dy + dz - lo - hi, hi);
+                }
+                if (a.f) {
+                    const double fi = fi_s[il];
+                    so = fma(fi * fj, lk[kidx], so);
+                    ho = fma(fi, fj, ho);
+                } else {
+                    so += lk[kidx];
+                }
             }
-            const double wf = (i < j ? 2.0 : (i == j ? 1.0 : 0.0)) * fi_s[il] * fj;
-            sx = fma(wf, lk[kidx], sx);
-            sh += wf;
+            if (!a.f) ho += static_cast<double>(kKtRows);
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < kKtRows; ++k) {
+                const int il = i0 + k, i = ti * kKtTile + il;
+                const int vi = vi_s[il];
+                int dx = jx - ((vi << 24) >> 24), dy = jy - ((vi << 16) >> 24), dz = jz - ((vi << 8) >> 24);
+                dx = dx < 0 ? -dx : dx;
+                dy = dy < 0 ? -dy : dy;
+                dz = dz < 0 ? -dz : dz;
+                int kidx;
+                if (a.box) {
+                    kidx = (dx * a.n1 + dy) * a.n1 + dz;
+                } else {
+                    sort3(dx, dy, dz);
+                    kidx = ktab_index(dx, dy, dz);
+                }
+                const double wf = (i < j ? 2.0 : (i == j ? 1.0 : 0.0)) * fi_s[il] * fj;
+                sx = fma(wf, lk[kidx], sx);
+                sh += wf;
+            }
         }
+        t = t1;
+        t1 = t2;
+        cv = nv;
+        cw = nw;
     }
-    sx = block_sum(sx, red);
-    sh = block_sum(sh, red);
+    sx = block_sum(fma(2.0, so, sx), red);
+    sh = block_sum(fma(2.0, ho, sh), red);
     if (threadIdx.x == 0) {
         a.partial[2 * blockIdx.x] = sx;
         a.partial[2 * blockIdx.x + 1] = sh;

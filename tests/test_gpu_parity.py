@@ -394,6 +394,24 @@ def test_out_of_range_index_reports_and_poisons_only_its_row(pw, tables):
         assert np.isnan(out.cpu().numpy()[1])
 
 
+def test_bad_occupied_index_in_a_long_list_poisons_the_energies(pw, tables):
+    """A bad index far into the occupied list lands in full tiles above the
+    diagonal, which the kernel-table exchange sums on a shorter path; those
+    tiles still see the NaN weight, for unit and given occupations."""
+    import torch
+    t = tables(169, 96)
+    occ = torch.arange(4000, dtype=torch.int32, device="cuda")
+    occ[3001] = t.N + 7
+    f = torch.linspace(0.5, 1.5, 4000, dtype=torch.float64, device="cuda")
+    for ff in (None, f):
+        out = t.energies_async(occ, ff, algo=pw.PAIR_KTABLE)
+        with pytest.raises(pw.PwcError) as ei:
+            t.sync()
+        assert ei.value.status == pw.ERR_RANGE
+        e = out.cpu().numpy()
+        assert np.isnan(e[0]) and np.isnan(e[1])
+
+
 def test_one_over_L_scaling(pw, tables):
     import torch
     q = _dev(workloads.uniform_quads(123, 3000, seed=2), torch.int32)
