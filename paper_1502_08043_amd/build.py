@@ -22,7 +22,7 @@ SOURCES = ["api.cpp", "host_mesh.cpp", "server.cpp", "table_kernels.hip",
 # disabled for the device code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+         "-fvisibility=hidden", "-Wall", "-Wextra", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def hipcc() -> str:

@@ -75,8 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_prim(const double *__restrict__ be
         rd[j][threadIdx.x] = d[j];
     }
     __syncthreads();
+    const int tid = threadIdx.x;
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if (tid < w) {
 #pragma unroll
             for (int j = 0; j < kPrimM; ++j) {
                 rs[j][threadIdx.x] += rs[j][threadIdx.x + w];
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(kThreads) void k_prim(const double *__restrict__ be
         }
         __syncthreads();
     }
-    if (threadIdx.x < nm) {
-        const int j = threadIdx.x, m = m0 + j;
+    if (tid < nm) {
+        const int j = tid, m = m0 + j;
         prim[(static_cast<size_t>(q) * 2 + 0) * (K + 1) + m] = (m == 0) ? 0.0 : rs[j][0];
         prim[(static_cast<size_t>(q) * 2 + 1) * (K + 1) + m] = rd[j][0];
     }
