@@ -513,3 +513,34 @@ def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
     with pytest.raises(pw.PwcError) as ei:
         pw.Table.load(tmp_path / "flip.tab")
     assert ei.value.status == pw.ERR_IO
+
+
+def test_tables_created_from_many_threads_at_once(pw):
+    """Table creation from several host threads at once (the upload staging
+    buffers are shared by the process) gives every thread the same tables."""
+    import threading
+    import torch
+    with pw.Table(1.0, 40, 64) as ref_t:
+        ref = ref_t.copy_tables().cpu().numpy()
+    got, errors = [], []
+
+    def work():
+        try:
+            for _ in range(6):
+                s = torch.cuda.Stream()
+                with torch.cuda.stream(s):
+                    t = pw.Table(1.0, 40, 64, stream=s)
+                    tab = t.copy_tables(stream=s)
+                s.synchronize()
+                got.append(tab.cpu().numpy())
+                t.close()
+        except Exception as e:          # noqa: BLE001 - reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=work) for _ in range(6)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=120)
+    assert not errors and not any(x.is_alive() for x in th)
+    assert len(got) == 36 and all(np.array_equal(g, ref) for g in got)
