@@ -717,6 +717,7 @@ pwc_status pwc_release_cached_memory(void) {
         pwc::release_cached(-1);
     }
     pwc::release_stages();
+    pwc::release_value_plans();
     return PWC_OK;
 }
 

@@ -184,6 +184,11 @@ hipError_t launch_direct(DirectBatch b, hipStream_t s);
 // triples of a cube, E1^3 triples of a box) and the reconstruction that reads it.
 int64_t value_count(const Table &t);
 hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s);
+void release_value_plans();   // the build's cached block lists (after a device wait)
+// The c tiles of the build's pair tile pt (so[f] = m^2 + m'^2 of orbit f,
+// ascending): n tiles of 64 c from c_lo, covering every value of its pairs
+// that a quadruple can reach.
+void value_tile_c_range(const int *so, int E1, bool box, int smax, int64_t pt, int *c_lo, int *n);
 hipError_t launch_rec_values(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
                              hipStream_t s);
 // pairsum_kernels.hip

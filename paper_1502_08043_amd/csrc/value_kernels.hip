@@ -39,6 +39,8 @@
 // loaded and stored non-temporally so that they do not evict them.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "pwc_internal.h"
 
@@ -50,36 +52,26 @@ constexpr int kVbTile = 64;      // values of c per block
 constexpr int kVbTileP = 128;    // pairs per block
 constexpr int kVbChunk = 8;      // nodes per LDS stage
 
-constexpr int kVbMaxCtiles = 64;    // c tiles of the largest table (E1 <= 4096)
-
 struct ValBuildArgs {
     const double *tab;    // [rows][Qp] folded W^(1/3) tau (a box: x, y, z tables stacked)
     int Qp;
     int E1;
     int box;
     int64_t npairs;
-    int ctiles;           // ceil(E1 / kVbTile)
-    // c tiles end at E1: tile ct covers c0 .. c0 + 63, c0 = c_off + 64 ct,
-    // c_off = E1 - 64 ctiles <= 0, so the one partial tile is the first,
-    // which the fewest pairs reach (a cube keeps c >= b).
-    int c_off;
-    // Blocks are numbered c tile by c tile: c tile ct owns blocks
-    // first[ct] .. first[ct + 1] - 1, one per tile of 128 pairs that has a
-    // pair with b <= the tile's last c (every pair tile for a box).
-    int first[kVbMaxCtiles + 1];
+    // Block i takes pair tile pt = desc[i] & 0xffffff (pairs 128 pt ..
+    // 128 pt + 127) and its c tile k = desc[i] >> 24, the 64 values of c from
+    // c_lo + 64 k, c_lo the smallest b of its pairs (0 for a box); only the
+    // tiles value_tile_c_range keeps have a block.
+    const uint32_t *desc;
     double pref;
-    // Orbit representatives (m, m') [2 E1] and the largest |m|^2 + |m'|^2 a
-    // quadruple of the basis can reach: 8 n2max (|n_k - n_i|^2 <= 4 n2max).
-    const int32_t *reps;
-    int smax;
     double *val;
 };
 
-__device__ __forceinline__ int64_t tri2(int64_t b) { return b * (b + 1) / 2; }
+__host__ __device__ inline int64_t tri2(int64_t b) { return b * (b + 1) / 2; }
 __device__ __forceinline__ int64_t tri3(int64_t c) { return c * (c + 1) * (c + 2) / 6; }
 
 // The b of pair p (cube numbering p = b (b + 1) / 2 + a, 0 <= a <= b).
-__device__ __forceinline__ int pair_b(int64_t p) {
+__host__ __device__ inline int pair_b(int64_t p) {
     int b = static_cast<int>((sqrt(8.0 * static_cast<double>(p) + 1.0) - 1.0) * 0.5);
     while (tri2(b + 1) <= p) ++b;       // guard the rounding of the square root
     while (tri2(b) > p) --b;
@@ -88,11 +80,6 @@ __device__ __forceinline__ int pair_b(int64_t p) {
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
-// Squared size m^2 + m'^2 of orbit f; orbits are numbered by it, ascending.
-__device__ __forceinline__ int orbit_s(const int32_t *reps, int f) {
-    const int m = reps[2 * f], mp = reps[2 * f + 1];
-    return m * m + mp * mp;
-}
 
 // Each of the block's four waves computes 32 values of c by 64 pairs as
 // 2 x 4 tiles of v_mfma_f64_16x16x4f64, D[i][j] += sum_k A[i][k] B[k][j]
@@ -104,10 +91,9 @@ __device__ __forceinline__ int orbit_s(const int32_t *reps, int f) {
 __global__ __launch_bounds__(kVbThreads, 4) void k_values_build(ValBuildArgs a) {
     __shared__ double Ps[kVbChunk][kVbTileP];
     __shared__ double Cs[kVbChunk][kVbTile];
-    int ct = 0;
-    while (static_cast<int>(blockIdx.x) >= a.first[ct + 1]) ++ct;
-    const int64_t p0 = static_cast<int64_t>(blockIdx.x - a.first[ct]) * kVbTileP;
-    const int c0 = a.c_off + ct * kVbTile;
+    const uint32_t d = a.desc[blockIdx.x];
+    const int64_t p0 = static_cast<int64_t>(d & 0xffffffu) * kVbTileP;
+    const int c0 = (a.box ? 0 : pair_b(p0)) + static_cast<int>(d >> 24) * kVbTile;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int wp = (wave & 1) * 64, wc = (wave >> 1) * 32;
     const int li = lane % 16, lk = lane / 16;
@@ -119,12 +105,6 @@ __global__ __launch_bounds__(kVbThreads, 4) void k_values_build(ValBuildArgs a) 
     const int sc = tid / 4, scq = (tid % 4) * 2;
     const int64_t myp = p0 + sp;
     const double *ra = nullptr, *rb = nullptr, *rc = nullptr;
-    // A value is reachable only if the three orbit sizes sum to at most
-    // smax (the x, y and z parts of |m|^2 + |m'|^2).  The block leaves when
-    // none of its pairs reaches its smallest c: no quadruple of the basis
-    // reads those values, so they are not computed.
-    const int s_c = orbit_s(a.reps, max(c0, 0));
-    bool need = false;
     if (myp < a.npairs) {
         int pa, pb;
         if (a.box) {
@@ -134,11 +114,9 @@ __global__ __launch_bounds__(kVbThreads, 4) void k_values_build(ValBuildArgs a) 
             pb = pair_b(myp);
             pa = static_cast<int>(myp - tri2(pb));
         }
-        need = orbit_s(a.reps, pa) + orbit_s(a.reps, a.box ? pb - a.E1 : pb) + s_c <= a.smax;
         ra = a.tab + static_cast<size_t>(pa) * a.Qp;
         rb = a.tab + static_cast<size_t>(pb) * a.Qp;
     }
-    if (!__syncthreads_or(need)) return;
     if (c0 + sc >= 0 && c0 + sc < a.E1) rc = a.tab + static_cast<size_t>((a.box ? 2 * a.E1 : 0) + c0 + sc) * a.Qp;
 
     f64x4 acc[2][4];
@@ -319,6 +297,94 @@ int64_t value_count(const Table &t) {
     return t.ndir == 3 ? e * e * e : e * (e + 1) * (e + 2) / 6;
 }
 
+// The c tiles of pair tile pt: c_lo, c_lo + 64, ..., n of them, covering every
+// c >= b (a cube) up to the largest c that a pair of the tile can reach
+// (orbit sizes summing to at most smax).  The smallest size sum of the tile
+// is its first pair's or the first of the next row (a row's sizes ascend).
+void value_tile_c_range(const int *so, int E1, bool box, int smax, int64_t pt, int *c_lo, int *n) {
+    const int64_t npairs = box ? static_cast<int64_t>(E1) * E1 : static_cast<int64_t>(E1) * (E1 + 1) / 2;
+    const int64_t p0 = pt * kVbTileP, p1 = (p0 + kVbTileP < npairs ? p0 + kVbTileP : npairs) - 1;
+    int smin;
+    if (box) {
+        const int x0 = static_cast<int>(p0 / E1), y0 = static_cast<int>(p0 % E1);
+        smin = so[x0] + so[y0];
+        if (p1 / E1 > x0) {
+            const int t = so[x0 + 1];
+            smin = t < smin ? t : smin;
+        }
+        *c_lo = 0;
+    } else {
+        const int b0 = pair_b(p0), a0 = static_cast<int>(p0 - tri2(b0));
+        smin = so[a0] + so[b0];
+        if (pair_b(p1) > b0) {
+            const int t = so[b0 + 1];
+            smin = t < smin ? t : smin;
+        }
+        *c_lo = b0;
+    }
+    *n = 0;
+    const int room = smax - smin;
+    if (room < 0) return;
+    int lo = 0, hi = E1 - 1;   // the last orbit with size <= room (orbit 0 has size 0)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (so[mid] <= room) lo = mid;
+        else hi = mid - 1;
+    }
+    if (lo >= *c_lo) *n = (lo - *c_lo + kVbTile) / kVbTile;
+}
+
+namespace {
+// Block descriptors of the build, per device and (cutoff, cube or box): they
+// depend on nothing else, so each is formed and uploaded once per process.
+struct PlanKey {
+    int device, n2max, box;
+    bool operator<(const PlanKey &o) const {
+        return device != o.device ? device < o.device : n2max != o.n2max ? n2max < o.n2max : box < o.box;
+    }
+};
+struct Plan {
+    uint32_t *d_desc = nullptr;
+    int64_t blocks = 0;
+};
+std::mutex g_plan_mu;
+std::map<PlanKey, Plan> g_plans;
+
+hipError_t build_plan(const Table &t, Plan &pl) {
+    std::vector<int32_t> fold, reps;
+    build_fold(t.K, fold, reps);
+    std::vector<int> so(t.E1);
+    for (int f = 0; f < t.E1; ++f) so[f] = reps[2 * f] * reps[2 * f] + reps[2 * f + 1] * reps[2 * f + 1];
+    const bool box = t.ndir == 3;
+    const int64_t npairs = box ? static_cast<int64_t>(t.E1) * t.E1 : static_cast<int64_t>(t.E1) * (t.E1 + 1) / 2;
+    const int64_t npt = (npairs + kVbTileP - 1) / kVbTileP;
+    if (npt > int64_t(0xffffff) || (t.E1 + kVbTile - 1) / kVbTile > 255) return hipErrorInvalidValue;
+    std::vector<uint32_t> desc;
+    for (int64_t pt = 0; pt < npt; ++pt) {
+        int c_lo = 0, n = 0;
+        value_tile_c_range(so.data(), t.E1, box, 8 * t.n2max, pt, &c_lo, &n);
+        for (int k = 0; k < n; ++k) desc.push_back(static_cast<uint32_t>(pt) | (static_cast<uint32_t>(k) << 24));
+    }
+    pl.blocks = static_cast<int64_t>(desc.size());
+    if (desc.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&pl.d_desc), sizeof(uint32_t) * desc.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(pl.d_desc, desc.data(), sizeof(uint32_t) * desc.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess && pl.d_desc) {
+        (void)hipFree(pl.d_desc);
+        pl.d_desc = nullptr;
+    }
+    return e;
+}
+}  // namespace
+
+void release_value_plans() {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto &kv : g_plans)
+        if (kv.second.d_desc) (void)hipFree(kv.second.d_desc);
+    g_plans.clear();
+}
+
 hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
     ValBuildArgs a{};
     a.tab = t.d_tauF;
@@ -326,24 +392,25 @@ hipError_t launch_values_build(const Table &t, double *d_val, hipStream_t s) {
     a.E1 = t.E1;
     a.box = t.ndir == 3;
     a.npairs = a.box ? static_cast<int64_t>(t.E1) * t.E1 : static_cast<int64_t>(t.E1) * (t.E1 + 1) / 2;
-    a.ctiles = (t.E1 + kVbTile - 1) / kVbTile;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
-    a.reps = t.d_reps;
-    a.smax = 8 * t.n2max;
     a.val = d_val;
-    if (a.ctiles > kVbMaxCtiles || a.Qp % kVbChunk) return hipErrorInvalidValue;
-    a.c_off = t.E1 - a.ctiles * kVbTile;
-    int64_t blocks = 0;
-    for (int ct = 0; ct < a.ctiles; ++ct) {
-        a.first[ct] = static_cast<int>(blocks);
-        // pairs with b <= last c of the tile: p < (c_last + 1)(c_last + 2) / 2
-        const int64_t c_last = a.c_off + (ct + 1) * kVbTile - 1;
-        const int64_t np = a.box ? a.npairs : std::min<int64_t>(a.npairs, (c_last + 1) * (c_last + 2) / 2);
-        blocks += (np + kVbTileP - 1) / kVbTileP;
-        if (blocks > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+    if (a.Qp % kVbChunk) return hipErrorInvalidValue;
+    Plan pl;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        const PlanKey key{t.device, t.n2max, a.box};
+        auto it = g_plans.find(key);
+        if (it == g_plans.end()) {
+            const hipError_t e = build_plan(t, pl);
+            if (e != hipSuccess) return e;
+            it = g_plans.emplace(key, pl).first;
+        }
+        pl = it->second;
     }
-    for (int ct = a.ctiles; ct <= kVbMaxCtiles; ++ct) a.first[ct] = static_cast<int>(blocks);
-    hipLaunchKernelGGL(k_values_build, dim3(static_cast<unsigned>(blocks)), dim3(kVbThreads), 0, s, a);
+    if (pl.blocks == 0) return hipSuccess;
+    if (pl.blocks > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+    a.desc = pl.d_desc;
+    hipLaunchKernelGGL(k_values_build, dim3(static_cast<unsigned>(pl.blocks)), dim3(kVbThreads), 0, s, a);
     return hipGetLastError();
 }
 
