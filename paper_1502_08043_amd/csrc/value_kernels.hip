@@ -23,13 +23,14 @@
 // runs the node sums on the FP64 matrix cores, four nodes per step in node
 // order; the next chunk's rows are read into registers while they work.
 // Short chunks keep the registers at four waves per SIMD, which the
-// matrix cores need to stay busy across the barriers.  A cube keeps c >= b
-// only: blocks whose every c lies below every b of their pairs are not
-// launched.  Nor are values computed that no quadruple of the basis can
-// read: with m = n_k - n_i and m' = n_l - n_j, |m|^2 + |m'|^2 <= 8 n2max, and
-// that sum is the total of the three orbits' m^2 + m'^2.  About 4 blocks in 10
-// of the 9171-planewave table have no such value and exit at once; their
-// table entries are left unwritten.
+// matrix cores need to stay busy across the barriers.  Only the values a
+// quadruple of the basis can read are computed: a cube keeps c >= b, and
+// with m = n_k - n_i and m' = n_l - n_j, |m|^2 + |m'|^2 <= 8 n2max, which is
+// the total of the three orbits' m^2 + m'^2.  Each tile of 128 pairs takes
+// the 64-wide c tiles from its smallest b up to the largest c one of its
+// pairs can reach; the list of (pair tile, c tile) blocks depends only on
+// the cutoff and the shape and is formed once.  Other entries of the table
+// are left unwritten.
 //
 // Reconstruction.  Decode each quadruple (basis and fold map in LDS), sort
 // the cube's entries, read one value.  HBM traffic per quadruple: 16 bytes
