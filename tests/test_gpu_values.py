@@ -209,8 +209,12 @@ def test_cached_blocks_are_reused_safely(pw):
         t.build_values()
         again = t.reconstruct(quads)
         t.sync()
-    pw.release_cached_memory()
-    assert torch.equal(first, again)
+    pw.release_cached_memory()                 # blocks, staging buffers, build block lists
+    with pw.Table(1.0, 169, 96) as t:          # everything formed again
+        t.build_values()
+        fresh = t.reconstruct(quads)
+        t.sync()
+    assert torch.equal(first, again) and torch.equal(first, fresh)
     assert (2.0 * half - first).abs().max().item() <= 1e-15 * first.abs().max().item()
 
 
