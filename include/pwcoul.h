@@ -200,8 +200,11 @@ PWC_API pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2m
  * Free a table.  NULL is accepted.  Its device blocks (and its value table)
  * go to a per-device cache of the library, after a wait for the device, and
  * later tables of the same device reuse them (a block serves a table at most
- * 1/8 smaller than itself); the cache keeps at most 4 GiB
- * and pwc_release_cached_memory returns all of it to the device.
+ * 1/8 smaller than itself); the cache keeps at most 4 GiB.
+ * pwc_release_cached_memory waits for the current device and returns the
+ * cached blocks, the pinned upload buffers whose copies are done and the
+ * value-table build's block lists (formed once per cutoff and shape); it must
+ * not run while another thread calls into the library.
  */
 PWC_API pwc_status pwc_table_destroy(pwc_table *t);
 PWC_API pwc_status pwc_release_cached_memory(void);
