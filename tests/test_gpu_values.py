@@ -345,3 +345,28 @@ def test_values_at_the_edge_of_the_reachable_set(pw, sides, n2max, Q):
         f"(bound {8 * n2max}), max diff {err:.2e} of {top:.3g}")
     assert edge == 8 * n2max
     assert err <= 1e-13 * top
+
+
+@pytest.mark.parametrize("n2max", [1, 2, 3, 5, 8, 12, 17, 26, 37, 50, 72, 101])
+def test_values_every_cutoff_against_node_passes(pw, n2max):
+    """The build's block list (per pair tile, the c tiles up to its reach)
+    for many cutoffs, on a cube and a box: every value a quadruple reads,
+    outer shells included, equals the node passes of the same table."""
+    import torch
+    for make in (lambda: pw.Table(1.0, n2max, 32), lambda: pw.Table.box(1.0, 1.2, 0.9, n2max, 32)):
+        with make() as t:
+            b = t.basis().astype(np.int64)
+            r2 = (b * b).sum(1)
+            g = workloads.rng(n2max)
+            outer = np.flatnonzero(r2 >= max(0, r2.max() - 3))
+            n = 100_000
+            pick = lambda: np.where(g.uniform(size=n) < 0.5, outer[g.integers(0, len(outer), n)],
+                                    g.integers(0, t.N, n))
+            q = _dev(np.stack([pick(), pick(), pick(), pick()], 1).astype(np.int32), torch.int32)
+            t.set_direct_max(0)
+            ref = t.reconstruct(q)
+            t.build_values()
+            got = t.reconstruct(q)
+            t.sync()
+        top = ref.abs().max().item()
+        assert (got - ref).abs().max().item() <= 1e-13 * top
