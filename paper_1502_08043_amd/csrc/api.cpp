@@ -337,7 +337,7 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
     t.nd = 2 * t.K + 1;
     t.mesh = m;
     t.h_basis = enumerate_basis(n2max);
-    t.N = static_cast<int64_t>(t.h_basis.size() / 3);
+    t.N = static_cast<int64_t>(t.h_basis->packed.size());
     if (!build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) return PWC_ERR_ARG;
     t.Q = static_cast<int>(t.h_beta.size());
     build_fold(t.K, su.fold, su.reps);
@@ -371,13 +371,7 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
     const int Q = t.Q;
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     // Host-side inputs of the table kernels.
-    std::vector<int32_t> packed(t.N);
-    for (int64_t i = 0; i < t.N; ++i) {
-        const int x = t.h_basis[3 * i], y = t.h_basis[3 * i + 1], z = t.h_basis[3 * i + 2];
-        packed[i] = static_cast<int32_t>((static_cast<uint32_t>(x) & 0xffu) |
-                                         ((static_cast<uint32_t>(y) & 0xffu) << 8) |
-                                         ((static_cast<uint32_t>(z) & 0xffu) << 16));
-    }
+    const std::vector<int32_t> &packed = t.h_basis->packed;
     std::vector<double> glx, glw, gl;
     gauss_legendre(kGlPanelPoints, 0.0, 1.0, glx, glw);
     gl = glx;
@@ -664,9 +658,9 @@ pwc_status pwc_mesh_build(const pwc_mesh *mesh, double L, double *h_beta, double
 
 pwc_status pwc_basis_enumerate(int n2max, int32_t *h_n, int64_t *N) {
     if (n2max < 1 || n2max > PWC_MAX_N2MAX || !N) return PWC_ERR_ARG;
-    const std::vector<int32_t> b = pwc::enumerate_basis(n2max);
-    *N = static_cast<int64_t>(b.size() / 3);
-    if (h_n) std::copy(b.begin(), b.end(), h_n);
+    const auto b = pwc::enumerate_basis(n2max);
+    *N = static_cast<int64_t>(b->packed.size());
+    if (h_n) std::copy(b->n.begin(), b->n.end(), h_n);
     return PWC_OK;
 }
 
@@ -766,7 +760,7 @@ pwc_status pwc_table_box(const pwc_table *t, double *sides) {
 
 pwc_status pwc_basis(const pwc_table *t, int32_t *h_n) {
     if (!t || !h_n) return PWC_ERR_ARG;
-    std::memcpy(h_n, t->t.h_basis.data(), sizeof(int32_t) * t->t.h_basis.size());
+    std::memcpy(h_n, t->t.h_basis->n.data(), sizeof(int32_t) * t->t.h_basis->n.size());
     return PWC_OK;
 }
 

@@ -13,17 +13,26 @@ namespace pwc {
 namespace {
 // The basis, the fold map and the Gauss-Legendre unit rules are pure
 // functions of n2max, K and q; tables of one process mostly share them, so
-// each is formed once and copied out afterwards.
+// each is formed once (the basis is then shared, the others copied out).
 std::mutex g_memo_mu;
-std::map<int, std::vector<int32_t>> g_basis_memo;
+std::map<int, std::shared_ptr<const Basis>> g_basis_memo;
 }  // namespace
 
 static std::vector<int32_t> enumerate_basis_uncached(int n2max);
 
-std::vector<int32_t> enumerate_basis(int n2max) {
+std::shared_ptr<const Basis> enumerate_basis(int n2max) {
     std::lock_guard<std::mutex> lk(g_memo_mu);
     auto it = g_basis_memo.find(n2max);
-    if (it == g_basis_memo.end()) it = g_basis_memo.emplace(n2max, enumerate_basis_uncached(n2max)).first;
+    if (it == g_basis_memo.end()) {
+        auto b = std::make_shared<Basis>();
+        b->n = enumerate_basis_uncached(n2max);
+        b->packed.resize(b->n.size() / 3);
+        for (size_t i = 0; i < b->packed.size(); ++i)
+            b->packed[i] = static_cast<int32_t>((static_cast<uint32_t>(b->n[3 * i]) & 0xffu) |
+                                                ((static_cast<uint32_t>(b->n[3 * i + 1]) & 0xffu) << 8) |
+                                                ((static_cast<uint32_t>(b->n[3 * i + 2]) & 0xffu) << 16));
+        it = g_basis_memo.emplace(n2max, std::move(b)).first;
+    }
     return it->second;
 }
 

@@ -15,8 +15,14 @@ namespace pwc {
 
 // ---------------------------------------------------------------- host ----
 
-// Canonical planewave basis |n|^2 <= n2max, ascending (|n|^2, nx, ny, nz).
-std::vector<int32_t> enumerate_basis(int n2max);
+// Canonical planewave basis |n|^2 <= n2max, ascending (|n|^2, nx, ny, nz):
+// n [N][3], and each vector packed into one int32 (x, y, z in bytes 0..2, as
+// the kernels read it).  Formed once per cutoff and shared.
+struct Basis {
+    std::vector<int32_t> n;
+    std::vector<int32_t> packed;
+};
+std::shared_ptr<const Basis> enumerate_basis(int n2max);
 
 // q-point Gauss-Legendre rule on [a, b] (Newton iteration on the Legendre
 // three-term recurrence), nodes ascending.
@@ -74,7 +80,7 @@ struct Table {
     int64_t N = 0;
     int n_interval1 = 0;
     pwc_mesh mesh{};
-    std::vector<int32_t> h_basis;   // [N][3]
+    std::shared_ptr<const Basis> h_basis;
     std::vector<double> h_beta, h_W;
     FoldLayout fl;       // reconstruction layout of the FP64 path
     FoldLayout flm;      // and of the split-FP32 path (same E, Qp)
