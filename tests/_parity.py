@@ -38,13 +38,16 @@ def setup(n2max, n_nodes=0, mesh=None, beta_c=1.0):
 
 
 def cond_scale(tau, W, basis, quads, L=1.0):
-    K = (tau.shape[1] - 1) // 2
+    """tau: [Q, nd, nd] for a cube, [3, Q, nd, nd] (one table per direction)
+    for a box, whose L is the reference length."""
+    K = (tau.shape[-1] - 1) // 2
     q = np.asarray(quads, dtype=np.int64)
     m = basis[q[:, 2]] - basis[q[:, 0]] + K
     mp = basis[q[:, 3]] - basis[q[:, 1]] + K
     prod = np.abs(W)[:, None] * np.ones((1, len(q)))
     for d in range(3):
-        prod = prod * np.abs(tau[:, m[:, d], mp[:, d]])
+        td = tau[d] if tau.ndim == 4 else tau
+        prod = prod * np.abs(td[:, m[:, d], mp[:, d]])
     return prod.sum(axis=0) / (math.sqrt(math.pi) * L)
 
 

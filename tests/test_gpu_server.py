@@ -1,10 +1,13 @@
 """GPU tests of the continuous-batching server (pwc_server_*)."""
+import math
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads
+from tests import _parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -256,3 +259,89 @@ def test_two_waiters_on_one_ticket(pw):
             x.join(timeout=60)
         assert not any(x.is_alive() for x in th)
     assert sorted(got) == sorted([pw.OK, pw.ERR_STATE])
+
+
+def _oracle_key(key):
+    """Oracle basis, weights, tables and reference length of a serving key
+    (sides, n2max, mesh spec): a cube or a box, the default beta-mesh or a
+    literal alpha_c (beta_c = 4 alpha_c / L0^2)."""
+    sides, n2max, spec = key
+    b = oracle.enumerate_basis(n2max)
+    K = 2 * math.isqrt(n2max)
+    L0 = float(np.prod(sides) ** (1.0 / 3.0)) if len(sides) == 3 else sides[0]
+    kind, q, qt, alpha_c = spec
+    beta_c = 4.0 * alpha_c / (L0 * L0) if alpha_c > 0 else 1.0
+    if kind == "geometric":
+        beta, W, _ = oracle.mesh2(q, qt, beta_c=beta_c)
+    else:
+        beta, W, _ = oracle.mesh1(q, beta_c=beta_c)
+    if len(sides) == 3:
+        L0, _, tau = oracle.box_tables(beta, K, sides)
+    else:
+        tau = oracle.tau_table(beta, K)
+    return b, W, tau, L0
+
+
+def test_served_outputs_match_the_oracle(pw):
+    """What the server returns, against the FP64 oracle: reconstructions on
+    the direct kernel (batched) and on the node passes, and energies with
+    every pair algorithm, in both precisions, on a cube with the default
+    mesh, a cube with a literal alpha_c, a box and a two-interval mesh, all
+    submitted together so that they share slots and launches."""
+    import torch
+    keys = [((1.0,), 40, ("geometric", 7, 8, 0.0)),
+            ((1.3,), 25, ("geometric", 5, 8, 0.25)),
+            ((1.0, 1.3, 0.8), 25, ("geometric", 5, 8, 0.0)),
+            ((0.8,), 16, ("two_interval", 24, 24, 0.0))]
+    jobs = []
+    g = workloads.rng(2015)
+    for key in keys:
+        sides, n2max, (kind, q, qt, alpha_c) = key
+        mesh = (pw.Mesh.geometric(q, qt, alpha_c=alpha_c) if kind == "geometric"
+                else pw.Mesh.two_interval(q, qt, alpha_c=alpha_c))
+        b, W, tau, L0 = _oracle_key(key)
+        N = len(b)
+        L = sides if len(sides) == 3 else sides[0]
+        r2 = (b.astype(np.int64) ** 2).sum(1)
+        M = int((r2 <= 4).sum())
+        f = g.uniform(0.25, 1.0, M)
+        for prec in (pw.FP64, pw.MIXED):
+            for n in (3001, 40_000, 600_000):              # two direct sizes, one above it
+                quads = workloads.lookup_stream(N, M, n, seed=int(g.integers(1 << 30)))
+                jobs.append(("rec", key, L, mesh, prec, quads, None))
+            for algo in (pw.PAIR_AUTO, pw.PAIR_NODESUM):
+                jobs.append(("ene", key, L, mesh, prec, np.arange(M, dtype=np.int32), (algo, f)))
+    outs, tickets = [], []
+    with pw.Server(2 << 30, max_inflight=6) as srv:
+        for kind, key, L, mesh, prec, x, extra in jobs:
+            dx = torch.from_numpy(x).cuda()
+            if kind == "rec":
+                out = torch.full((len(x),), -1.0, dtype=torch.float64, device="cuda")
+                tickets.append(srv.submit_reconstruct(L, key[1], dx, out, precision=prec, mesh=mesh))
+            else:
+                out = torch.full((2,), -1.0, dtype=torch.float64, device="cuda")
+                fd = torch.from_numpy(extra[1]).cuda()
+                tickets.append(srv.submit_energies(L, key[1], dx, out, f=fd, precision=prec,
+                                                   algo=extra[0], mesh=mesh))
+            outs.append(out)
+        results = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert all(r.status == pw.OK for r in results)
+    assert st["batched"] > 0
+    worst = {}
+    for (kind, key, L, mesh, prec, x, extra), out, res in zip(jobs, outs, results):
+        b, W, tau, L0 = _oracle_key(key)
+        got = out.cpu().numpy()
+        if kind == "rec":
+            rows = np.arange(0, len(x), 1 if len(x) <= 40_000 else 7)   # every 7th of the long ones
+            ref = oracle.reconstruct(tau, W, b, x[rows], L=L0)
+            err = P.worst_cond_err(got[rows], ref, P.cond_scale(tau, W, b, x[rows], L=L0))
+            assert err < (P.TOL_FP64 if prec == pw.FP64 else P.TOL_MIXED), (key, prec, len(x), err)
+        else:
+            eh, ex = oracle.energies(tau, W, b, x, f=extra[1], L=L0)
+            err = max(abs(got[0] - eh) / abs(eh), abs(got[1] - ex) / abs(ex))
+            assert err < (P.TOL_E_FP64 if prec == pw.FP64 else P.TOL_E_MIXED), (key, prec, err)
+            assert res.e_h == got[0] and res.e_x == got[1]
+        k = (kind, str(key[0]), prec)
+        worst[k] = max(worst.get(k, 0.0), err)
+    say("[server] served vs oracle: " + ", ".join(f"{k}: {v:.1e}" for k, v in sorted(worst.items())))

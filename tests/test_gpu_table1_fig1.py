@@ -41,17 +41,21 @@ def _meshes(pw):
 
 
 def test_table_one_every_mesh(setup):
+    """Every Table I mesh, both pair algorithms and both precisions: the FP64
+    path and the split-FP32 path (float-float node sums, FP64 reductions)
+    each within 1e-12 relative of the oracle and 1.5e-6 of the printed ratio."""
     pw, b, h, R, occ = setup
     eks = oracle.e_ks(len(b))
     for name, mesh, (beta, W, _), printed in _meshes(pw):
+        ref = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W)
         with pw.Table(1.0, 169, 0, mesh=mesh) as t:
-            for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
-                eh, ex = t.energies(occ, algo=algo)
-                ref = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W)
-                say(f"[table1] {name} algo={algo}: {ex / eks:.7f} (paper {printed}), "
-                    f"rel vs oracle {abs(ex - ref) / abs(ref):.1e}")
-                assert abs(ex / eks - printed) < 1.5e-6
-                assert abs(ex - ref) < 1e-12 * abs(ref)
+            for prec in (pw.FP64, pw.MIXED):
+                for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
+                    eh, ex = t.energies(occ, precision=prec, algo=algo)
+                    say(f"[table1] {name} prec={prec} algo={algo}: {ex / eks:.7f} (paper {printed}), "
+                        f"rel vs oracle {abs(ex - ref) / abs(ref):.1e}")
+                    assert abs(ex / eks - printed) < 1.5e-6
+                    assert abs(ex - ref) < 1e-12 * abs(ref)
 
 
 def test_fig_one_shell_curve(setup):
@@ -66,6 +70,10 @@ def test_fig_one_shell_curve(setup):
             hm, Rm = oracle.diff_histogram(b[:M])
             ref = oracle.exchange_from_histogram(hm, Rm, diag, W)
             assert abs(ex - ref) < 1e-12 * abs(ref)
+            # the split-FP32 path on the same shells, both pair algorithms
+            for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
+                _, exm = t.energies(occ[:M], precision=pw.MIXED, algo=algo)
+                assert abs(exm - ref) < 1e-12 * abs(ref), (M, algo, abs(exm - ref) / abs(ref))
             ratios.append(ex / oracle.e_ks(M))
     say("[fig1] E_x/E_KS: " + " ".join(f"{r:.6f}" for r in ratios))
     assert np.all(np.diff(ratios) > 0)

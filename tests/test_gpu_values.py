@@ -305,13 +305,27 @@ def test_values_build_is_stream_ordered(pw):
     assert torch.equal(same, other)
 
 
+def _oracle_tables(sides, n2max, Q):
+    """Oracle basis, weights, tables and reference length for a cube (sides
+    of length 1) or a box on the default mesh."""
+    o = P.setup(n2max, Q)
+    if len(sides) == 1:
+        return o["basis"], o["W"], o["tau"], sides[0]
+    L0, _, tau = oracle.box_tables(o["beta"], o["K"], sides)
+    return o["basis"], o["W"], tau, L0
+
+
 @pytest.mark.parametrize("sides,n2max,Q", [((1.0,), 169, 96), ((1.0,), 40, 64), ((1.0, 1.3, 0.8), 40, 64)])
-def test_values_at_the_edge_of_the_reachable_set(pw, sides, n2max, Q):
+def test_values_at_the_edge_of_the_reachable_set(pw, monkeypatch, sides, n2max, Q):
     """The build skips values no quadruple can reach (orbit sizes summing past
     8 n2max).  Quadruples on the outer shells, many of them antipodal
     (k = -i, l = -j: |m|^2 + |m'|^2 = 8 n2max on the outermost shell), read the
-    values nearest that edge; each must equal the node passes of the table."""
+    values nearest that edge; each must equal the node passes of the table,
+    and a sample the oracle.  The value block is filled with NaN before the
+    build (a test-only switch of the library), so a value the build missed
+    cannot pass for one left in a recycled block by an earlier table."""
     import torch
+    monkeypatch.setenv("PWC_TEST_POISON_VALUES", "1")
     make = (lambda: pw.Table(sides[0], n2max, Q)) if len(sides) == 1 else \
         (lambda: pw.Table.box(*sides, n2max, Q))
     with make() as t:
@@ -341,19 +355,32 @@ def test_values_at_the_edge_of_the_reachable_set(pw, sides, n2max, Q):
         t.sync()
     top = ref.abs().max().item()
     err = (got - ref).abs().max().item()
+    assert not torch.isnan(got).any().item()
+    # the oracle on every antipodal row of the first 9000 and 3000 others
+    ob, oW, otau, L0 = _oracle_tables(sides, n2max, Q)
+    qh = np.stack([i, j, k, l], 1).astype(np.int32)
+    rows = np.concatenate([np.arange(0, 9000, 3), np.arange(1, 9000, 3)])
+    oref = oracle.reconstruct(otau, oW, ob, qh[rows], L=L0)
+    oerr = P.worst_cond_err(got.cpu().numpy()[rows], oref, P.cond_scale(otau, oW, ob, qh[rows], L=L0))
     say(f"[values] edge n2max={n2max} sides={sides}: max |m|^2+|m'|^2 = {edge} "
-        f"(bound {8 * n2max}), max diff {err:.2e} of {top:.3g}")
+        f"(bound {8 * n2max}), max diff {err:.2e} of {top:.3g}, oracle {oerr:.2e}")
     assert edge == 8 * n2max
     assert err <= 1e-13 * top
+    assert oerr < P.TOL_FP64
 
 
 @pytest.mark.parametrize("n2max", [1, 2, 3, 5, 8, 12, 17, 26, 37, 50, 72, 101])
-def test_values_every_cutoff_against_node_passes(pw, n2max):
+def test_values_every_cutoff_against_node_passes(pw, monkeypatch, n2max):
     """The build's block list (per pair tile, the c tiles up to its reach)
     for many cutoffs, on a cube and a box: every value a quadruple reads,
-    outer shells included, equals the node passes of the same table."""
+    outer shells included, equals the node passes of the same table, and a
+    sample of 3000 the oracle.  The value block starts as NaN (test-only
+    switch), so nothing the build skipped can be read unnoticed."""
     import torch
-    for make in (lambda: pw.Table(1.0, n2max, 32), lambda: pw.Table.box(1.0, 1.2, 0.9, n2max, 32)):
+    monkeypatch.setenv("PWC_TEST_POISON_VALUES", "1")
+    for sides in ((1.0,), (1.0, 1.2, 0.9)):
+        make = (lambda: pw.Table(1.0, n2max, 32)) if len(sides) == 1 else \
+            (lambda: pw.Table.box(*sides, n2max, 32))
         with make() as t:
             b = t.basis().astype(np.int64)
             r2 = (b * b).sum(1)
@@ -362,11 +389,18 @@ def test_values_every_cutoff_against_node_passes(pw, n2max):
             n = 100_000
             pick = lambda: np.where(g.uniform(size=n) < 0.5, outer[g.integers(0, len(outer), n)],
                                     g.integers(0, t.N, n))
-            q = _dev(np.stack([pick(), pick(), pick(), pick()], 1).astype(np.int32), torch.int32)
+            qh = np.stack([pick(), pick(), pick(), pick()], 1).astype(np.int32)
+            q = _dev(qh, torch.int32)
             t.set_direct_max(0)
             ref = t.reconstruct(q)
             t.build_values()
             got = t.reconstruct(q)
             t.sync()
         top = ref.abs().max().item()
+        assert not torch.isnan(got).any().item()
         assert (got - ref).abs().max().item() <= 1e-13 * top
+        ob, oW, otau, L0 = _oracle_tables(sides, n2max, 32)
+        rows = np.arange(3000)
+        oref = oracle.reconstruct(otau, oW, ob, qh[rows], L=L0)
+        oerr = P.worst_cond_err(got.cpu().numpy()[rows], oref, P.cond_scale(otau, oW, ob, qh[rows], L=L0))
+        assert oerr < P.TOL_FP64, (sides, oerr)
