@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -512,10 +513,14 @@ pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int 
 
 namespace {
 
-// Table file: a fixed header, then beta[Q], W[Q] and tau[Q][nd][nd] (FP64,
-// native byte order), the payload covered by an FNV-1a checksum.
+// Table file: a fixed header, then beta[Q], W[Q], the folded FP64 tables
+// tau[ndir][Q][E1] (one value per orbit of (m, m') under (m, m') -> (m', m)
+// and (m, m') -> (-m, -m'), about a quarter of the nd^2 entries) and the
+// orbit representatives (m, m') as int8 pairs [E1][2], in native byte order;
+// the payload is covered by an FNV-1a checksum.  The representatives are
+// those of build_fold; a load checks them and expands the full table.
 constexpr char kTableMagic[8] = {'P', 'W', 'C', 'T', 'A', 'B', 'L', '1'};
-constexpr uint32_t kTableVersion = 1;
+constexpr uint32_t kTableVersion = 2;
 
 struct TableFileHeader {
     char magic[8];
@@ -537,19 +542,40 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) 
     return h;
 }
 
-}  // namespace
+// Payload size of a file with these fields, or 0 if they are out of the
+// library's limits (checked before anything is allocated).
+uint64_t table_payload_bytes(int n2max, int Q, int nd, int ndir) {
+    if (n2max < 1 || n2max > PWC_MAX_N2MAX || Q < 1 || Q > PWC_MAX_NODES) return 0;
+    if (ndir != 1 && ndir != 3) return 0;
+    const int nmax = static_cast<int>(std::floor(std::sqrt(static_cast<double>(n2max)) + 1e-9));
+    if (nd != 4 * nmax + 1) return 0;
+    const uint64_t E1 = static_cast<uint64_t>(2 * nmax + 1) * (2 * nmax + 1);   // orbits of the fold
+    return sizeof(double) * (2 * static_cast<uint64_t>(Q) + static_cast<uint64_t>(ndir) * Q * E1) +
+           2 * E1;
+}
 
-pwc_status pwc_table_save(const pwc_table *t, const char *path) {
-    if (!t || !path) return PWC_ERR_ARG;
-    const pwc::Table &tb = t->t;
-    const size_t ntau = static_cast<size_t>(tb.ndir) * tb.Q * tb.nd * tb.nd;
-    std::vector<double> payload(2 * static_cast<size_t>(tb.Q) + ntau);
-    std::memcpy(payload.data(), tb.h_beta.data(), sizeof(double) * tb.Q);
-    std::memcpy(payload.data() + tb.Q, tb.h_W.data(), sizeof(double) * tb.Q);
+pwc_status table_save(const pwc::Table &tb, const char *path) {
+    std::vector<int32_t> fold, reps;
+    pwc::build_fold(tb.K, fold, reps);
+    const size_t E1 = reps.size() / 2, nd = static_cast<size_t>(tb.nd);
+    const size_t nfull = static_cast<size_t>(tb.ndir) * tb.Q * nd * nd;
+    std::vector<double> full(nfull);
     hipError_t e = tb.ready ? hipEventSynchronize(tb.ready) : hipSuccess;
-    if (e == hipSuccess)
-        e = hipMemcpy(payload.data() + 2 * tb.Q, tb.d_tau, sizeof(double) * ntau, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(full.data(), tb.d_tau, sizeof(double) * nfull, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
+    const uint64_t bytes = table_payload_bytes(tb.n2max, tb.Q, tb.nd, tb.ndir);
+    std::vector<char> payload(bytes);
+    char *w = payload.data();
+    std::memcpy(w, tb.h_beta.data(), sizeof(double) * tb.Q);
+    std::memcpy(w + sizeof(double) * tb.Q, tb.h_W.data(), sizeof(double) * tb.Q);
+    double *folded = reinterpret_cast<double *>(w + 2 * sizeof(double) * tb.Q);
+    for (size_t dq = 0; dq < static_cast<size_t>(tb.ndir) * tb.Q; ++dq)
+        for (size_t f = 0; f < E1; ++f) {
+            const size_t row = static_cast<size_t>(reps[2 * f] + tb.K), col = static_cast<size_t>(reps[2 * f + 1] + tb.K);
+            folded[dq * E1 + f] = full[(dq * nd + row) * nd + col];
+        }
+    int8_t *r8 = reinterpret_cast<int8_t *>(folded + static_cast<size_t>(tb.ndir) * tb.Q * E1);
+    for (size_t i = 0; i < 2 * E1; ++i) r8[i] = static_cast<int8_t>(reps[i]);
     TableFileHeader h{};
     std::memcpy(h.magic, kTableMagic, sizeof(h.magic));
     h.version = kTableVersion;
@@ -568,32 +594,28 @@ pwc_status pwc_table_save(const pwc_table *t, const char *path) {
     h.q_tail = tb.mesh.q_tail;
     h.ratio = tb.mesh.ratio;
     h.alpha_c = tb.mesh.alpha_c;
-    h.payload_bytes = sizeof(double) * payload.size();
-    h.checksum = fnv1a(payload.data(), h.payload_bytes);
+    h.payload_bytes = bytes;
+    h.checksum = fnv1a(payload.data(), bytes);
     FILE *f = std::fopen(path, "wb");
     if (!f) return PWC_ERR_IO;
     const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
-                    std::fwrite(payload.data(), 1, h.payload_bytes, f) == h.payload_bytes;
+                    std::fwrite(payload.data(), 1, bytes, f) == bytes;
     const bool closed = std::fclose(f) == 0;
     return ok && closed ? PWC_OK : PWC_ERR_IO;
 }
 
-pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
-    if (!out) return PWC_ERR_ARG;
-    *out = nullptr;
-    if (!path) return PWC_ERR_ARG;
+pwc_status table_load(const char *path, void *stream, pwc_table **out) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return PWC_ERR_IO;
     TableFileHeader h{};
+    // Every header field that sizes an allocation is checked first.
     bool ok = std::fread(&h, sizeof(h), 1, f) == 1 &&
               std::memcmp(h.magic, kTableMagic, sizeof(h.magic)) == 0 &&
-              h.version == kTableVersion && h.header_bytes == sizeof(h) && h.Q > 0 && h.nd > 0 &&
-              (h.ndir == 1 || h.ndir == 3) &&
-              h.payload_bytes == sizeof(double) * (2 * static_cast<uint64_t>(h.Q) +
-                                                   static_cast<uint64_t>(h.ndir) * h.Q * h.nd * h.nd);
-    std::vector<double> payload;
+              h.version == kTableVersion && h.header_bytes == sizeof(h) &&
+              h.payload_bytes != 0 && h.payload_bytes == table_payload_bytes(h.n2max, h.Q, h.nd, h.ndir);
+    std::vector<char> payload;
     if (ok) {
-        payload.resize(h.payload_bytes / sizeof(double));
+        payload.resize(h.payload_bytes);
         ok = std::fread(payload.data(), 1, h.payload_bytes, f) == h.payload_bytes &&
              std::fgetc(f) == EOF && fnv1a(payload.data(), h.payload_bytes) == h.checksum;
     }
@@ -608,25 +630,57 @@ pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
     m.alpha_c = h.alpha_c;
     int q = 0;
     if (!pwc::mesh_valid(m, &q) || q != h.Q) return PWC_ERR_IO;
-    pwc_table *t = new (std::nothrow) pwc_table;
-    if (!t) return PWC_ERR_NOMEM;
+    std::unique_ptr<pwc_table> t(new pwc_table);
     pwc::TableSetup su;
     const double sides[3] = {h.Lx, h.Ly, h.Lz};
     pwc_status st = pwc::plan_table(sides, h.n2max, m, t->t, su);
+    if (st == PWC_ERR_ARG) st = PWC_ERR_IO;
     if (st == PWC_OK && (t->t.Q != h.Q || t->t.nd != h.nd || t->t.N != h.N || t->t.ndir != h.ndir))
         st = PWC_ERR_IO;
-    if (st == PWC_OK) {
-        // The stored mesh is the table's mesh.
-        t->t.h_beta.assign(payload.begin(), payload.begin() + h.Q);
-        t->t.h_W.assign(payload.begin() + h.Q, payload.begin() + 2 * h.Q);
-        st = pwc::build_table(t->t, su, static_cast<hipStream_t>(stream), payload.data() + 2 * h.Q);
-    }
-    if (st != PWC_OK) {
-        delete t;
-        return st;
-    }
-    *out = t;
+    if (st != PWC_OK) return st;
+    const size_t E1 = su.reps.size() / 2, nd = static_cast<size_t>(h.nd);
+    const double *beta = reinterpret_cast<const double *>(payload.data());
+    const double *folded = beta + 2 * static_cast<size_t>(h.Q);
+    const int8_t *r8 = reinterpret_cast<const int8_t *>(folded + static_cast<size_t>(h.ndir) * h.Q * E1);
+    for (size_t i = 0; i < 2 * E1; ++i)
+        if (r8[i] != su.reps[i]) return PWC_ERR_IO;   // another orbit numbering
+    // The stored mesh is the table's mesh; the full tables follow from the
+    // folded ones (each entry is its orbit representative's value).
+    t->t.h_beta.assign(beta, beta + h.Q);
+    t->t.h_W.assign(beta + h.Q, beta + 2 * h.Q);
+    std::vector<double> full(static_cast<size_t>(h.ndir) * h.Q * nd * nd);
+    for (size_t dq = 0; dq < static_cast<size_t>(h.ndir) * h.Q; ++dq)
+        for (size_t e = 0; e < nd * nd; ++e) full[dq * nd * nd + e] = folded[dq * E1 + su.fold[e]];
+    st = pwc::build_table(t->t, su, static_cast<hipStream_t>(stream), full.data());
+    if (st != PWC_OK) return st;
+    *out = t.release();
     return PWC_OK;
+}
+
+}  // namespace
+
+pwc_status pwc_table_save(const pwc_table *t, const char *path) {
+    if (!t || !path) return PWC_ERR_ARG;
+    try {
+        return table_save(t->t, path);
+    } catch (const std::bad_alloc &) {
+        return PWC_ERR_NOMEM;
+    } catch (...) {
+        return PWC_ERR_IO;
+    }
+}
+
+pwc_status pwc_table_load(const char *path, void *stream, pwc_table **out) {
+    if (!out) return PWC_ERR_ARG;
+    *out = nullptr;
+    if (!path) return PWC_ERR_ARG;
+    try {
+        return table_load(path, stream, out);
+    } catch (const std::bad_alloc &) {
+        return PWC_ERR_NOMEM;
+    } catch (...) {
+        return PWC_ERR_IO;
+    }
 }
 
 pwc_status pwc_table_destroy(pwc_table *t) {
@@ -678,6 +732,12 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
     const hipStream_t s = static_cast<hipStream_t>(stream);
     // Stream-ordered: work queued after this call on `stream` sees the values.
     hipError_t err = pwc::wait_ready(tb, s);
+    // Test-only switch: start from a block of NaN (all bits set), so that a
+    // value the build fails to write cannot pass for one an earlier table
+    // left in a recycled block.
+    const char *poison = std::getenv("PWC_TEST_POISON_VALUES");
+    if (err == hipSuccess && poison && poison[0] && std::strcmp(poison, "0") != 0)
+        err = hipMemsetAsync(d, 0xff, bytes, s);
     if (err == hipSuccess) err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
     if (err != hipSuccess) {
         pwc::dev_release(d, got);

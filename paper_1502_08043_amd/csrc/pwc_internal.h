@@ -158,9 +158,15 @@ int packed_entry_bytes(int E);
 // end of every node pass), recorded for the first slab.
 // Every launch_* that checks indices raises d_err when given, else the
 // table's own error word.
+// d_scratch: a caller-owned buffer for the decoded stream of at least
+// reconstruct_scratch_bytes(t, n) bytes, or nullptr (a stream-ordered
+// allocation per call).
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               double *d_out, pwc_precision p, hipStream_t s,
-                              hipEvent_t *stage_ev = nullptr, int *d_err = nullptr);
+                              hipEvent_t *stage_ev = nullptr, int *d_err = nullptr,
+                              void *d_scratch = nullptr);
+// Device bytes of the decoded stream of one node-pass call of n quadruples.
+size_t reconstruct_scratch_bytes(const Table &t, int64_t n);
 // direct_kernels.hip: small quadruple lists, up to kDirectMaxJobs requests
 // (any tables and precisions) per launch, jobs passed by value.
 struct DirectJob {

@@ -655,8 +655,15 @@ hipError_t run_layout(const PassArgs &a, const Table &t, const FoldLayout &fl, h
 
 int packed_entry_bytes(int E) { return E <= Pk32::kMaxE ? 4 : 8; }
 
+size_t reconstruct_scratch_bytes(const Table &t, int64_t n) {
+    const int64_t slab = std::min<int64_t>(n, kRecSlab);
+    return static_cast<size_t>(packed_entry_bytes(t.fl.E)) *
+           static_cast<size_t>((slab + kStreamPad - 1) / kStreamPad * kStreamPad);
+}
+
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
-                              pwc_precision p, hipStream_t s, hipEvent_t *stage_ev, int *d_err) {
+                              pwc_precision p, hipStream_t s, hipEvent_t *stage_ev, int *d_err,
+                              void *d_scratch) {
     if (n <= 0) return hipSuccess;
     PassArgs a{};
     a.quads = reinterpret_cast<const int4 *>(d_quads);
@@ -674,11 +681,16 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.ord_g = (p == PWC_MIXED ? t.flm : t.fl).G;
     a.out = d_out;
     a.err = d_err ? d_err : t.d_err;
-    const int64_t slab = std::min<int64_t>(n, kRecSlab);
-    const size_t bytes = static_cast<size_t>(packed_entry_bytes(t.fl.E)) *
-                         static_cast<size_t>((slab + kStreamPad - 1) / kStreamPad * kStreamPad);
-    hipError_t err = hipMallocAsync(&a.scratch, bytes, s);
-    if (err != hipSuccess) return err;
+    // The decoded stream: the caller's fixed scratch (it holds the whole
+    // padded stream, checked by the caller), else a stream-ordered
+    // allocation of one slab, freed behind the passes.
+    hipError_t err = hipSuccess;
+    if (d_scratch) {
+        a.scratch = d_scratch;
+    } else {
+        err = hipMallocAsync(&a.scratch, reconstruct_scratch_bytes(t, n), s);
+        if (err != hipSuccess) return err;
+    }
     if (p == PWC_MIXED) {
         a.tab = t.d_tauHL;
         err = run_layout<FF>(a, t, t.flm, s, stage_ev);
@@ -686,8 +698,10 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
         a.tab = t.d_tauF;
         err = run_layout<F64>(a, t, t.fl, s, stage_ev);
     }
-    const hipError_t e2 = hipFreeAsync(a.scratch, s);
-    if (err == hipSuccess) err = e2;
+    if (!d_scratch) {
+        const hipError_t e2 = hipFreeAsync(a.scratch, s);
+        if (err == hipSuccess) err = e2;
+    }
     return err;
 }
 

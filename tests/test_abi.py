@@ -109,34 +109,51 @@ def test_server_create_rejects_bad_arguments(lib):
     assert lib.pwc_server_destroy(None) == 0
 
 
-def test_table_files_rejected_before_device_work(lib, tmp_path):
-    """pwc_table_load refuses missing, foreign and corrupt files with
-    PWC_ERR_IO before touching the device."""
+def _table_header(version=2, n2max=2, Q=16, nd=5, ndir=1, N=19, payload_bytes=0, checksum=12345):
+    """A table-file header (the layout pwc_table_save writes): magic, version,
+    header size, the three box sides, n2max, Q, nd, mesh kind, N, n_sub,
+    q_sub, q_tail, ndir, ratio, alpha_c, payload size and checksum."""
     import struct
+    head = struct.pack("<8sIIdddiiiiqiiiiddQQ", b"PWCTABL1", version, 112, 1.0, 1.0, 1.0,
+                       n2max, Q, nd, 0, N, 1, 8, 8, ndir, 5.0, 0.0, payload_bytes, checksum)
+    assert len(head) == 112
+    return head
 
+
+def test_table_files_rejected_before_device_work(lib, tmp_path):
+    """pwc_table_load refuses missing, foreign, corrupt, truncated and
+    oversized files with PWC_ERR_IO before touching the device or sizing
+    any buffer from the file."""
     import numpy as np
     lib.pwc_table_load.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.pwc_table_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
     lib.pwc_status_str.restype = ctypes.c_char_p
     assert lib.pwc_status_str(7) == b"table file error"
     h = ctypes.c_void_p()
+
+    def load(name, data):
+        path = tmp_path / name
+        path.write_bytes(data)
+        return lib.pwc_table_load(str(path).encode(), None, ctypes.byref(h))
+
     assert lib.pwc_table_load(str(tmp_path / "missing.tab").encode(), None, ctypes.byref(h)) == 7
     assert h.value is None
     assert lib.pwc_table_load(None, None, ctypes.byref(h)) == 1
     assert lib.pwc_table_save(None, str(tmp_path / "x.tab").encode()) == 1
-    foreign = tmp_path / "foreign.tab"
-    foreign.write_bytes(b"not a table file" * 16)
-    assert lib.pwc_table_load(str(foreign).encode(), None, ctypes.byref(h)) == 7
-    # a well-formed header (Q = 16, nd = 5) whose payload fails the checksum
-    Q, nd = 16, 5
-    payload = np.arange(2 * Q + Q * nd * nd, dtype=np.float64).tobytes()
-    head = struct.pack("<8sIIdiiiiqiiiiddQQ", b"PWCTABL1", 1, 96, 1.0, 2, Q, nd, 0, 19,
-                       8, 1, 8, 0, 5.0, 0.0, len(payload), 12345)
-    assert len(head) == 96
-    bad = tmp_path / "bad.tab"
-    bad.write_bytes(head + payload)
-    assert lib.pwc_table_load(str(bad).encode(), None, ctypes.byref(h)) == 7
-    trunc = tmp_path / "trunc.tab"
-    trunc.write_bytes(head + payload[:-8])
-    assert lib.pwc_table_load(str(trunc).encode(), None, ctypes.byref(h)) == 7
+    assert load("foreign.tab", b"not a table file" * 16) == 7
+    assert load("empty.tab", b"") == 7
+    # n2max = 2: nmax = 1, nd = 5, E1 = 9 orbits; Q = 16 nodes (8 x 1 + 8)
+    Q, E1 = 16, 9
+    payload = np.arange(2 * Q + Q * E1, dtype=np.float64).tobytes() + bytes(2 * E1)
+    assert load("bad_sum.tab", _table_header(payload_bytes=len(payload)) + payload) == 7
+    assert load("trunc.tab", _table_header(payload_bytes=len(payload)) + payload[:-8]) == 7
+    assert load("trail.tab", _table_header(payload_bytes=len(payload)) + payload + b"x") == 7
+    assert load("v1.tab", _table_header(version=1, payload_bytes=len(payload)) + payload) == 7
+    # sizes that would wrap or exhaust memory are refused from the header alone
+    assert load("huge_q.tab", _table_header(Q=1 << 30, payload_bytes=(1 << 63) + 8) + payload) == 7
+    assert load("huge_nd.tab", _table_header(nd=1 << 20, payload_bytes=1 << 62) + payload) == 7
+    assert load("bad_nd.tab", _table_header(nd=7, payload_bytes=len(payload)) + payload) == 7
+    assert load("bad_n2.tab", _table_header(n2max=100000, payload_bytes=len(payload)) + payload) == 7
+    assert load("bad_dir.tab", _table_header(ndir=2, payload_bytes=len(payload)) + payload) == 7
+    assert load("neg_q.tab", _table_header(Q=-4, payload_bytes=len(payload)) + payload) == 7
     assert h.value is None

@@ -507,6 +507,13 @@ def test_table_save_load_round_trip(pw, tmp_path, n2max, mesh):
         u.build_values()                       # values are derived, not stored
         assert torch.equal(u.reconstruct(quads), v_ref)
         u.sync()
+    # the file holds one value per orbit of the fold (about a quarter of the
+    # nd^2 entries per node), the mesh and the orbit representatives
+    nmax = math.isqrt(n2max)
+    nd, E1, Q = 4 * nmax + 1, (2 * nmax + 1) ** 2, len(mesh_ref[0])
+    size = path.stat().st_size
+    assert size == 112 + 8 * (2 * Q + Q * E1) + 2 * E1
+    assert size < 0.3 * 8 * Q * nd * nd
     raw = bytearray(path.read_bytes())
     raw[200] ^= 1
     (tmp_path / "flip.tab").write_bytes(bytes(raw))
