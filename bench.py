@@ -12,21 +12,32 @@ integrals by one value read each, and the pair sums with their final
 reductions.  Inputs are resident in HBM before the timed region; every step
 builds its table and value table afresh.  `value` is that FP64 step.  Two more
 legs run the same step without a value table: FP64 node sums
-(`fp64_node_sums`) and split-FP32 node sums (`mixed`).
+(`fp64_node_sums`, reported as `value_small_storage`: the O(N^{2/3})-storage
+path of the paper) and split-FP32 node sums (`mixed`).
 
 The JSON line also carries
   roofline      -- the dominant kernel of the step (the value-table read,
                    k_rec_values) against the MI355X HBM peak, its launch time
-                   taken live with HIP events; value_build and
+                   taken live with HIP events; algorithmic bytes are 16 of
+                   indices in and 8 out per quadruple; value_build and
                    node_pass_roofline give the FP64 rates of the value-table
                    build and of the steady node pass;
-  cpu_baseline  -- the FP64 CPU oracle on a sample of the same stream;
+  cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the same stream,
+                   on all host cores and on one, median of 5 runs after one
+                   warm-up; the errors of every GPU result against it;
+  configs       -- the small configurations: all 19^4 integrals of the
+                   123-planewave basis (Q = 48) and 1e7 uniform quadruples of
+                   the 1045-planewave basis (Q = 64), FP64 against split-FP32;
+  fixed_error   -- every path timed at the node count that reaches a target
+                   error against the converged oracle (1e-9 absolute, and six
+                   places), node sums against node sums;
   legs          -- per-leg step and kernel times, pair-sum rates;
   serving       -- p50/p99 latency of a Poisson request stream over many
-                   boxes, cutoffs and node counts.
+                   boxes, cutoffs and node counts at 50, 80 and 95% load, a
+                   64 MiB budget, and FP64 against split-FP32.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--serve-requests R | --no-serve]
+                    [--serve-requests R | --no-serve] [--no-configs] [--no-fixed-error]
     python bench.py --pmc-workload     # the short run the counter profiles use
 """
 import argparse
@@ -69,8 +80,10 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quads", type=int, default=workloads.C4_STREAM.n_quads)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-fixed-error", action="store_true")
     ap.add_argument("--pmc-workload", action="store_true")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the code hash the recorded counter traffic is keyed on")
@@ -147,65 +160,150 @@ def pmc_workload():
           f"passes {kernel_hash('passes')}", flush=True)
 
 
-def fixed_error_leg(pw, w, quads, n, steps, warmup, target=1e-9):
-    """Throughput at equal total error: the smallest default-mesh Q whose
-    integrals are within `target` (absolute, L = 1) of the converged mesh
-    (Q = 176, 8 x 21 + 8 nodes) on a sample of the stream, then both
-    precisions timed at that Q.  Rounding (about 1e-13 on either path) is far
-    below the target, so the quadrature error decides Q."""
+FIXED_ERROR_TARGETS = (("1e-9", 1e-9), ("six_place", 1e-6))
+FIXED_ERROR_Q = (32, 40, 48, 56, 64, 72, 80, 88, 96, 112, 128)
+
+
+def fixed_error_leg(pw, w, quads, n, steps, warmup, ref=None):
+    """Throughput at equal error.  For each target (1e-9 absolute on the
+    integrals of L = 1, and six places: 1e-6 on the integrals and on
+    E_x/E_KS of the occupied sphere), the smallest default-mesh Q whose
+    results are within the target of the converged mesh (Q = 176, 8 x 21 + 8)
+    on a sample of the stream, then every path timed at that Q: the FP64
+    value table, FP64 node sums and split-FP32 node sums (node sums against
+    node sums is the like-for-like comparison).  `ref` holds the converged
+    references the oracle computed in the CPU-baseline leg (rows, integrals,
+    E_x/E_KS); without it the GPU's own Q = 176 value table stands in."""
     import torch
-    half = n // 2
-    rows = torch.cat([torch.arange(500_000), half + torch.arange(500_000)]).cuda()
-    sample = quads[rows].contiguous()
-    with pw.Table(w.L, w.n2max, 176) as t:
-        t.build_values()
-        ref = t.reconstruct(sample)
-        t.sync()
+    if ref is None:
+        half = n // 2
+        rows = np.concatenate([np.arange(10_000), half + np.arange(10_000)])
+        with pw.Table(w.L, w.n2max, 176) as t:
+            t.build_values()
+            ref_int = t.reconstruct(quads[torch.from_numpy(rows).cuda()].contiguous()).cpu().numpy()
+            t.sync()
+        ref = {"rows": rows, "integrals": ref_int, "ratio": None, "source": "GPU value table at Q = 176"}
+    M = ref.get("M", 925)
+    sample = quads[torch.from_numpy(ref["rows"]).cuda()].contiguous()
+    occ = torch.arange(M, dtype=torch.int32, device="cuda")
+    e_ks = -0.75 * (6.0 / math.pi) ** (1.0 / 3.0) * M ** (4.0 / 3.0) / w.L
     errs = {}
-    q_star = None
-    for Q in (48, 56, 64, 72, 80, 88, 96, 112, 128):
+    for Q in FIXED_ERROR_Q:
         with pw.Table(w.L, w.n2max, Q) as t:
             t.build_values()
-            got = t.reconstruct(sample)
+            got = t.reconstruct(sample).cpu().numpy()
+            _, ex = t.energies(occ)
             t.sync()
-        errs[Q] = (got - ref).abs().max().item()
-        if q_star is None and errs[Q] <= target:
-            q_star = Q
+        e = {"integrals_max_abs": float(np.max(np.abs(got - ref["integrals"])))}
+        if ref.get("ratio") is not None:
+            e["ex_over_eks_abs"] = abs(ex / e_ks - ref["ratio"])
+        errs[Q] = e
     out = torch.empty(n, dtype=torch.float64, device="cuda")
-    occ = torch.arange(925, dtype=torch.int32, device="cuda")
     eout = torch.empty(2, dtype=torch.float64, device="cuda")
-    rates = {}
-    for name, prec, values in (("fp64", pw.FP64, True), ("mixed", pw.MIXED, False)):
-        def step():
-            t = pw.Table(w.L, w.n2max, q_star)
-            if values:
-                t.build_values()
-            t.reconstruct(quads, out, precision=prec)
-            t.energies_async(occ, None, prec, eout)
-            t.sync()
-            t.close()
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        rates[name] = n * steps / (time.perf_counter() - t0)
-    return {"target_abs_error": target, "reference_Q": 176,
-            "sample": "1e6 quadruples of the stream (first 5e5 of each half)",
-            "max_abs_error_vs_Q176": {str(k): v for k, v in errs.items()}, "Q": q_star,
-            "fp64_value_table_integrals_per_s": rates["fp64"],
-            "mixed_node_sums_integrals_per_s": rates["mixed"],
-            "mixed_vs_fp64": rates["mixed"] / rates["fp64"]}
+    paths = (("fp64_value_table", pw.FP64, True), ("fp64_node_sums", pw.FP64, False),
+             ("mixed_node_sums", pw.MIXED, False))
+    points = {}
+    for label, target in FIXED_ERROR_TARGETS:
+        q_star = next((Q for Q in FIXED_ERROR_Q
+                       if all(v <= target for v in errs[Q].values())), None)
+        if q_star is None:
+            points[label] = {"target": target, "Q": None}
+            continue
+        rates = {}
+        for name, prec, values in paths:
+            def step():
+                t = pw.Table(w.L, w.n2max, q_star)
+                if values:
+                    t.build_values()
+                t.reconstruct(quads, out, precision=prec)
+                t.energies_async(occ, None, prec, eout)
+                t.sync()
+                t.close()
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            rates[name] = n * steps / (time.perf_counter() - t0)
+        node = {k: v for k, v in rates.items() if k != "fp64_value_table"}
+        points[label] = {
+            "target": target, "Q": q_star, "errors_at_Q": errs[q_star],
+            "integrals_per_s": rates,
+            "mixed_vs_fp64_node_sums": rates["mixed_node_sums"] / rates["fp64_node_sums"],
+            "faster_node_sum_path": max(node, key=node.get),
+            "fastest_path": max(rates, key=rates.get)}
+    return {"reference": ref["source"], "reference_Q": 176, "sample_rows": len(ref["rows"]),
+            "occupied_M": M,
+            "errors_vs_converged": {str(k): v for k, v in errs.items()}, "points": points}
 
 
-def serving_leg(pw, n_requests):
-    """Poisson request stream over (L, cutoff, Q) keys; p50/p99 at 80% load."""
+def configs_leg(pw, steps, warmup):
+    """The two small configurations, each step = table build + reconstruction
+    of every quadruple + the energies of the occupied set; FP64 (value table
+    and node sums) and split-FP32.  Returns the timings and the GPU outputs
+    (the errors against the oracle are taken in the CPU-baseline leg)."""
+    import torch
+    res, outs = {}, {}
+    for w in (workloads.C1_PLAIN, workloads.C2_SPLIT):
+        with pw.Table(w.L, w.n2max, w.n_nodes) as probe:
+            b = probe.basis().astype(np.int64)
+            N = probe.N
+        M = int(((b ** 2).sum(1) <= w.n2occ).sum())
+        qh = (workloads.all_quads(M) if w is workloads.C1_PLAIN
+              else workloads.uniform_quads(N, w.n_quads, seed=w.seed))
+        q = torch.from_numpy(qh).cuda()
+        n = len(qh)
+        occ = torch.arange(M, dtype=torch.int32, device="cuda")
+        legs = {}
+        for name, prec, values in (("fp64_value_table", pw.FP64, True),
+                                   ("fp64_node_sums", pw.FP64, False),
+                                   ("mixed_node_sums", pw.MIXED, False)):
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            eout = torch.empty(2, dtype=torch.float64, device="cuda")
+
+            def step():
+                t = pw.Table(w.L, w.n2max, w.n_nodes)
+                if values:
+                    t.build_values()
+                t.reconstruct(q, out, precision=prec)
+                t.energies_async(occ, None, prec, eout)
+                t.sync()
+                t.close()
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            legs[name] = {"ms_per_step": dt * 1e3, "integrals_per_s": n / dt,
+                          "node_terms_per_s": n * w.n_nodes / dt,
+                          "pairs_per_s": M * M / dt,
+                          "E_H": float(eout[0].item()), "E_x": float(eout[1].item())}
+            outs[(w.name, name)] = out
+        res[w.name] = {"basis_N": N, "occupied_M": M, "n_nodes": w.n_nodes, "n_quads": n,
+                       "quads": "all M^4 occupied quadruples" if w is workloads.C1_PLAIN
+                       else f"uniform over the basis, seed {w.seed}",
+                       "legs": legs}
+        log(f"[bench] {w.name}: " + ", ".join(f"{k} {v['integrals_per_s']:.3g}/s"
+                                               for k, v in legs.items()))
+    return res, outs
+
+
+def serving_leg(pw, n_requests, warmup_requests=100):
+    """The Poisson request stream over (L, cutoff, Q) keys: a serial FP64
+    pass (cold, then warm: the single-stream service time and latency), then
+    Poisson replays at 50, 80 and 95% of the warm single-stream capacity, a
+    replay at 80% under a 64 MiB HBM budget (admission waits and
+    evictions), and the 80% replay with every request on the split-FP32
+    path.  Latency percentiles skip the first `warmup_requests` of each run."""
     import torch
     mix = workloads.ServingMix(n_requests=n_requests)
     reqs = workloads.serving_stream(mix)
-    probe = pw.Table(1.0, 100, 16)
+    probe = pw.Table(1.0, 400, 16)
     n2 = (probe.basis().astype(np.int64) ** 2).sum(1)
     probe.close()
     pool = torch.randint(0, 1 << 30, (mix.n_range[1], 4), dtype=torch.int32, device="cuda")
@@ -213,8 +311,7 @@ def serving_leg(pw, n_requests):
     inputs = []
     for r in reqs:
         if r.n2max not in nbasis:
-            with pw.Table(1.0, r.n2max, 16) as small:   # basis size of this cutoff
-                nbasis[r.n2max] = small.N
+            nbasis[r.n2max] = int((n2 <= r.n2max).sum())
         if r.kind == 0:
             q = (pool[:r.n_quads] % nbasis[r.n2max]).contiguous()
             inputs.append((q, torch.empty(r.n_quads, dtype=torch.float64, device="cuda")))
@@ -227,47 +324,180 @@ def serving_leg(pw, n_requests):
     def mesh(Q):
         return pw.Mesh.geometric((Q - 8) // 8, 8, alpha_c=0.25)
 
-    def submit(srv, r, x):
+    def submit(srv, r, x, prec):
         if r.kind == 0:
-            return srv.submit_reconstruct(r.L, r.n2max, x[0], x[1], mesh=mesh(r.n_nodes))
-        return srv.submit_energies(r.L, r.n2max, x[0], x[1], mesh=mesh(r.n_nodes))
+            return srv.submit_reconstruct(r.L, r.n2max, x[0], x[1], precision=prec, mesh=mesh(r.n_nodes))
+        return srv.submit_energies(r.L, r.n2max, x[0], x[1], precision=prec, mesh=mesh(r.n_nodes))
 
-    with pw.Server(16 << 30, max_inflight=8) as srv:
-        # serial pass: builds every table and measures the service time
+    def pct(lat):
+        lat = np.sort(np.asarray(lat[warmup_requests:]))
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), float(lat[-1])
+
+    def serial(srv, prec):
+        lat = []
         t0 = time.perf_counter()
         for r, x in zip(reqs, inputs):
-            res = srv.wait(submit(srv, r, x))
-            assert res.status == pw.OK
-        serial_s = time.perf_counter() - t0
-        st_serial = srv.stats()
-        srv.reset_stats()
-        t0 = time.perf_counter()
-        for r, x in zip(reqs, inputs):
-            srv.wait(submit(srv, r, x))
-        warm_serial_s = time.perf_counter() - t0
-        srv.reset_stats()
-        # Poisson replay at 80% of the warm single-stream capacity
-        rate = 0.8 * len(reqs) / warm_serial_s
+            res = srv.wait(submit(srv, r, x, prec))
+            assert res.status == pw.OK, res.status
+            lat.append(res.latency_ms)
+        return time.perf_counter() - t0, lat
+
+    def replay(srv, rate, prec):
         gaps = workloads.rng(mix.seed + 1).exponential(1.0 / rate, size=len(reqs))
         arrivals = np.cumsum(gaps)
+        srv.reset_stats()
         tickets = []
         t0 = time.perf_counter()
         for a, r, x in zip(arrivals, reqs, inputs):
             while time.perf_counter() - t0 < a:
                 pass
-            tickets.append(submit(srv, r, x))
-        for tk in tickets:
-            srv.wait(tk)
+            tickets.append(submit(srv, r, x, prec))
+        res = [srv.wait(tk) for tk in tickets]
+        wall = time.perf_counter() - t0
         st = srv.stats()
-    return {"requests": len(reqs), "offered_load": 0.8, "offered_rate_hz": rate,
-            "distinct_tables": int(st_serial["table_builds"]),
-            "cold_serial_s": serial_s, "warm_serial_s": warm_serial_s,
-            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
-            "integrals_per_s": st["integrals_per_s"], "completed": int(st["completed"]),
-            "failed": int(st["failed"]), "slots": 8,
-            "mix": "80% reconstruct (n log-uniform 1e4..1e6), 20% energies; L in 8 values "
-                   "[0.5, 4], n2max = R^2 (R 5..20), Q in {32,48,64,96,128}, alpha_c = 0.25; "
-                   "Zipf(1.1) key popularity"}
+        assert all(x.status == pw.OK for x in res)
+        p50, p99, mx = pct([x.latency_ms for x in res])
+        work = sum(r.n_quads for r in reqs if r.kind == 0)
+        return {"offered_rate_hz": rate, "p50_ms": p50, "p99_ms": p99, "max_ms": mx,
+                "completed_per_s": len(reqs) / wall, "integrals_per_s": work / wall,
+                "table_builds": int(st["table_builds"]), "evictions": int(st["evictions"]),
+                "launches": int(st["launches"]), "batched": int(st["batched"])}
+
+    out = {"requests": len(reqs), "warmup_requests": warmup_requests, "slots": 8,
+           "mix": "80% reconstruct (n log-uniform 1e4..1e6), 20% energies; L in 8 values "
+                  "[0.5, 4], n2max = R^2 (R 5..20), Q in {32,48,64,96,128}, alpha_c = 0.25; "
+                  "Zipf(1.1) key popularity; Poisson arrivals, seed 2015"}
+    with pw.Server(16 << 30, max_inflight=8) as srv:
+        cold_s, _ = serial(srv, pw.FP64)                 # builds every table
+        out["distinct_tables"] = int(srv.stats()["table_builds"])
+        srv.reset_stats()
+        warm_s, lat = serial(srv, pw.FP64)
+        p50, p99, mx = pct(lat)
+        out["serial_fp64"] = {"cold_s": cold_s, "warm_s": warm_s, "p50_ms": p50, "p99_ms": p99,
+                              "max_ms": mx, "completed_per_s": len(reqs) / warm_s}
+        capacity = len(reqs) / warm_s
+        out["capacity_hz"] = capacity
+        for load in (0.5, 0.8, 0.95):
+            out[f"fp64_load_{int(load * 100)}"] = replay(srv, load * capacity, pw.FP64)
+            log(f"[bench] serving fp64 at {load:.0%}: p50 {out[f'fp64_load_{int(load * 100)}']['p50_ms']:.3f} "
+                f"p99 {out[f'fp64_load_{int(load * 100)}']['p99_ms']:.3f} ms")
+        serial(srv, pw.MIXED)                             # warm the split-FP32 path
+        out["mixed_load_80"] = replay(srv, 0.8 * capacity, pw.MIXED)
+    with pw.Server(64 << 20, max_inflight=8) as srv:
+        serial(srv, pw.FP64)
+        out["budget_64MiB_fp64_load_80"] = replay(srv, 0.8 * capacity, pw.FP64)
+        out["budget_64MiB_fp64_load_80"]["budget_bytes"] = 64 << 20
+    log(f"[bench] serving 64 MiB at 80%: p50 {out['budget_64MiB_fp64_load_80']['p50_ms']:.3f} "
+        f"p99 {out['budget_64MiB_fp64_load_80']['p99_ms']:.3f} ms, "
+        f"evictions {out['budget_64MiB_fp64_load_80']['evictions']}")
+    return out
+
+
+def cpu_baseline_leg(w, quads_h, N, M, n, gpu_out, cfg_outs):
+    """The FP64 CPU oracle: timed on a bounded sample of the lookup stream on
+    all host cores and on one core (median of 5 runs after one warm-up each),
+    and the reference for every GPU error the line reports: the stream
+    sample at the timed mesh, a converged (Q = 176) sample with E_x/E_KS for
+    the fixed-error leg, and the two small configurations."""
+    import torch
+    import oracle
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    basis64 = oracle.enumerate_basis(w.n2max)
+    K = 2 * int(math.isqrt(w.n2max))
+    beta, W, _ = oracle.default_mesh(w.n_nodes)
+    t0 = time.perf_counter()
+    tau = oracle.tau_table(beta, K)
+    t_tab = time.perf_counter() - t0
+
+    def timed(qs, threads):
+        oracle.reconstruct(tau, W, basis64, qs[:1000], nthreads=threads)   # warm-up
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oracle.reconstruct(tau, W, basis64, qs, nthreads=threads)
+            ts.append(time.perf_counter() - t0)
+        return len(qs) / float(np.median(ts)), ts
+
+    # bounded samples: the first s/2 quadruples of each half of the stream
+    def sample(s):
+        rows = np.concatenate([np.arange(s // 2), n // 2 + np.arange(s - s // 2)])
+        return rows, quads_h[rows]
+    rows_all, qs_all = sample(min(n, 20_000_000))
+    rate_all, ts_all = timed(qs_all, all_threads)
+    _, qs_one = sample(min(n, 2_000_000))
+    rate_one, ts_one = timed(qs_one, 1)
+    log(f"[bench] oracle: {rate_all:.4g} integrals/s on {all_threads} threads, {rate_one:.4g} on 1")
+
+    # errors of the lookup-stream legs against the oracle on the timed sample
+    ref = oracle.reconstruct(tau, W, basis64, qs_all, nthreads=all_threads)
+    sub = np.arange(0, len(rows_all), 100)
+    qq = qs_all[sub].astype(np.int64)
+    m = basis64[qq[:, 2]] - basis64[qq[:, 0]] + K
+    mp = basis64[qq[:, 3]] - basis64[qq[:, 1]] + K
+    scale = np.abs(W)[:, None] * np.ones((1, len(qq)))
+    for d in range(3):
+        scale = scale * np.abs(tau[:, m[:, d], mp[:, d]])
+    scale = scale.sum(0) / math.sqrt(math.pi)
+    dev_rows = torch.from_numpy(rows_all).cuda()
+    errs = {}
+    for k, o in gpu_out.items():
+        got = o[dev_rows].cpu().numpy()
+        errs[k] = {"max_abs": float(np.max(np.abs(got - ref))),
+                   "mean_abs": float(np.mean(np.abs(got - ref))),
+                   "max_condition_aware": float(np.max(np.abs(got[sub] - ref[sub]) / scale))}
+
+    # converged references (Q = 176) for the fixed-error leg and the
+    # quadrature error of the timed mesh
+    half = n // 2
+    rows_c = np.concatenate([np.arange(10_000), half + np.arange(10_000)])
+    beta_c, W_c, _ = oracle.default_mesh(176)
+    tau_c = oracle.tau_table(beta_c, K)
+    ref_c = oracle.reconstruct(tau_c, W_c, basis64, quads_h[rows_c], nthreads=all_threads)
+    h, R = oracle.diff_histogram(basis64[:M])
+    ex_c = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta_c, 2 * R), W_c)
+    got_c = gpu_out["fp64"][torch.from_numpy(rows_c).cuda()].cpu().numpy()
+    errs["fp64_vs_converged_Q176"] = {"max_abs": float(np.max(np.abs(got_c - ref_c))),
+                                      "sample": len(rows_c)}
+    converged = {"rows": rows_c, "integrals": ref_c, "ratio": ex_c / oracle.e_ks(M), "M": M,
+                 "source": "FP64 oracle at Q = 176 (8 x 21 + 8)"}
+
+    # the two small configurations, every output against the oracle
+    cfg_errs = {}
+    for wc in (workloads.C1_PLAIN, workloads.C2_SPLIT):
+        bc = oracle.enumerate_basis(wc.n2max)
+        Kc = 2 * int(math.isqrt(wc.n2max))
+        bq, Wq, _ = oracle.default_mesh(wc.n_nodes)
+        tq = oracle.tau_table(bq, Kc)
+        Mc = int(((bc ** 2).sum(1) <= wc.n2occ).sum())
+        qc = (workloads.all_quads(Mc) if wc is workloads.C1_PLAIN
+              else workloads.uniform_quads(len(bc), wc.n_quads, seed=wc.seed))
+        rc = oracle.reconstruct(tq, Wq, bc, qc, nthreads=all_threads)
+        eh, ex = oracle.energies(tq, Wq, bc, np.arange(Mc, dtype=np.int32), nthreads=all_threads)
+        q2 = qc[::50].astype(np.int64)
+        m2 = bc[q2[:, 2]] - bc[q2[:, 0]] + Kc
+        mp2 = bc[q2[:, 3]] - bc[q2[:, 1]] + Kc
+        sc = np.abs(Wq)[:, None] * np.ones((1, len(q2)))
+        for d in range(3):
+            sc = sc * np.abs(tq[:, m2[:, d], mp2[:, d]])
+        sc = sc.sum(0) / math.sqrt(math.pi)
+        e = {}
+        for (wname, leg), o in cfg_outs.items():
+            if wname != wc.name:
+                continue
+            got = o.cpu().numpy()
+            e[leg] = {"max_abs": float(np.max(np.abs(got - rc))),
+                      "mean_abs": float(np.mean(np.abs(got - rc))),
+                      "max_condition_aware": float(np.max(np.abs(got[::50] - rc[::50]) / sc))}
+        cfg_errs[wc.name] = {"integrals": e, "E_H": eh, "E_x": ex}
+
+    cpu = {"value": rate_all, "unit": "integrals/s", "cores": all_threads, "kind": "oracle",
+           "sample": (f"{len(qs_all)} quadruples of the lookup stream (the first {len(qs_all) // 2} "
+                      f"of each half); median of 5 runs after one warm-up"),
+           "runs_s": ts_all,
+           "one_core": {"value": rate_one, "cores": 1, "sample": f"{len(qs_one)} quadruples",
+                        "runs_s": ts_one},
+           "table_build_s": t_tab, "gpu_error_vs_oracle": errs}
+    return cpu, converged, cfg_errs
 
 
 def main():
@@ -381,16 +611,20 @@ def main():
     e_fp64 = t.energies(occ)
     t.close()
 
-    # Roofline of the step's dominant kernel, the value-table read: per
-    # quadruple 16 bytes of indices in, one 8-byte value read, 8 bytes out,
-    # one launch per call.
+    # Roofline of the step's dominant kernel, the value-table read.  The
+    # algorithmic traffic per quadruple is 16 bytes of indices in and 8 bytes
+    # out; the 8-byte value read is a cost of this design, not of the method,
+    # and is reported apart ("design_bytes_per_quadruple").  One launch per call.
     gather_ms = legs["fp64"]["reconstruct_ms"]
-    achieved = 32.0 * n / (gather_ms * 1e-3) / 1e9
+    achieved = 24.0 * n / (gather_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS, "traffic": recorded_traffic("values"),
                 "kernel": "k_rec_values (decode, one value read per quadruple)",
-                "launches_per_call": 1, "algorithmic_bytes_per_launch": 32.0 * n,
-                "avg_launch_ms": gather_ms, "kernel_source_sha256_16": kernel_hash("values")}
+                "launches_per_call": 1, "algorithmic_bytes_per_quadruple": 24,
+                "algorithmic_bytes_per_launch": 24.0 * n, "avg_launch_ms": gather_ms,
+                "design_bytes_per_quadruple": 32,
+                "design_GBps": 32.0 * n / (gather_ms * 1e-3) / 1e9,
+                "kernel_source_sha256_16": kernel_hash("values")}
     # The value-table build is a contraction, V[p][c] = sum_q P_q(p) T_q(c): its
     # algorithmic work is one multiply-add (2 flops) per node and value that a
     # quadruple can read (the build skips the rest); the pair products P,
@@ -438,63 +672,29 @@ def main():
                   "frac": m_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": mpass_ms,
                   "lds_read_TBps": 3 * 8 * mlay["nodes_per_pass"] * n / (mpass_ms * 1e-3) / 1e12}
 
-    fixed_error = fixed_error_leg(pw, w, quads, n, args.steps, args.warmup)
-    log(f"[bench] fixed error 1e-9: Q = {fixed_error['Q']}, FP64 value table "
-        f"{fixed_error['fp64_value_table_integrals_per_s']:.4g}/s, mixed "
-        f"{fixed_error['mixed_node_sums_integrals_per_s']:.4g}/s; errors {fixed_error['max_abs_error_vs_Q176']}")
+    cfg, cfg_outs = (None, {}) if args.no_configs else configs_leg(pw, args.steps, args.warmup)
+
+    cpu, converged, cfg_errs = None, None, None
+    if not args.no_cpu_baseline:
+        cpu, converged, cfg_errs = cpu_baseline_leg(w, quads_h, N, M, n, out, cfg_outs)
+        log(f"[bench] errors vs oracle: {cpu['gpu_error_vs_oracle']}")
+    if cfg is not None and cfg_errs is not None:
+        for name, e in cfg_errs.items():
+            cfg[name]["error_vs_oracle"] = e
+    del cfg_outs
+
+    fixed_error = None
+    if not args.no_fixed_error:
+        fixed_error = fixed_error_leg(pw, w, quads, n, args.steps, args.warmup, converged)
+        for label, pt in fixed_error["points"].items():
+            log(f"[bench] fixed error {label}: Q = {pt['Q']}, rates {pt.get('integrals_per_s')}")
 
     serving = None
     if not args.no_serve:
         log(f"[bench] serving leg: {args.serve_requests} requests")
         serving = serving_leg(pw, args.serve_requests)
-        log(f"[bench] serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
-            f"{serving['offered_rate_hz']:.0f} req/s")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        basis64 = oracle.enumerate_basis(w.n2max)
-        beta, W, _ = oracle.default_mesh(w.n_nodes)
-        t0 = time.perf_counter()
-        tau = oracle.tau_table(beta, 2 * int(math.isqrt(w.n2max)))
-        t_tab = time.perf_counter() - t0
-        sample = min(n, 100_000_000)      # the whole stream: about 1-2 s on 16 host threads
-        rows = np.concatenate([np.arange(sample // 2), n // 2 + np.arange(sample - sample // 2)])
-        qs = quads_h[rows]
-        t0 = time.perf_counter()
-        ref = oracle.reconstruct(tau, W, basis64, qs, nthreads=threads)
-        t_rec = time.perf_counter() - t0
-        # condition-aware error: |C - C_ref| / sum_q |W_q X Y Z| / (sqrt(pi) L)
-        sub = rows[::100]
-        K = (tau.shape[1] - 1) // 2
-        qq = quads_h[sub].astype(np.int64)
-        m = basis64[qq[:, 2]] - basis64[qq[:, 0]] + K
-        mp = basis64[qq[:, 3]] - basis64[qq[:, 1]] + K
-        scale = np.abs(W)[:, None] * np.ones((1, len(qq)))
-        for d in range(3):
-            scale = scale * np.abs(tau[:, m[:, d], mp[:, d]])
-        scale = scale.sum(0) / math.sqrt(math.pi)
-        errs = {}
-        for k in ("fp64", "fp64_node_sums", "mixed"):
-            got = out[k][torch.from_numpy(rows).cuda()].cpu().numpy()
-            errs[k] = {"max_abs": float(np.max(np.abs(got - ref))),
-                       "max_condition_aware": float(np.max(np.abs(got[::100] - ref[::100]) / scale))}
-        # quadrature error of the timed mesh: the oracle on the converged mesh
-        # (Q = 176) for a subsample, against the FP64 result
-        sub2 = rows[:: max(1, len(rows) // 20000)]
-        beta_c, W_c, _ = oracle.default_mesh(176)
-        tau_c = oracle.tau_table(beta_c, 2 * int(math.isqrt(w.n2max)))
-        ref_c = oracle.reconstruct(tau_c, W_c, basis64, quads_h[sub2], nthreads=threads)
-        got_c = out["fp64"][torch.from_numpy(sub2).cuda()].cpu().numpy()
-        errs["fp64_vs_converged_Q176"] = {"max_abs": float(np.max(np.abs(got_c - ref_c))),
-                                          "sample": len(sub2)}
-        cpu = {"value": sample / t_rec, "unit": "integrals/s", "cores": threads, "kind": "oracle",
-               "sample": (f"the whole stream, {sample} quadruples" if sample == n else
-                          f"{sample} quadruples of the stream (first {sample // 2} of each half)"),
-               "table_build_s": t_tab, "gpu_error_vs_oracle": errs}
-        log(f"[bench] oracle: {sample / t_rec:.4g} integrals/s on {threads} threads; errors {errs}")
-
+    vb_bytes = legs["fp64"]["value_table_bytes"]
     res = {
         "metric": "integrals/s and pair-sum/s at 9.2k-PW basis, mixed vs FP64 at fixed err; p99 ms",
         "value": legs["fp64"]["integrals_per_s"],
@@ -511,7 +711,14 @@ def main():
         "config": {"workload": w.name, "L": w.L, "n2max": w.n2max, "basis_N": N,
                    "occupied_M": M, "n_nodes": Q, "mesh": "geometric 8x11 + 8 tail",
                    "n_quads": n, "seed": w.seed, "table_device_bytes": table_bytes,
+                   "value_table_bytes": vb_bytes,
+                   "timed_path_device_bytes": table_bytes + vb_bytes,
+                   "small_storage_path_device_bytes": table_bytes,
                    "step": "table build + value table + reconstruct all quads + E_H/E_x at M=925"},
+        "value_small_storage": legs["fp64_node_sums"]["integrals_per_s"],
+        "value_small_storage_ms_per_step": legs["fp64_node_sums"]["ms_per_step"],
+        "value_small_storage_note": ("the same FP64 step on the O(N^{2/3}) tables alone (node sums, "
+                                     f"{table_bytes} device bytes): no value table"),
         "pair_sums_per_s": {
             "M925_ktable": legs["fp64_node_sums"]["exchange_M925_ktable_pairs_per_s"],
             "M9171_ktable": legs["fp64_node_sums"]["exchange_M9171_ktable_pairs_per_s"],
@@ -520,10 +727,11 @@ def main():
                           legs["fp64_node_sums"]["integrals_per_s"],
                           "integrals_per_s_ratio_vs_value_table": legs["mixed"]["integrals_per_s"] /
                           legs["fp64"]["integrals_per_s"]},
-        "p99_ms": serving["p99_ms"] if serving else None,
+        "p99_ms": serving["fp64_load_80"]["p99_ms"] if serving else None,
         "legs": legs,
         "table_build_ms": table_ms,
         "energies_fp64_M925": {"E_H": e_fp64[0], "E_x": e_fp64[1]},
+        "configs": cfg,
         "serving": serving,
         "roofline": roofline,
         "value_build": value_build,
