@@ -197,10 +197,16 @@ PWC_API pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2m
                                         const pwc_mesh *mesh, void *stream, pwc_table **out);
 
 /*
- * Free a table.  NULL is accepted.  Its device blocks (and its value table)
- * go to a per-device cache of the library, after a wait for the device, and
- * later tables of the same device reuse them (a block serves a table at most
- * 1/8 smaller than itself); the cache keeps at most 4 GiB.
+ * Free a table.  NULL is accepted.  The call does not wait for the device:
+ * its device blocks (and its value table) go to a per-device cache of the
+ * library together with events recorded after the last work each stream
+ * queued on the table (every call that takes the table and a stream records
+ * one), and a later table of the same device reuses a block only once all
+ * of those events have completed (a block serves a table at most 1/8
+ * smaller than itself); the cache keeps at most 4 GiB.  If the table was
+ * used on more than 32 streams, or on a stream under graph capture, the
+ * call waits for the device instead.  pwc_table_free_values waits for the
+ * device before its block enters the cache.
  * pwc_release_cached_memory waits for the current device and returns the
  * cached blocks, the pinned upload buffers whose copies are done and the
  * value-table build's block lists (formed once per cutoff and shape); it must

@@ -100,17 +100,57 @@ namespace pwc {
 // tables of the same device: allocating and releasing a 0.5 GB value table
 // costs about 0.1 ms each way.  At most kCacheBytes are kept; a block is
 // reused for a request at most 1/8 smaller than it, so a table never holds
-// much more memory than it needs.
+// much more memory than it needs.  A released table's blocks carry the
+// events of the streams that used it (EventSet) and are reused only after
+// all of them have completed, so releasing a table never waits for work on
+// other tables; a block released without events waited for the device.
+struct EventSet {
+    int refs = 0;                    // blocks that hold the set (g_cache_mu)
+    std::vector<hipEvent_t> ev;
+};
+
 namespace {
 std::mutex g_cache_mu;
 struct CachedBlock {
     int device;
     void *p;
     size_t bytes;
+    EventSet *es;    // nullptr: idle
 };
 std::vector<CachedBlock> g_cache;   // oldest first
 size_t g_cache_total = 0;
 constexpr size_t kCacheBytes = size_t(4) << 30;
+
+void unref(EventSet *es) {   // caller holds g_cache_mu
+    if (es && --es->refs == 0) {
+        for (hipEvent_t e : es->ev) (void)hipEventDestroy(e);
+        delete es;
+    }
+}
+
+// True once every event of the block's set has completed (the set is then
+// dropped).  hipErrorNotReady is not a sticky error; clear it all the same.
+bool block_idle(CachedBlock &b) {
+    if (!b.es) return true;
+    for (hipEvent_t e : b.es->ev) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    unref(b.es);
+    b.es = nullptr;
+    return true;
+}
+
+void free_block(CachedBlock &b) {   // caller holds g_cache_mu
+    if (b.es)
+        for (hipEvent_t e : b.es->ev) (void)hipEventSynchronize(e);
+    unref(b.es);
+    b.es = nullptr;
+    (void)hipFree(b.p);
+}
 
 void release_cached(int device) {   // device < 0: every device; caller holds the lock
     for (auto it = g_cache.begin(); it != g_cache.end();) {
@@ -118,7 +158,7 @@ void release_cached(int device) {   // device < 0: every device; caller holds th
             ++it;
             continue;
         }
-        (void)hipFree(it->p);
+        free_block(*it);
         g_cache_total -= it->bytes;
         it = g_cache.erase(it);
     }
@@ -133,7 +173,7 @@ hipError_t dev_alloc(size_t bytes, void **p, size_t *got) {
         auto best = g_cache.end();
         for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
             if (it->device == dev && it->bytes >= bytes && it->bytes - bytes <= bytes / 8 &&
-                (best == g_cache.end() || it->bytes < best->bytes))
+                (best == g_cache.end() || it->bytes < best->bytes) && block_idle(*it))
                 best = it;
         if (best != g_cache.end()) {
             *p = best->p;
@@ -156,20 +196,50 @@ hipError_t dev_alloc(size_t bytes, void **p, size_t *got) {
     return e;
 }
 
-void dev_release(void *p, size_t bytes) {
+void dev_release(void *p, size_t bytes, EventSet *es) {
     if (!p) return;
-    // Work in flight may still read the block: wait for the device first, as
-    // hipFree would.
-    (void)hipDeviceSynchronize();
+    // Work in flight may still read the block: without the events of its
+    // users, wait for the device first, as hipFree would.
+    if (!es) (void)hipDeviceSynchronize();
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache.push_back({dev, p, bytes});
+    if (es) ++es->refs;
+    g_cache.push_back({dev, p, bytes, es});
     g_cache_total += bytes;
     while (g_cache_total > kCacheBytes && !g_cache.empty()) {
-        (void)hipFree(g_cache.front().p);
+        free_block(g_cache.front());
         g_cache_total -= g_cache.front().bytes;
         g_cache.erase(g_cache.begin());
+    }
+}
+
+void note_use(const Table &t, hipStream_t s) {
+    if (!t.uses) return;
+    UseLog &u = *t.uses;
+    std::lock_guard<std::mutex> lk(u.mu);
+    if (u.overflow) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        u.overflow = true;   // a captured record cannot be queried: wait for the device instead
+        return;
+    }
+    hipEvent_t ev = nullptr;
+    for (auto &x : u.ev)
+        if (x.first == s) ev = x.second;
+    if (!ev) {
+        if (u.ev.size() >= static_cast<size_t>(kMaxUseStreams) ||
+            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            u.overflow = true;
+            return;
+        }
+        u.ev.emplace_back(s, ev);
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        u.overflow = true;
     }
 }
 
@@ -256,11 +326,40 @@ void release_stages() {   // buffers whose copies have completed
 }  // namespace
 
 void free_table(Table &t) {
-    dev_release(t.d_block, t.block_bytes);   // waits for the device: the upload is done
+    // The blocks wait for the table's construction (ready) and for the last
+    // work of every stream that used it; if that record is incomplete, the
+    // release waits for the device.
+    EventSet *es = nullptr;
+    if (t.uses && (t.d_block || t.d_val)) {
+        std::lock_guard<std::mutex> lk(t.uses->mu);
+        if (!t.uses->overflow) {
+            es = new (std::nothrow) EventSet;
+            if (es) {
+                for (auto &x : t.uses->ev) es->ev.push_back(x.second);
+                t.uses->ev.clear();
+                if (t.ready) es->ev.push_back(t.ready);
+                t.ready = nullptr;
+            }
+        }
+    }
+    if (es) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        ++es->refs;   // held across the two releases below
+    }
+    dev_release(t.d_block, t.block_bytes, es);
     t.d_block = nullptr;
-    dev_release(t.d_val, t.val_alloc);
+    dev_release(t.d_val, t.val_alloc, es);
     t.d_val = nullptr;
     t.val_bytes = t.val_alloc = 0;
+    if (es) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        unref(es);
+    }
+    if (t.uses) {   // events of streams the blocks no longer wait for
+        std::lock_guard<std::mutex> lk(t.uses->mu);
+        for (auto &x : t.uses->ev) (void)hipEventDestroy(x.second);
+        t.uses->ev.clear();
+    }
     if (t.ready) (void)hipEventDestroy(t.ready);
     t.ready = nullptr;
     t.h_img.reset();
@@ -369,6 +468,7 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
         return from_hip(e);
     }
     carve(t, su.reps.size(), static_cast<char *>(t.d_block));
+    t.uses = std::make_shared<UseLog>();
     const int Q = t.Q;
     const size_t Qd = static_cast<size_t>(t.dl.c) * t.dl.nchunk;
     // Host-side inputs of the table kernels.
@@ -740,9 +840,11 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
         err = hipMemsetAsync(d, 0xff, bytes, s);
     if (err == hipSuccess) err = pwc::launch_values_build(tb, static_cast<double *>(d), s);
     if (err != hipSuccess) {
+        (void)hipStreamSynchronize(s);
         pwc::dev_release(d, got);
         return from_hip(err);
     }
+    pwc::note_use(tb, s);
     tb.d_val = static_cast<double *>(d);
     tb.val_bytes = bytes;
     tb.val_alloc = got;
@@ -835,9 +937,11 @@ pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
     if (!t || !d_dst) return PWC_ERR_ARG;
     const size_t bytes = sizeof(double) * t->t.ndir * t->t.Q * t->t.nd * t->t.nd;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = pwc::wait_ready(t->t, s);
+    hipError_t e = pwc::wait_ready(t->t, s);
     if (e != hipSuccess) return from_hip(e);
-    return from_hip(hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice, s));
+    e = hipMemcpyAsync(d_dst, t->t.d_tau, bytes, hipMemcpyDeviceToDevice, s);
+    pwc::note_use(t->t, s);
+    return from_hip(e);
 }
 
 pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n, double *d_out,
@@ -847,18 +951,21 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
-    const hipError_t ew = pwc::wait_ready(t->t, static_cast<hipStream_t>(stream));
-    if (ew != hipSuccess) return from_hip(ew);
-    if (t->t.d_val && p == PWC_FP64)   // every distinct value is at hand: one read each
-        return from_hip(pwc::launch_rec_values(t->t, d_quads, n, d_out, static_cast<hipStream_t>(stream)));
-    if (n <= t->t.direct_max) {   // small list: four lanes per quadruple, no node passes
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = pwc::wait_ready(t->t, s);
+    if (e != hipSuccess) return from_hip(e);
+    if (t->t.d_val && p == PWC_FP64) {   // every distinct value is at hand: one read each
+        e = pwc::launch_rec_values(t->t, d_quads, n, d_out, s);
+    } else if (n <= t->t.direct_max) {   // small list: four lanes per quadruple, no node passes
         pwc::DirectBatch b{};
         b.job[0] = pwc::direct_job(t->t, d_quads, n, d_out, p, nullptr);
         b.njobs = 1;
-        return from_hip(pwc::launch_direct(b, static_cast<hipStream_t>(stream)));
+        e = pwc::launch_direct(b, s);
+    } else {
+        e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s);
     }
-    return from_hip(pwc::launch_reconstruct(t->t, d_quads, n, d_out, p,
-                                            static_cast<hipStream_t>(stream)));
+    pwc::note_use(t->t, s);
+    return from_hip(e);
 }
 
 pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n) {
@@ -883,6 +990,7 @@ pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, i
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s, ev.data());
+    pwc::note_use(t->t, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int k = 0; k < stages && e == hipSuccess; ++k) {
         float ms = 0.0f;
@@ -906,9 +1014,11 @@ pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const doubl
     if ((reinterpret_cast<uintptr_t>(d_out) & 7) || (d_f && (reinterpret_cast<uintptr_t>(d_f) & 7)))
         return PWC_ERR_ARG;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = pwc::wait_ready(t->t, s);
+    hipError_t e = pwc::wait_ready(t->t, s);
     if (e != hipSuccess) return from_hip(e);
-    return from_hip(pwc::launch_energies(t->t, d_occ, d_f, M, p, algo, d_out, s));
+    e = pwc::launch_energies(t->t, d_occ, d_f, M, p, algo, d_out, s);
+    pwc::note_use(t->t, s);
+    return from_hip(e);
 }
 
 pwc_status pwc_energies_async(const pwc_table *t, const int32_t *d_occ, const double *d_f,
@@ -939,6 +1049,7 @@ pwc_status pwc_sync(const pwc_table *t, void *stream) {
     int flag = 0;
     hipError_t e = pwc::wait_ready(t->t, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, t->t.d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    pwc::note_use(t->t, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return from_hip(e);
     if (flag) {

@@ -503,6 +503,22 @@ hipError_t launch_ktab_build(Table &t, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Grid of the kernel-table pair sum for M occupied orbitals (its partials
+// take 2 doubles per workgroup).
+static int ktab_grid(const Table &t, int64_t M) {
+    const size_t lds = sizeof(double) * static_cast<size_t>(t.kt_n);
+    const int per_cu = std::max(1, std::min(8, static_cast<int>((kLdsMax - 4096) / std::max<size_t>(lds, 1))));
+    const int64_t nT = (M + kKtTile - 1) / kKtTile;
+    return static_cast<int>(std::min<int64_t>(nT * (nT + 1) / 2, int64_t(t.n_cu) * per_cu));
+}
+
+size_t energies_scratch_bytes(const Table &t, int64_t M, pwc_pair_algo algo) {
+    if (M <= 0) return 0;
+    if (algo != PWC_PAIR_NODESUM && t.kt_n > 0) return sizeof(double) * 2 * static_cast<size_t>(ktab_grid(t, M));
+    const size_t nT = static_cast<size_t>((M + kTile - 1) / kTile);
+    return sizeof(double) * 2 * nT * nT;
+}
+
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f, int64_t M,
                            pwc_precision p, pwc_pair_algo algo, double *d_out, hipStream_t s,
                            int *d_err) {
@@ -532,9 +548,7 @@ hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d
         a.nT = static_cast<int>((M + kKtTile - 1) / kKtTile);
         a.err = err_word;
         const size_t lds = sizeof(double) * static_cast<size_t>(t.kt_n);
-        const int per_cu = std::max(1, std::min(8, static_cast<int>((kLdsMax - 4096) / std::max<size_t>(lds, 1))));
-        const int64_t upper = static_cast<int64_t>(a.nT) * (a.nT + 1) / 2;
-        const int grid = static_cast<int>(std::min<int64_t>(upper, int64_t(t.n_cu) * per_cu));
+        const int grid = ktab_grid(t, M);
         double *partial = nullptr;
         err = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * 2 * grid, s);
         if (err != hipSuccess) return err;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <memory>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "pwcoul.h"
@@ -67,6 +68,19 @@ struct DiagLayout {
     int nchunk = 0;
 };
 
+// The streams that queued work reading or writing a table's device memory:
+// one event per stream, recorded again after each use.  When the table is
+// released, its blocks wait for these events (not for the whole device)
+// before another table may reuse them.  A stream under graph capture, or
+// more than kMaxUseStreams streams, sets `overflow` and the release waits
+// for the device instead.
+struct UseLog {
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+    bool overflow = false;
+};
+constexpr int kMaxUseStreams = 32;
+
 struct Table {
     // Box sides (a cube has three equal sides).  L is the reference length:
     // the side of a cube, (Lx Ly Lz)^(1/3) for a box; direction d of a box
@@ -123,7 +137,12 @@ struct Table {
     // table may be used on any stream as soon as pwc_table_create returns.
     hipEvent_t ready = nullptr;
     std::shared_ptr<const std::vector<char>> h_img;   // upload source, alive until destroy
+    std::shared_ptr<UseLog> uses;   // created by build_table
 };
+
+// Record that work on the table's memory was queued on stream s (after the
+// launches): the table's release then waits for it.
+void note_use(const Table &t, hipStream_t s);
 
 // Order work queued next on stream s after the table's construction.
 inline hipError_t wait_ready(const Table &t, hipStream_t s) {
@@ -145,9 +164,12 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
 pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const double *h_tau = nullptr);
 void free_table(Table &t);
 // Device blocks of tables and value tables, through a small per-device cache
-// of released blocks (dev_release waits for the device first).
+// of released blocks.  A block released with an event set is reused only
+// once every event of the set has completed; without one, dev_release waits
+// for the device first.
+struct EventSet;
 hipError_t dev_alloc(size_t bytes, void **p, size_t *got);
-void dev_release(void *p, size_t bytes);
+void dev_release(void *p, size_t bytes, EventSet *es = nullptr);
 
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau);
@@ -205,6 +227,8 @@ hipError_t launch_rec_values(const Table &t, const int32_t *d_quads, int64_t n, 
                              hipStream_t s);
 // pairsum_kernels.hip
 hipError_t launch_ktab_build(Table &t, hipStream_t s);
+// Device bytes launch_energies allocates for its partial sums.
+size_t energies_scratch_bytes(const Table &t, int64_t M, pwc_pair_algo algo);
 hipError_t launch_energies(const Table &t, const int32_t *d_occ, const double *d_f,
                            int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
                            hipStream_t s, int *d_err = nullptr);

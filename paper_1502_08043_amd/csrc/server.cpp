@@ -136,15 +136,19 @@ struct pwc_server {
     bool admit();
     void fail(const Pending &p, pwc_status st, double queue_ms, int built);
     void publish_residency();
-    size_t scratch_bytes(const pwc_request &r) const;
+    size_t scratch_bytes(const pwc::Table &t, const pwc_request &r) const;
     bool make_room(size_t need);
 };
 
-size_t pwc_server::scratch_bytes(const pwc_request &r) const {
-    if (r.kind == PWC_REQ_RECONSTRUCT && r.n <= pwc::kDirectDefault) return 0;   // direct kernel
-    if (r.kind == PWC_REQ_RECONSTRUCT)   // decoded quadruples: at most 8 bytes each
-        return sizeof(uint2) * static_cast<size_t>(std::min<int64_t>(r.n, pwc::kRecSlab)) + (1 << 16);
-    return 1 << 20;   // pair-sum partials
+// Device scratch the request's kernels allocate on its table (stream-ordered
+// allocations, priced from the path they take): none for the direct kernel,
+// the decoded stream for the node passes, the pair-sum partials for energies
+// (kernel-table or node-sum grid).  Rounded up to 64 KiB.
+size_t pwc_server::scratch_bytes(const pwc::Table &t, const pwc_request &r) const {
+    size_t b = 0;
+    if (r.kind == PWC_REQ_RECONSTRUCT) b = r.n <= t.direct_max ? 0 : pwc::reconstruct_scratch_bytes(t, r.n);
+    else b = pwc::energies_scratch_bytes(t, r.n, static_cast<pwc_pair_algo>(r.algo));
+    return (b + 65535) / 65536 * 65536;
 }
 
 // Evict unreferenced tables, least recently used first, until `need` more
@@ -241,7 +245,7 @@ bool pwc_server::admit() {
             p = pending.front();
         }
         const Key key = key_of(p.r, p.mesh);
-        const size_t scratch = scratch_bytes(p.r);
+        size_t scratch = 0;
         auto it = cache.find(key);
         int built = 0;
         if (it == cache.end()) {
@@ -254,6 +258,7 @@ bool pwc_server::admit() {
                 st = planned ? pwc::plan_table(sides, p.r.n2max, p.mesh, planned->t, planned_su)
                              : PWC_ERR_NOMEM;
             }
+            if (st == PWC_OK) scratch = scratch_bytes(planned->t, p.r);
             if (st == PWC_OK && planned->t.bytes + scratch > budget) st = PWC_ERR_NOMEM;
             if (st == PWC_OK && p.r.kind == PWC_REQ_ENERGIES && p.r.algo == PWC_PAIR_KTABLE &&
                 planned->t.kt_n == 0)
@@ -295,6 +300,13 @@ bool pwc_server::admit() {
             if (p.r.kind == PWC_REQ_ENERGIES && p.r.algo == PWC_PAIR_KTABLE && it->second.t->t.kt_n == 0) {
                 { std::lock_guard<std::mutex> lk(mu); pending.pop_front(); }
                 fail(p, PWC_ERR_ARG, 0.0, 0);
+                any = true;
+                continue;
+            }
+            scratch = scratch_bytes(it->second.t->t, p.r);
+            if (it->second.bytes + scratch > budget) {   // can never fit beside its table
+                { std::lock_guard<std::mutex> lk(mu); pending.pop_front(); }
+                fail(p, PWC_ERR_NOMEM, 0.0, 0);
                 any = true;
                 continue;
             }
@@ -363,6 +375,7 @@ bool pwc_server::admit() {
             }
             if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int) * b.njobs, s.stream);
             if (e == hipSuccess) e = pwc::launch_direct(b, s.stream);
+            for (const Member &m : s.members) pwc::note_use(m.tab->t->t, s.stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int) * b.njobs, hipMemcpyDeviceToHost, s.stream);
         } else {
@@ -382,6 +395,7 @@ bool pwc_server::admit() {
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(s.h_e, p.r.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
             }
+            pwc::note_use(t, s.stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
         }

@@ -345,3 +345,92 @@ def test_served_outputs_match_the_oracle(pw):
         k = (kind, str(key[0]), prec)
         worst[k] = max(worst.get(k, 0.0), err)
     say("[server] served vs oracle: " + ", ".join(f"{k}: {v:.1e}" for k, v in sorted(worst.items())))
+
+
+def test_scratch_is_priced_by_the_path_taken(pw):
+    """Admission prices each request's device scratch from the kernels it
+    will run on its table: the node-sum pair partials grow as (M/32)^2
+    (1.3 MB at M = 9171), the kernel-table ones stay small, the direct
+    kernel needs none and the node passes need the decoded stream.  With a
+    budget of the table plus 0.6 MB, what cannot fit beside the table fails
+    with ERR_NOMEM at once and the rest runs; with 2 MB more it all runs,
+    and the results are the library's."""
+    import torch
+    pw.release_cached_memory()                 # no recycled (larger) blocks
+    key = (1.0, 169, 32)
+    with pw.Table(*key) as t:
+        tb = t.device_bytes
+        occ = torch.arange(t.N, dtype=torch.int32, device="cuda")
+        e_node = np.array(t.energies(occ, algo=pw.PAIR_NODESUM))
+        e_kt = np.array(t.energies(occ, algo=pw.PAIR_KTABLE))
+        small = torch.from_numpy(workloads.uniform_quads(t.N, 10_000, seed=8)).cuda()
+        big = torch.from_numpy(workloads.uniform_quads(t.N, 1_000_000, seed=9)).cuda()
+        r_small = t.reconstruct(small)
+        t.set_direct_max(0)
+        r_big = t.reconstruct(big)
+        t.sync()
+
+    def run(budget):
+        outs = {k: torch.full((2,), -1.0, dtype=torch.float64, device="cuda") for k in ("node", "kt")}
+        o_small = torch.empty(10_000, dtype=torch.float64, device="cuda")
+        o_big = torch.empty(1_000_000, dtype=torch.float64, device="cuda")
+        with pw.Server(budget, max_inflight=2) as srv:
+            ts = {"kt": srv.submit_energies(*key[:2], occ, outs["kt"], algo=pw.PAIR_KTABLE, n_nodes=key[2]),
+                  "node": srv.submit_energies(*key[:2], occ, outs["node"], algo=pw.PAIR_NODESUM,
+                                              n_nodes=key[2]),
+                  "small": srv.submit_reconstruct(*key[:2], small, o_small, n_nodes=key[2]),
+                  "big": srv.submit_reconstruct(*key[:2], big, o_big, n_nodes=key[2])}
+            st = {k: srv.wait(v).status for k, v in ts.items()}
+        return st, outs, o_small, o_big
+
+    st, outs, o_small, o_big = run(tb + 600_000)
+    say(f"[server] table {tb} B + 0.6 MB: {st}")
+    assert st == {"kt": pw.OK, "node": pw.ERR_NOMEM, "small": pw.OK, "big": pw.ERR_NOMEM}
+    assert np.array_equal(outs["kt"].cpu().numpy(), e_kt)
+    assert torch.equal(o_small, r_small)
+    st, outs, o_small, o_big = run(tb + 6_000_000)
+    assert all(v == pw.OK for v in st.values()), st
+    assert np.array_equal(outs["node"].cpu().numpy(), e_node)
+    assert np.array_equal(outs["kt"].cpu().numpy(), e_kt)
+    assert torch.equal(o_big, r_big) and torch.equal(o_small, r_small)
+
+
+def test_eviction_does_not_wait_for_other_tables(pw):
+    """A table released while a long reconstruction on another table is in
+    flight returns without waiting for it (its blocks wait for their own
+    streams' events instead), and a new table reuses the released block only
+    once the work that read it is done: results stay bitwise those of a
+    quiet device."""
+    import time
+    import torch
+    pw.release_cached_memory()
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    big = torch.randint(0, 9171, (60_000_000, 4), dtype=torch.int32, device="cuda", generator=gen)
+    q = torch.from_numpy(workloads.uniform_quads(1045, 200_000, seed=6)).cuda()
+    with pw.Table(1.0, 169, 96) as slow, pw.Table(1.0, 40, 64) as ref_t:
+        ref_t.set_direct_max(0)
+        ref = ref_t.reconstruct(q)
+        slow.set_direct_max(0)
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            out_big = slow.reconstruct(big, precision=pw.MIXED)   # a few ms of node passes
+        t = pw.Table(1.0, 40, 64)
+        t.set_direct_max(0)
+        got = t.reconstruct(q)
+        t0 = time.perf_counter()
+        t.close()                                   # releases its block behind the default stream
+        dt = time.perf_counter() - t0
+        busy = not side.query()
+        u = pw.Table(1.0, 40, 64)                   # same size: may take the released block
+        u.set_direct_max(0)
+        again = u.reconstruct(q)
+        u.sync()
+        torch.cuda.synchronize()
+        u.close()
+        slow.sync(side)
+    say(f"[server] release took {dt * 1e3:.3f} ms with the side stream busy={busy}")
+    assert torch.equal(got, ref) and torch.equal(again, ref)
+    assert not torch.isnan(out_big).any().item()
+    if busy:
+        assert dt < 2e-3
