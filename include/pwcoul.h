@@ -67,7 +67,8 @@ typedef enum {
     PWC_ERR_DEVICE = 4,  /* HIP runtime error */
     PWC_ERR_BUSY = 5,    /* server: queue full or shutting down */
     PWC_ERR_STATE = 6,   /* server: unknown ticket, or object in the wrong state */
-    PWC_ERR_IO = 7       /* table file missing, unreadable, corrupt or inconsistent */
+    PWC_ERR_IO = 7,      /* table file missing, unreadable, corrupt or inconsistent */
+    PWC_ERR_LIMIT = 8    /* a size beyond a fixed limit of the call (pwc_reconstruct_noalloc) */
 } pwc_status;
 
 typedef enum {
@@ -347,6 +348,29 @@ PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, i
 PWC_API pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                            double *d_out, pwc_precision p, void *stream,
                                            double *h_ms, int max_stages, int *n_stages);
+
+/* Largest quadruple count of one pwc_reconstruct_noalloc call. */
+#define PWC_NOALLOC_MAX_QUADS 8388608
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The node
+ * passes of pwc_reconstruct (whatever the direct-kernel size, and with or
+ * without a value table: the same kernels and results as pwc_reconstruct
+ * with direct_max = 0) whose decoded-quadruple stream lives in a fixed
+ * device array of the library (64 MiB per device, held until the process
+ * ends) instead of a per-call allocation; no call allocates or frees device
+ * or host memory.  Arguments, layouts, errors and ownership as
+ * pwc_reconstruct; async on `stream`.  n > PWC_NOALLOC_MAX_QUADS returns
+ * PWC_ERR_LIMIT with nothing enqueued (split longer lists into calls of at
+ * most that many).  Every call on one device shares that device's array:
+ * two calls whose work may overlap on the device (different streams with
+ * no ordering between them, or several host threads) race and give wrong
+ * results; calls on one stream, or ordered by events, are safe.  Nothing in
+ * the array needs clearing between calls.
+ */
+PWC_API pwc_status pwc_reconstruct_noalloc(const pwc_table *t, const int32_t *d_quads, int64_t n,
+                                           double *d_out, pwc_precision p, void *stream);
 
 /*
  * Uniform-electron-gas energies of one spin channel (Sec. III) for the M

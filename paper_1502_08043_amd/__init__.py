@@ -23,7 +23,8 @@ MESH_GEOMETRIC = 0
 MESH_TWO_INTERVAL = 1
 PAIR_AUTO, PAIR_NODESUM, PAIR_KTABLE = 0, 1, 2
 
-OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE, ERR_IO = range(8)
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE, ERR_IO, ERR_LIMIT = range(9)
+NOALLOC_MAX_QUADS = 8388608     # PWC_NOALLOC_MAX_QUADS
 
 
 class PwcError(RuntimeError):
@@ -87,6 +88,7 @@ def lib():
             "pwc_mesh_nodes": (i32, [vp, vp, vp]),
             "pwc_table_copy": (i32, [vp, vp, vp]),
             "pwc_reconstruct": (i32, [vp, vp, i64, vp, i32, vp]),
+            "pwc_reconstruct_noalloc": (i32, [vp, vp, i64, vp, i32, vp]),
             "pwc_energies_async": (i32, [vp, vp, vp, i64, i32, vp, vp]),
             "pwc_energies_ex": (i32, [vp, vp, vp, i64, i32, i32, vp, vp]),
             "pwc_energies": (i32, [vp, vp, vp, i64, i32, vp, vp]),
@@ -312,6 +314,18 @@ class Table:
         _check(lib().pwc_reconstruct(self.handle, _dev_ptr(quads, torch.int32, "quads"), n,
                                      _dev_ptr(out, torch.float64, "out"), int(precision),
                                      _stream(stream)), "pwc_reconstruct")
+        return out
+
+    def reconstruct_noalloc(self, quads, out, precision=FP64, stream=None):
+        """pwc_reconstruct_noalloc: the node passes with the library's fixed
+        scratch (no allocation by the library; the caller passes `out`);
+        async.  Calls that may overlap on the device race."""
+        if quads.dim() != 2 or quads.shape[1] != 4 or out.numel() != quads.shape[0]:
+            raise ValueError("quads must be [n, 4] and out [n]")
+        _check(lib().pwc_reconstruct_noalloc(self.handle, _dev_ptr(quads, torch.int32, "quads"),
+                                             quads.shape[0], _dev_ptr(out, torch.float64, "out"),
+                                             int(precision), _stream(stream)),
+               "pwc_reconstruct_noalloc")
         return out
 
     def reconstruct_profile(self, quads, out=None, precision=FP64, stream=None):

@@ -214,7 +214,7 @@ void dev_release(void *p, size_t bytes, EventSet *es) {
     }
 }
 
-void note_use(const Table &t, hipStream_t s) {
+void note_use(const Table &t, hipStream_t s, bool may_create) {
     if (!t.uses) return;
     UseLog &u = *t.uses;
     std::lock_guard<std::mutex> lk(u.mu);
@@ -229,7 +229,7 @@ void note_use(const Table &t, hipStream_t s) {
     for (auto &x : u.ev)
         if (x.first == s) ev = x.second;
     if (!ev) {
-        if (u.ev.size() >= static_cast<size_t>(kMaxUseStreams) ||
+        if (!may_create || u.ev.size() >= static_cast<size_t>(kMaxUseStreams) ||
             hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             u.overflow = true;
@@ -559,6 +559,7 @@ const char *pwc_status_str(pwc_status s) {
         case PWC_ERR_BUSY: return "busy";
         case PWC_ERR_STATE: return "invalid state";
         case PWC_ERR_IO: return "table file error";
+        case PWC_ERR_LIMIT: return "size beyond the call's fixed limit";
     }
     return "unknown status";
 }
@@ -965,6 +966,24 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
         e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s);
     }
     pwc::note_use(t->t, s);
+    return from_hip(e);
+}
+
+pwc_status pwc_reconstruct_noalloc(const pwc_table *t, const int32_t *d_quads, int64_t n,
+                                   double *d_out, pwc_precision p, void *stream) {
+    if (!t || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (n > PWC_NOALLOC_MAX_QUADS) return PWC_ERR_LIMIT;
+    if (n == 0) return PWC_OK;
+    if (!d_quads || !d_out) return PWC_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
+        return PWC_ERR_ARG;
+    if (pwc::reconstruct_scratch_bytes(t->t, n) > pwc::kNoAllocScratchBytes) return PWC_ERR_LIMIT;
+    void *scratch = nullptr;
+    hipError_t e = pwc::noalloc_scratch(&scratch);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (e == hipSuccess) e = pwc::wait_ready(t->t, s);
+    if (e == hipSuccess) e = pwc::launch_reconstruct(t->t, d_quads, n, d_out, p, s, nullptr, nullptr, scratch);
+    pwc::note_use(t->t, s, false);   // re-records an existing event, creates none
     return from_hip(e);
 }
 

@@ -141,8 +141,10 @@ struct Table {
 };
 
 // Record that work on the table's memory was queued on stream s (after the
-// launches): the table's release then waits for it.
-void note_use(const Table &t, hipStream_t s);
+// launches): the table's release then waits for it.  With may_create false
+// no event is created: a stream without one marks the log incomplete (the
+// release then waits for the device) -- for callers that cannot allocate.
+void note_use(const Table &t, hipStream_t s, bool may_create = true);
 
 // Order work queued next on stream s after the table's construction.
 inline hipError_t wait_ready(const Table &t, hipStream_t s) {
@@ -189,6 +191,12 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               void *d_scratch = nullptr);
 // Device bytes of the decoded stream of one node-pass call of n quadruples.
 size_t reconstruct_scratch_bytes(const Table &t, int64_t n);
+// pwc_reconstruct_noalloc's fixed scratch: kNoAllocScratchBytes of static
+// device memory per device; *p is its address on the current device (looked
+// up once per device).  Holds the padded decoded stream of
+// PWC_NOALLOC_MAX_QUADS quadruples at 8 bytes each.
+constexpr size_t kNoAllocScratchBytes = size_t(8) * PWC_NOALLOC_MAX_QUADS;
+hipError_t noalloc_scratch(void **p);
 // direct_kernels.hip: small quadruple lists, up to kDirectMaxJobs requests
 // (any tables and precisions) per launch, jobs passed by value.
 struct DirectJob {

@@ -62,9 +62,18 @@
 // the decode orders the entries.  Other tables decode in k_decode first.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "ffloat.h"
 #include "pwc_internal.h"
+
+// Fixed scratch of pwc_reconstruct_noalloc: the decoded-quadruple stream of
+// one call, for callers that cannot allocate.  Every device that runs the
+// library holds its own copy until the process ends.  In host code this name
+// is a host-side stand-in, not a device address: host code uses only the
+// address hipGetSymbolAddress returns for the current device
+// (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[pwc::kNoAllocScratchBytes];
 
 namespace pwc {
 namespace {
@@ -654,6 +663,31 @@ hipError_t run_layout(const PassArgs &a, const Table &t, const FoldLayout &fl, h
 }  // namespace
 
 int packed_entry_bytes(int E) { return E <= Pk32::kMaxE ? 4 : 8; }
+
+namespace {
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (each device holds the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!q) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[dev] = q;
+    }
+    *p = g_noalloc_ptr[dev];
+    return hipSuccess;
+}
 
 size_t reconstruct_scratch_bytes(const Table &t, int64_t n) {
     const int64_t slab = std::min<int64_t>(n, kRecSlab);
