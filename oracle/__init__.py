@@ -12,7 +12,9 @@ Many-Electron Quantum Mechanical Coulomb Problem to O(N^{2/3}) Storage"):
               cutoff on |I|; Sec. III shell closings), canonical order.
 * mesh     -- Gauss-Legendre nodes on the Laplace variable split at the cutoff,
               with the t = 1/sqrt(alpha) map on the tail (Eqs. 10-14), and the
-              geometric "Mesh 2" sub-intervals (Sec. III, Table I).
+              geometric "Mesh 2" sub-intervals (Sec. III, Table I); "Mesh 3"
+              integrates the same pieces in sqrt(beta) and the tail with a
+              rule for polynomials in t^2 (Sec. II, after Eq. 14).
 * tables   -- the 1-D integral of Eq. 8 for planewave factors, one table per
               quadrature node indexed by the two wavevector differences;
               for a rectangular box one such table per direction, at the
@@ -28,14 +30,14 @@ the mathematics say "parity unpinned" in their docstring; at present there
 are none.
 """
 from .basis import enumerate_basis, shell_counts
-from .mesh import gauss_legendre, mesh1, mesh2, default_mesh
+from .mesh import gauss_legendre, mesh1, mesh2, mesh3, default_mesh
 from .tables import primitives, tau_table, tau_diag, tau00_closed_form, box_tables
 from .sums import reconstruct, energies
 from .exchange_hist import diff_histogram, exchange_from_histogram
 from .physics import e_ks, k_cube
 
 __all__ = [
-    "enumerate_basis", "shell_counts", "gauss_legendre", "mesh1", "mesh2",
+    "enumerate_basis", "shell_counts", "gauss_legendre", "mesh1", "mesh2", "mesh3",
     "default_mesh", "primitives", "tau_table", "tau_diag", "tau00_closed_form", "box_tables",
     "reconstruct", "energies", "diff_histogram",
     "exchange_from_histogram", "e_ks", "k_cube",

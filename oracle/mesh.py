@@ -19,6 +19,17 @@ Mesh 2 (Sec. III, Table I right): interval 1 cut at beta_c * 5^{-7}, ...,
 beta_c * 5^{-1}, q points on each of the 8 pieces, plus q_tail tail points
 (the tail count is not printed; 8 is the default).
 
+Mesh 3 (not in the paper's tables; built on its suggestions in Sec. II after
+Eq. 14 that the nodes can be cut by matching the rule to the integrand's
+functional form and that a rule made for polynomials in x^2 is twice as
+efficient): interval 1 is cut into the same geometric pieces, but each piece
+is integrated by Gauss-Legendre in s = beta^{1/2}, beta = s^2 with weight
+2 s w (near beta = 0 the integrand is a power series in beta^{1/2}: each
+factor tends to sqrt(pi) - sqrt(beta) + ..., so in s it is polynomial-like);
+the tail uses the q_tail-point rule in t exact for polynomials in t^2 (the
+tail integrand of Eq. 11 is a series in t^2), i.e. the q_tail positive nodes
+of the 2 q_tail-point Gauss-Legendre rule on [-t_c, t_c].
+
 Gauss-Legendre rules are the roots of P_q and the weights 2/((1-x^2) P_q'^2),
 evaluated in 34-digit arithmetic (mpmath; numpy's eigenvalue nodes serve only
 as starting points of the Newton polish) and rounded to FP64 once, after the
@@ -116,3 +127,41 @@ def default_mesh(n_nodes: int, beta_c: float = 1.0):
     if n_nodes < 16 or n_nodes % 8:
         raise ValueError("default mesh needs Q >= 16 and Q % 8 == 0")
     return mesh2((n_nodes - 8) // 8, 8, 8, 5.0, beta_c)
+
+
+def _tail_even(q_tail: int, beta_c: float):
+    """Tail nodes of the rule in t exact for polynomials in t^2, degree
+    <= 4 q_tail - 2, on (0, beta_c^{-1/2}]: an even integrand's integral over
+    [-t_c, t_c] is twice that over [0, t_c], and the 2 q_tail-point
+    Gauss-Legendre rule on [-t_c, t_c] is symmetric, so its q_tail positive
+    nodes with their weights integrate [0, t_c].  Then beta = 1/t^2,
+    W = 2 w / t^3 as for the plain tail."""
+    with mp.workdps(_DPS):
+        xs, ws = _gl_unit(2 * q_tail)
+        tc = 1 / mp.sqrt(mp.mpf(beta_c))
+        pos = [(x, w) for x, w in zip(xs, ws) if x > 0]
+        t = [tc * x for x, _ in pos]
+        w = [tc * y for _, y in pos]
+        beta = [1 / (x * x) for x in t]
+        W = [2 * y / (x * x * x) for x, y in zip(t, w)]
+    return np.array([float(v) for v in beta]), np.array([float(v) for v in W])
+
+
+def mesh3(q_sub: int, q_tail: int = 4, n_sub: int = 4, ratio: float = 7.0,
+          beta_c: float = 1.0):
+    """Mesh 3: the geometric pieces of Mesh 2 (edges 0, beta_c ratio^{-(n_sub-1)},
+    ..., beta_c), each with q_sub Gauss-Legendre points in s = sqrt(beta)
+    (node beta = s^2, weight 2 s w), plus q_tail tail points of the rule exact
+    for polynomials in t^2 (see the module docstring).
+    Returns (beta, W, n_interval1)."""
+    edges = [0.0] + [beta_c * ratio ** (-(n_sub - 1 - k)) for k in range(n_sub)]
+    bs, ws = [], []
+    with mp.workdps(_DPS):
+        for k in range(n_sub):
+            s, w = _gl_mp(q_sub, mp.sqrt(mp.mpf(edges[k])), mp.sqrt(mp.mpf(edges[k + 1])))
+            bs.append(np.array([float(x * x) for x in s]))
+            ws.append(np.array([float(2 * x * y) for x, y in zip(s, w)]))
+    b2, w2 = _tail_even(q_tail, beta_c)
+    bs.append(b2)
+    ws.append(w2)
+    return np.concatenate(bs), np.concatenate(ws), n_sub * q_sub
