@@ -162,18 +162,22 @@ def pmc_workload():
 
 FIXED_ERROR_TARGETS = (("1e-9", 1e-9), ("six_place", 1e-6))
 FIXED_ERROR_Q = (32, 40, 48, 56, 64, 72, 80, 88, 96, 112, 128)
+ROOT_MESH_Q_SUB = (4, 5, 6, 7, 8, 9, 10, 12)     # Mesh 3: 4 pieces (ratio 7) x q_sub + 4 tail
 
 
 def fixed_error_leg(pw, w, quads, n, steps, warmup, ref=None):
     """Throughput at equal error.  For each target (1e-9 absolute on the
     integrals of L = 1, and six places: 1e-6 on the integrals and on
-    E_x/E_KS of the occupied sphere), the smallest default-mesh Q whose
-    results are within the target of the converged mesh (Q = 176, 8 x 21 + 8)
-    on a sample of the stream, then every path timed at that Q: the FP64
-    value table, FP64 node sums and split-FP32 node sums (node sums against
-    node sums is the like-for-like comparison).  `ref` holds the converged
-    references the oracle computed in the CPU-baseline leg (rows, integrals,
-    E_x/E_KS); without it the GPU's own Q = 176 value table stands in."""
+    E_x/E_KS of the occupied sphere), and for each mesh family -- the
+    paper's Mesh 2 (8 geometric pieces x q + 8 tail points) and Mesh 3 (4
+    pieces in sqrt(beta) x q + 4 tail points exact for polynomials in t^2) --
+    the smallest mesh whose results are within the target of the converged
+    oracle on a sample of the stream; every path is then timed on it: the
+    FP64 value table, FP64 node sums and split-FP32 node sums (node sums
+    against node sums is the like-for-like comparison).  `ref` holds the
+    converged references the oracle computed in the CPU-baseline leg (rows,
+    integrals, E_x/E_KS); without it the GPU's own Q = 176 Mesh 2 value
+    table stands in."""
     import torch
     if ref is None:
         half = n // 2
@@ -187,32 +191,31 @@ def fixed_error_leg(pw, w, quads, n, steps, warmup, ref=None):
     sample = quads[torch.from_numpy(ref["rows"]).cuda()].contiguous()
     occ = torch.arange(M, dtype=torch.int32, device="cuda")
     e_ks = -0.75 * (6.0 / math.pi) ** (1.0 / 3.0) * M ** (4.0 / 3.0) / w.L
+    families = {"mesh2": [(f"geometric 8x{(Q - 8) // 8}+8", pw.mesh_default(Q)) for Q in FIXED_ERROR_Q],
+                "mesh3": [(f"root 4x{q}+4 ratio 7", pw.Mesh.geometric_root(q, 4, n_sub=4, ratio=7.0))
+                          for q in ROOT_MESH_Q_SUB]}
     errs = {}
-    for Q in FIXED_ERROR_Q:
-        with pw.Table(w.L, w.n2max, Q) as t:
-            t.build_values()
-            got = t.reconstruct(sample).cpu().numpy()
-            _, ex = t.energies(occ)
-            t.sync()
-        e = {"integrals_max_abs": float(np.max(np.abs(got - ref["integrals"])))}
-        if ref.get("ratio") is not None:
-            e["ex_over_eks_abs"] = abs(ex / e_ks - ref["ratio"])
-        errs[Q] = e
+    for fam, meshes in families.items():
+        for name, mesh in meshes:
+            with pw.Table(w.L, w.n2max, 0, mesh=mesh) as t:
+                t.build_values()
+                got = t.reconstruct(sample).cpu().numpy()
+                _, ex = t.energies(occ)
+                t.sync()
+                e = {"Q": t.Q, "integrals_max_abs": float(np.max(np.abs(got - ref["integrals"])))}
+            if ref.get("ratio") is not None:
+                e["ex_over_eks_abs"] = abs(ex / e_ks - ref["ratio"])
+            errs[name] = e
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     eout = torch.empty(2, dtype=torch.float64, device="cuda")
     paths = (("fp64_value_table", pw.FP64, True), ("fp64_node_sums", pw.FP64, False),
              ("mixed_node_sums", pw.MIXED, False))
-    points = {}
-    for label, target in FIXED_ERROR_TARGETS:
-        q_star = next((Q for Q in FIXED_ERROR_Q
-                       if all(v <= target for v in errs[Q].values())), None)
-        if q_star is None:
-            points[label] = {"target": target, "Q": None}
-            continue
+
+    def rates_on(mesh):
         rates = {}
         for name, prec, values in paths:
             def step():
-                t = pw.Table(w.L, w.n2max, q_star)
+                t = pw.Table(w.L, w.n2max, 0, mesh=mesh)
                 if values:
                     t.build_values()
                 t.reconstruct(quads, out, precision=prec)
@@ -227,16 +230,30 @@ def fixed_error_leg(pw, w, quads, n, steps, warmup, ref=None):
                 step()
             torch.cuda.synchronize()
             rates[name] = n * steps / (time.perf_counter() - t0)
-        node = {k: v for k, v in rates.items() if k != "fp64_value_table"}
-        points[label] = {
-            "target": target, "Q": q_star, "errors_at_Q": errs[q_star],
-            "integrals_per_s": rates,
-            "mixed_vs_fp64_node_sums": rates["mixed_node_sums"] / rates["fp64_node_sums"],
-            "faster_node_sum_path": max(node, key=node.get),
-            "fastest_path": max(rates, key=rates.get)}
-    return {"reference": ref["source"], "reference_Q": 176, "sample_rows": len(ref["rows"]),
-            "occupied_M": M,
-            "errors_vs_converged": {str(k): v for k, v in errs.items()}, "points": points}
+        return rates
+
+    points = {}
+    for label, target in FIXED_ERROR_TARGETS:
+        pt = {"target": target}
+        for fam, meshes in families.items():
+            hit = next(((nm, m) for nm, m in meshes
+                        if all(v <= target for k, v in errs[nm].items() if k != "Q")), None)
+            if hit is None:
+                pt[fam] = {"mesh": None}
+                continue
+            rates = rates_on(hit[1])
+            node = {k: v for k, v in rates.items() if k != "fp64_value_table"}
+            pt[fam] = {"mesh": hit[0], "Q": errs[hit[0]]["Q"], "errors": errs[hit[0]],
+                       "integrals_per_s": rates,
+                       "mixed_vs_fp64_node_sums": rates["mixed_node_sums"] / rates["fp64_node_sums"],
+                       "faster_node_sum_path": max(node, key=node.get),
+                       "fastest_path": max(rates, key=rates.get)}
+        if pt.get("mesh2", {}).get("Q") and pt.get("mesh3", {}).get("Q"):
+            pt["mesh3_vs_mesh2_speedup"] = {k: pt["mesh3"]["integrals_per_s"][k] / pt["mesh2"]["integrals_per_s"][k]
+                                            for k in pt["mesh2"]["integrals_per_s"]}
+        points[label] = pt
+    return {"reference": ref["source"], "sample_rows": len(ref["rows"]), "occupied_M": M,
+            "errors_vs_converged": errs, "points": points}
 
 
 def configs_leg(pw, steps, warmup):
@@ -687,7 +704,9 @@ def main():
     if not args.no_fixed_error:
         fixed_error = fixed_error_leg(pw, w, quads, n, args.steps, args.warmup, converged)
         for label, pt in fixed_error["points"].items():
-            log(f"[bench] fixed error {label}: Q = {pt['Q']}, rates {pt.get('integrals_per_s')}")
+            for fam in ("mesh2", "mesh3"):
+                log(f"[bench] fixed error {label} {fam}: {pt[fam].get('mesh')} (Q = {pt[fam].get('Q')}), "
+                    f"rates {pt[fam].get('integrals_per_s')}")
 
     serving = None
     if not args.no_serve:

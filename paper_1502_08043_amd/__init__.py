@@ -21,6 +21,7 @@ FP64 = 0
 MIXED = 1
 MESH_GEOMETRIC = 0
 MESH_TWO_INTERVAL = 1
+MESH_GEOMETRIC_ROOT = 2
 PAIR_AUTO, PAIR_NODESUM, PAIR_KTABLE = 0, 1, 2
 
 OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_STATE, ERR_IO, ERR_LIMIT = range(9)
@@ -40,6 +41,11 @@ class Mesh(ctypes.Structure):
     @classmethod
     def geometric(cls, q_sub, q_tail=8, n_sub=8, ratio=5.0, alpha_c=0.0):
         return cls(MESH_GEOMETRIC, n_sub, ratio, q_sub, q_tail, alpha_c)
+
+    @classmethod
+    def geometric_root(cls, q_sub, q_tail=4, n_sub=4, ratio=7.0, alpha_c=0.0):
+        """Pieces in sqrt(beta), tail exact for polynomials in t^2."""
+        return cls(MESH_GEOMETRIC_ROOT, n_sub, ratio, q_sub, q_tail, alpha_c)
 
     @classmethod
     def two_interval(cls, q_sub, q_tail=None, alpha_c=0.0):

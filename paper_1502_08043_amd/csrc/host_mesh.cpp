@@ -146,7 +146,7 @@ bool mesh_valid(const pwc_mesh &m, int *n_nodes) {
     int Q = 0;
     if (m.q_sub < 1 || m.q_sub > 256 || m.q_tail < 1 || m.q_tail > 256) return false;
     if (!(std::isfinite(m.alpha_c))) return false;
-    if (m.kind == PWC_MESH_GEOMETRIC) {
+    if (m.kind == PWC_MESH_GEOMETRIC || m.kind == PWC_MESH_GEOMETRIC_ROOT) {
         if (m.n_sub < 1 || m.n_sub > 32 || !(m.ratio > 1.0) || !std::isfinite(m.ratio)) return false;
         Q = m.n_sub * m.q_sub + m.q_tail;
     } else if (m.kind == PWC_MESH_TWO_INTERVAL) {
@@ -168,14 +168,26 @@ bool build_mesh(const pwc_mesh &m, double L, std::vector<double> &beta, std::vec
     beta.clear();
     W.clear();
     std::vector<double> x, w;
-    if (m.kind == PWC_MESH_GEOMETRIC) {
+    std::vector<ext> se, we;
+    if (m.kind == PWC_MESH_GEOMETRIC || m.kind == PWC_MESH_GEOMETRIC_ROOT) {
         // Interval 1 cut geometrically: edges 0, beta_c r^{-(n-1)}, ..., beta_c r^{-1}, beta_c.
         double lo = 0.0;
         for (int k = 0; k < m.n_sub; ++k) {
             const double hi = beta_c * std::pow(m.ratio, -(m.n_sub - 1 - k));
-            gauss_legendre(m.q_sub, lo, hi, x, w);
-            beta.insert(beta.end(), x.begin(), x.end());
-            W.insert(W.end(), w.begin(), w.end());
+            if (m.kind == PWC_MESH_GEOMETRIC) {
+                gauss_legendre(m.q_sub, lo, hi, x, w);
+                beta.insert(beta.end(), x.begin(), x.end());
+                W.insert(W.end(), w.begin(), w.end());
+            } else {
+                // Gauss-Legendre in s = beta^{1/2} on [lo^{1/2}, hi^{1/2}]:
+                // beta = s^2, d beta = 2 s ds.  Near beta = 0 the integrand is
+                // a series in beta^{1/2}, smooth in s.
+                gauss_legendre_ext(m.q_sub, std::sqrt(static_cast<ext>(lo)), std::sqrt(static_cast<ext>(hi)), se, we);
+                for (int i = 0; i < m.q_sub; ++i) {
+                    beta.push_back(static_cast<double>(se[i] * se[i]));
+                    W.push_back(static_cast<double>(2.0L * se[i] * we[i]));
+                }
+            }
             lo = hi;
         }
     } else {
@@ -184,14 +196,25 @@ bool build_mesh(const pwc_mesh &m, double L, std::vector<double> &beta, std::vec
         W.insert(W.end(), w.begin(), w.end());
     }
     *n_interval1 = static_cast<int>(beta.size());
-    // Tail (Eqs. 11-13): Gauss-Legendre in t = beta^{-1/2} on (0, beta_c^{-1/2}];
+    // Tail (Eqs. 11-13): t = beta^{-1/2} on (0, t_c], t_c = beta_c^{-1/2};
     // d beta = -2 t^{-3} dt, so node t maps to beta = 1/t^2 with weight 2 w / t^3.
-    std::vector<ext> te, we;
-    gauss_legendre_ext(m.q_tail, 0.0L, 1.0L / std::sqrt(static_cast<ext>(beta_c)), te, we);
+    // Gauss-Legendre in t, or (GEOMETRIC_ROOT) the rule exact for
+    // polynomials in t^2 up to degree 4 q_tail - 2 -- the tail integrand is a
+    // series in t^2 (Eqs. 10-11) -- which is the positive half of the
+    // 2 q_tail-point Gauss-Legendre rule on [-t_c, t_c].
+    const ext tc = 1.0L / std::sqrt(static_cast<ext>(beta_c));
+    std::vector<ext> te, wt;
+    if (m.kind == PWC_MESH_GEOMETRIC_ROOT) {
+        gauss_legendre_ext(2 * m.q_tail, -tc, tc, te, wt);
+        te.erase(te.begin(), te.begin() + m.q_tail);   // ascending: the positive half
+        wt.erase(wt.begin(), wt.begin() + m.q_tail);
+    } else {
+        gauss_legendre_ext(m.q_tail, 0.0L, tc, te, wt);
+    }
     for (int i = 0; i < m.q_tail; ++i) {
         const ext t = te[i];
         beta.push_back(static_cast<double>(1.0L / (t * t)));
-        W.push_back(static_cast<double>(2.0L * we[i] / (t * t * t)));
+        W.push_back(static_cast<double>(2.0L * wt[i] / (t * t * t)));
     }
     return static_cast<int>(beta.size()) == Q;
 }

@@ -24,13 +24,16 @@ TOL_TABLE = 1e-14         # tables: relative to each node's largest |tau|
 @functools.lru_cache(maxsize=None)
 def setup(n2max, n_nodes=0, mesh=None, beta_c=1.0):
     """Oracle basis, mesh and tables.  mesh: None (default Mesh 2 for n_nodes),
-    ("geometric", q_sub, q_tail) or ("two_interval", q)."""
+    ("geometric", q_sub, q_tail), ("root", q_sub, q_tail, n_sub, ratio) (Mesh 3)
+    or ("two_interval", q)."""
     b = oracle.enumerate_basis(n2max)
     nmax = math.isqrt(n2max)
     if mesh is None:
         beta, W, n1 = oracle.default_mesh(n_nodes, beta_c)
     elif mesh[0] == "geometric":
         beta, W, n1 = oracle.mesh2(mesh[1], mesh[2], beta_c=beta_c)
+    elif mesh[0] == "root":
+        beta, W, n1 = oracle.mesh3(mesh[1], mesh[2], n_sub=mesh[3], ratio=mesh[4], beta_c=beta_c)
     else:
         beta, W, n1 = oracle.mesh1(mesh[1], beta_c=beta_c)
     tau = oracle.tau_table(beta, 2 * nmax)

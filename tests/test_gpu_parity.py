@@ -83,6 +83,66 @@ def test_tables_other_meshes(pw, kind):
         assert (np.abs(tau - o["tau"]).max(axis=(1, 2)) / scale).max() < P.TOL_TABLE
 
 
+@pytest.mark.parametrize("n2max,spec", [(169, (8, 4, 4, 7.0)), (40, (5, 3, 6, 5.0)), (9, (3, 2, 3, 10.0))])
+def test_root_mesh_tables_integrals_energies(pw, n2max, spec):
+    """Mesh 3 (GEOMETRIC_ROOT): mesh, tables, integrals on every path (direct
+    kernel, node passes, value table; both precisions) and energies (both pair
+    algorithms and precisions) against the oracle on the same mesh."""
+    import torch
+    q, qt, n_sub, ratio = spec
+    o = P.setup(n2max, mesh=("root", q, qt, n_sub, ratio))
+    m = pw.Mesh.geometric_root(q, qt, n_sub=n_sub, ratio=ratio)
+    N = len(o["basis"])
+    M = int(((o["basis"].astype(np.int64) ** 2).sum(1) <= min(n2max, 36)).sum())
+    with pw.Table(1.0, n2max, 0, mesh=m) as t:
+        beta, W = t.mesh_nodes()
+        assert np.max(np.abs(beta - o["beta"]) / o["beta"]) < 5e-16
+        assert np.max(np.abs(W - o["W"]) / o["W"]) < 5e-16
+        tau = t.copy_tables().cpu().numpy()
+        scale = np.abs(o["tau"]).max(axis=(1, 2))
+        assert (np.abs(tau - o["tau"]).max(axis=(1, 2)) / scale).max() < P.TOL_TABLE
+        quads = workloads.lookup_stream(N, M, 700_001, seed=n2max)
+        rows = workloads.sample_rows(len(quads), 20_000, seed=2)
+        t.set_direct_max(0)
+        _check_reconstruct(pw, t, o, quads[rows], label=f"root mesh passes {n2max}")
+        t.set_direct_max(1 << 19)
+        _check_reconstruct(pw, t, o, quads[rows], label=f"root mesh direct {n2max}")
+        t.build_values()
+        got = t.reconstruct(_dev(quads, torch.int32)).cpu().numpy()[rows]
+        t.sync()
+        ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads[rows])
+        err = P.worst_cond_err(got, ref, P.cond_scale(o["tau"], o["W"], o["basis"], quads[rows]))
+        assert err < P.TOL_FP64, err
+        occ = np.arange(M, dtype=np.int32)
+        f = workloads.occupations(M, seed=5)
+        eh, ex = oracle.energies(o["tau"], o["W"], o["basis"], occ, f)
+        for prec in (pw.FP64, pw.MIXED):
+            for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
+                gh, gx = t.energies(_dev(occ, torch.int32), _dev(f, torch.float64), precision=prec, algo=algo)
+                assert abs(gh - eh) < P.TOL_E_FP64 * eh and abs(gx - ex) < P.TOL_E_FP64 * abs(ex)
+
+
+def test_root_mesh_table_one_converged_ratio(pw):
+    """Sec. III, Table I: E_x/E_KS at M = 9171 from a 36-node Mesh 3 on the
+    GPU, within the printed precision of the converged 0.965431 and within
+    1e-12 of the oracle's histogram route on the same mesh."""
+    import json
+    import os
+    import torch
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+    b = oracle.enumerate_basis(169)
+    h, R = oracle.diff_histogram(b)
+    beta, W, _ = oracle.mesh3(8, 4, n_sub=4, ratio=7.0)
+    ref = oracle.exchange_from_histogram(h, R, oracle.tau_diag(beta, 2 * R), W)
+    occ = torch.arange(len(b), dtype=torch.int32, device="cuda")
+    with pw.Table(1.0, 169, 0, mesh=pw.Mesh.geometric_root(8, 4, n_sub=4, ratio=7.0)) as t:
+        for prec in (pw.FP64, pw.MIXED):
+            for algo in (pw.PAIR_KTABLE, pw.PAIR_NODESUM):
+                _, ex = t.energies(occ, precision=prec, algo=algo)
+                assert abs(ex - ref) < 1e-12 * abs(ref)
+                assert abs(ex / oracle.e_ks(len(b)) - g["mesh2"]["10"][1]) < 1.5e-6
+
+
 # ------------------------------------------------------------ integrals ----
 
 def _check_reconstruct(pw, t, o, quads, L=1.0, label=""):

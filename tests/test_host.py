@@ -50,6 +50,20 @@ def test_library_two_interval_mesh_matches_oracle(pw, q):
     assert np.max(np.abs(W - rw) / rw) <= 2.5e-16
 
 
+@pytest.mark.parametrize("q,qt,n_sub,ratio,alpha_c,L", [(8, 4, 4, 7.0, 0.0, 1.0), (5, 3, 6, 5.0, 0.0, 1.0),
+                                                   (12, 8, 8, 5.0, 0.0, 1.0), (7, 6, 4, 7.0, 0.25, 1.7),
+                                                   (20, 16, 2, 30.0, 0.0, 1.0), (1, 1, 1, 2.0, 0.0, 1.0)])
+def test_library_root_mesh_matches_oracle(pw, q, qt, n_sub, ratio, alpha_c, L):
+    """Mesh 3 (GEOMETRIC_ROOT): pieces in sqrt(beta), tail for polynomials in t^2."""
+    m = pw.Mesh.geometric_root(q, qt, n_sub=n_sub, ratio=ratio, alpha_c=alpha_c)
+    assert pw.mesh_count(m) == n_sub * q + qt
+    beta, W = pw.mesh_points(m, L=L)
+    bc = 4.0 * alpha_c / (L * L) if alpha_c > 0 else 1.0
+    rb, rw, n1 = oracle.mesh3(q, qt, n_sub=n_sub, ratio=ratio, beta_c=bc)
+    assert np.max(np.abs(beta - rb) / rb) <= 2.5e-16
+    assert np.max(np.abs(W - rw) / rw) <= 2.5e-16
+
+
 def test_library_fixed_alpha_mesh_scales_with_the_box(pw):
     # alpha_c = 0.25 bohr^2 in a box of side 2: beta_c = 4 alpha_c / L^2 = 0.25
     beta, W = pw.mesh_points(pw.Mesh.geometric(5, 8, alpha_c=0.25), L=2.0)
