@@ -22,6 +22,9 @@ Many-Electron Quantum Mechanical Coulomb Problem to O(N^{2/3}) Storage"):
 * sums     -- the node sum of Eq. 14 (reconstruction of <ij|kl>) and the
               uniform-electron-gas Hartree / exchange pair sums of Sec. III,
               in plain C with Neumaier-compensated FP64 accumulation.
+* gauss    -- the same scheme for a separable s-type Gaussian basis (Sec. II):
+              pair products, the closed-form 1-D factor, screened pairs, and
+              the node sum over the three direction factors.
 * exchange_hist -- an independent route to the exchange energy through the
               histogram of wavevector differences (cross-check only).
 
@@ -34,11 +37,13 @@ from .mesh import gauss_legendre, mesh1, mesh2, mesh3, default_mesh
 from .tables import primitives, tau_table, tau_diag, tau00_closed_form, box_tables
 from .sums import reconstruct, energies
 from .exchange_hist import diff_histogram, exchange_from_histogram
+from .gauss import gauss_pairs, pair_params, gauss_G, gauss_tau, gauss_decode, gauss_reconstruct
 from .physics import e_ks, k_cube
 
 __all__ = [
     "enumerate_basis", "shell_counts", "gauss_legendre", "mesh1", "mesh2", "mesh3",
     "default_mesh", "primitives", "tau_table", "tau_diag", "tau00_closed_form", "box_tables",
     "reconstruct", "energies", "diff_histogram",
-    "exchange_from_histogram", "e_ks", "k_cube",
+    "exchange_from_histogram", "e_ks", "k_cube", "gauss_pairs", "pair_params", "gauss_G",
+    "gauss_tau", "gauss_decode", "gauss_reconstruct",
 ]

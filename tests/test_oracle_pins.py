@@ -468,3 +468,103 @@ def test_box_axis_permutation_and_scaling():
     eh, ex = oracle.energies(t1, W, b, occ, L=L0)
     c00 = oracle.reconstruct(t1, W, b, np.zeros((1, 4), dtype=np.int32), L=L0)[0]
     assert abs(eh - 0.5 * 19 ** 2 * c00) < 1e-13 * eh and ex < 0
+
+
+# ------------------------------------------------------ Gaussian basis ----
+
+def _gauss_setup():
+    a, A = workloads.gaussian_set(workloads.GAUSS_SMALL)
+    pairs, pmap = oracle.gauss_pairs(a, A, 1e-15)
+    return a, A, pairs, pmap
+
+
+def test_gauss_factor_against_bruteforce_2d():
+    """The 1-D factor G(s) in closed form (Gaussian product theorem, then
+    two Gaussian integrals) against tensor Gauss-Legendre of its defining
+    double integral, for pairs at several separations and kernel widths."""
+    a, A, pairs, pmap = _gauss_setup()
+    c, p, P = oracle.pair_params(a, A, pairs)
+    for (u, v, up, vp) in [(0, 0, 0, 0), (0, 3, 5, 6), (1, 2, 9, 11), (4, 4, 10, 7), (2, 8, 3, 3)]:
+        x, y = pmap[u, v], pmap[up, vp]
+        assert x >= 0 and y >= 0
+        for s in (1e-3, 0.05, 0.7, 4.0, 60.0):
+            ref = _brute.gauss_G2d(s, a, A, u, v, up, vp, n=320)
+            got = oracle.gauss_G(s, c[x], p[x], P[x], c[y], p[y], P[y])
+            assert abs(got - ref) <= 2e-12 * abs(ref) + 1e-300, (u, v, up, vp, s, got, ref)
+
+
+def test_gauss_integrals_against_boys_closed_form():
+    """Isotropic s-type Gaussians (one exponent in all three directions): the
+    scheme's integrals (pair tables on a 46-node Mesh 3, reference length 8
+    bohr, about the extent of the centers) against the closed form through
+    the Boys function; the screened integrals are zero and their exact values
+    below 1e-16."""
+    a, A, pairs, pmap = _gauss_setup()
+    n1 = len(a)
+    ne = len(workloads.GAUSS_SMALL.exponents)
+    iso = np.array([(l * n1 + m) * n1 + n for l in range(n1) for m in range(n1) for n in range(n1)
+                    if l % ne == m % ne == n % ne])
+    quads = iso[workloads.rng(3).integers(0, len(iso), (3000, 4))]
+    lidx = oracle.gauss_decode(quads, n1)
+    ex = np.array([_brute.gauss_exact(a[lidx[r, :, 0]], A[lidx[r]], np.array([[0, 1, 2, 3]]))[0]
+                   for r in range(len(quads))])
+    beta, W, _ = oracle.mesh3(10, 6, n_sub=4, ratio=7.0)
+    L = 8.0
+    got = oracle.gauss_reconstruct(oracle.gauss_tau(beta, a, A, pairs, L=L), W, pmap, n1, quads, L=L)
+    kept = got != 0
+    assert kept.sum() > 2000
+    assert np.max(np.abs(got - ex)) < 1e-12
+    assert np.max(np.abs(got - ex)[kept] / np.abs(ex[kept])) < 1e-9
+    assert np.max(np.abs(ex[~kept])) < 1e-16
+
+
+@pytest.mark.slow
+def test_gauss_anisotropic_integrals_by_laplace_quadrature():
+    """Functions whose exponents differ between directions (no closed form):
+    pi^{-1/2} Int_0^inf s^{-1/2} prod_d G_d(s) ds with each G_d by brute-force
+    2-D quadrature and the s-integral by adaptive QUADPACK (the split at
+    s = 1 and the map s -> 1/s above it keep both ends finite), against the
+    scheme on its mesh."""
+    from scipy.integrate import quad
+    a, A, pairs, pmap = _gauss_setup()
+    n1 = len(a)
+    quads = np.array([[(0 * n1 + 3) * n1 + 5, (1 * n1 + 2) * n1 + 4, (2 * n1 + 1) * n1 + 7,
+                       (0 * n1 + 0) * n1 + 6],
+                      [(5 * n1 + 8) * n1 + 1, (9 * n1 + 9) * n1 + 2, (4 * n1 + 11) * n1 + 0,
+                       (6 * n1 + 7) * n1 + 3]])
+    lidx = oracle.gauss_decode(quads, n1)
+    beta, W, _ = oracle.mesh3(10, 6, n_sub=4, ratio=7.0)
+    L = 8.0
+    got = oracle.gauss_reconstruct(oracle.gauss_tau(beta, a, A, pairs, L=L), W, pmap, n1, quads, L=L)
+    for r in range(len(quads)):
+        l = lidx[r]
+
+        def integrand(s):
+            g = 1.0
+            for d in range(3):
+                g *= _brute.gauss_G2d(s, a, A, l[0, d], l[2, d], l[1, d], l[3, d], n=96)
+            return g / math.sqrt(s)
+        lo = quad(lambda t: integrand(t * t) * 2 * t, 0.0, 1.0, epsabs=1e-15, epsrel=1e-12, limit=200)[0]
+        hi = quad(lambda t: integrand(1.0 / t) / (t * t), 1e-12, 1.0, epsabs=1e-15, epsrel=1e-12,
+                  limit=200)[0]
+        ref = (lo + hi) / math.sqrt(math.pi)
+        assert abs(got[r] - ref) < 1e-9 * abs(ref), (r, got[r], ref)
+
+
+def test_gauss_integral_symmetries():
+    """Real functions: <ij|kl> = <kj|il> = <il|kj> = <jk|li>... the eight
+    permutations that keep i, k at r and j, l at r' or swap the two sides,
+    exactly; the screening is exact in the pair band."""
+    a, A, pairs, pmap = _gauss_setup()
+    n1 = len(a)
+    beta, W, _ = oracle.mesh3(8, 4)
+    tau = oracle.gauss_tau(beta, a, A, pairs, L=8.0)
+    q = workloads.uniform_quads(n1 ** 3, 2000, seed=4)
+    i, j, k, l = q.T
+    f = lambda *c: oracle.gauss_reconstruct(tau, W, pmap, n1, np.stack(c, 1), L=8.0)
+    v = f(i, j, k, l)
+    for perm in ((k, j, i, l), (i, l, k, j), (k, l, i, j), (j, i, l, k), (l, k, j, i)):
+        assert np.array_equal(v, f(*perm))
+    assert (v == 0).sum() > 0 and (v != 0).sum() > 0
+    with pytest.raises(IndexError):
+        oracle.gauss_reconstruct(tau, W, pmap, n1, np.array([[0, 0, 0, n1 ** 3]]))

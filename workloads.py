@@ -84,6 +84,35 @@ def sample_rows(n: int, k: int, seed: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Separable Gaussian basis: one-dimensional s-type Gaussians on a line of
+# centers, several exponents per center (the same set along x, y and z).
+
+@dataclass(frozen=True)
+class GaussianSet:
+    name: str
+    n_centers: int
+    exponents: tuple         # per center (bohr^-2)
+    spacing: float           # bohr between neighbouring centers
+    jitter: float            # uniform jitter of each center (bohr)
+    seed: int
+    n_nodes: int = 0         # default mesh node count for this set (0: caller's)
+
+
+GAUSS_SMALL = GaussianSet("gauss_12x2", 6, (0.6, 2.5), 1.4, 0.2, 31)
+GAUSS_BENCH = GaussianSet("gauss_24x2", 12, (0.8, 3.0), 1.5, 0.2, 1502)
+
+
+def gaussian_set(gs: GaussianSet):
+    """(exponents a [n1], centers A [n1]) with n1 = n_centers * len(exponents),
+    ordered by center, then exponent."""
+    g = rng(gs.seed)
+    centers = gs.spacing * np.arange(gs.n_centers) + g.uniform(-gs.jitter, gs.jitter, gs.n_centers)
+    a = np.array([e for _ in range(gs.n_centers) for e in gs.exponents], dtype=np.float64)
+    A = np.repeat(centers, len(gs.exponents)).astype(np.float64)
+    return a, A
+
+
+# ---------------------------------------------------------------------------
 # Serving workload: a Poisson stream of requests over many (L, cutoff, Q) keys.
 
 @dataclass
