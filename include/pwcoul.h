@@ -144,6 +144,9 @@ typedef struct {
 /* Maximum sizes accepted by pwc_table_create. */
 #define PWC_MAX_N2MAX 624    /* nmax <= 24, table dimension 4 nmax + 1 <= 97 */
 #define PWC_MAX_NODES 512
+/* ... and by pwc_table_create_gauss (n1^3 basis functions fit an int32). */
+#define PWC_GAUSS_MAX_N1 1290
+#define PWC_GAUSS_MAX_PAIRS 8192
 
 typedef struct pwc_table pwc_table;
 typedef struct pwc_server pwc_server;
@@ -209,6 +212,41 @@ PWC_API pwc_status pwc_table_create(double L, int n2max, int n_nodes, const pwc_
  */
 PWC_API pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int n_nodes,
                                         const pwc_mesh *mesh, void *stream, pwc_table **out);
+
+/*
+ * Tables for a separable basis of s-type Gaussians (Sec. II: products of
+ * one-dimensional Gaussians are the other common separable basis; the paper
+ * works the formulas out for planewaves only).  One-dimensional functions
+ * f_u(x) = (2 a_u / pi)^{1/4} exp(-a_u (x - A_u)^2), u < n1, from h_exp
+ * (a_u > 0, bohr^-2) and h_center (A_u, bohr), host arrays [n1]; the same set
+ * along x, y and z, and every product is a basis function:
+ * I = (l n1 + m) n1 + n is f_l(x) f_m(y) f_n(z), N = n1^3.
+ * <ij|kl> = Int Int g_i(r) g_k(r) g_j(r') g_l(r') / |r - r'| (the functions
+ * are real).  Writing 1/r = pi^{-1/2} Int s^{-1/2} exp(-s r^2) ds with
+ * s = 1/(beta L^2), the factor of direction d is the closed form
+ *   tau_q(x, y) = c_x c_y pi / sqrt(p_x p_y beta_q + (p_x + p_y)/L^2)
+ *                 exp(-p_x p_y (P_x - P_y)^2 / (p_x p_y beta_q L^2 + p_x + p_y)),
+ * for the one-dimensional pair products f_u f_v = c exp(-p (x - P)^2) of
+ * (i, k) (x) and (j, l) (y), and <ij|kl> = (1/(sqrt(pi) L)) sum_q W_q
+ * tau_q tau_q tau_q (Eq. 14).  L is a reference length for the mesh
+ * (beta = 4 alpha / L^2); about the extent of the centers serves well.  A
+ * pair (u, v) is kept when exp(-(a_u a_v/(a_u + a_v))(A_u - A_v)^2) >= eps
+ * (0 <= eps < 1): the band of eta N^{1/3} products of Sec. II; an integral
+ * that needs a dropped pair is zero.  Tables: the full FP64 [Q][P1][P1]
+ * (pwc_table_copy; P1 kept pairs) and the folded pairs of pairs with the
+ * weights, FP64 and split FP32.  pwc_reconstruct (both precisions, any n,
+ * async) and pwc_sync, pwc_table_copy, pwc_mesh_nodes, pwc_table_info
+ * (N = n1^3) and pwc_table_destroy take such a table; the planewave calls
+ * (energies, value table, layouts, files, basis vectors, no-allocation and
+ * profiled reconstruction) return PWC_ERR_ARG.  PWC_ERR_ARG for invalid
+ * inputs, PWC_ERR_RANGE if more than PWC_GAUSS_MAX_PAIRS pairs are kept.
+ * pwc_gauss_info reports n1, the kept pairs and eps (PWC_ERR_ARG for a
+ * planewave table).  Mesh, stream and ownership as pwc_table_create.
+ */
+PWC_API pwc_status pwc_table_create_gauss(const double *h_exp, const double *h_center, int n1,
+                                          double L, double eps, int n_nodes, const pwc_mesh *mesh,
+                                          void *stream, pwc_table **out);
+PWC_API pwc_status pwc_gauss_info(const pwc_table *t, int *n1, int *n_pairs, double *eps);
 
 /*
  * Free a table.  NULL is accepted.  The call does not wait for the device:

@@ -89,14 +89,14 @@ def gauss_tau(beta, a, A, pairs, L=1.0):
     c, p, P = pair_params(a, A, pairs)
     n = len(pairs)
     out = np.empty((beta.size, n, n))
+    # every (x, y) entry by the formula, elementwise over the pair grid
+    pq = p[:, None] * p[None, :]
+    ps = p[:, None] + p[None, :]
+    cc = c[:, None] * c[None, :]
+    d2 = (P[:, None] - P[None, :]) ** 2
     for iq, b in enumerate(beta):
-        for x in range(n):
-            for y in range(n):
-                pq = p[x] * p[y]
-                ps = p[x] + p[y]
-                den = pq * b + ps / (L * L)
-                out[iq, x, y] = c[x] * c[y] * math.pi / math.sqrt(den) * \
-                    math.exp(-pq * (P[x] - P[y]) ** 2 / (pq * b * L * L + ps))
+        den = pq * b + ps / (L * L)
+        out[iq] = cc * math.pi / np.sqrt(den) * np.exp(-pq * d2 / (pq * b * L * L + ps))
     return out
 
 

@@ -101,6 +101,10 @@ def lib():
             "pwc_sync": (i32, [vp, vp]),
             "pwc_reconstruct_profile": (i32, [vp, vp, i64, vp, i32, vp, vp, i32,
                                               ctypes.POINTER(i32)]),
+            "pwc_table_create_gauss": (i32, [vp, vp, i32, dbl, dbl, i32, ctypes.POINTER(Mesh), vp,
+                                             ctypes.POINTER(vp)]),
+            "pwc_gauss_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -376,6 +380,40 @@ class Table:
     def sync(self, stream=None):
         """Wait for the stream and raise PwcError if a kernel saw a bad index."""
         _check(lib().pwc_sync(self.handle, _stream(stream)), "pwc_sync")
+
+
+class GaussTable(Table):
+    """Tables of a separable s-type Gaussian basis (pwc_table_create_gauss):
+    one-dimensional exponents `exps` and centers `centers` (host arrays [n1]),
+    the same set along x, y and z; basis function (l n1 + m) n1 + n is
+    f_l(x) f_m(y) f_n(z).  reconstruct / sync / copy_tables / mesh_nodes as
+    for planewave tables."""
+
+    def __init__(self, exps, centers, L, eps=1e-15, n_nodes=0, mesh=None, stream=None):
+        a = np.ascontiguousarray(exps, dtype=np.float64)
+        A = np.ascontiguousarray(centers, dtype=np.float64)
+        if a.shape != A.shape or a.ndim != 1:
+            raise ValueError("exps and centers must be 1-D arrays of one length")
+        h = ctypes.c_void_p()
+        mp = ctypes.byref(mesh) if mesh is not None else None
+        _check(lib().pwc_table_create_gauss(a.ctypes.data_as(ctypes.c_void_p),
+                                            A.ctypes.data_as(ctypes.c_void_p), len(a), float(L),
+                                            float(eps), int(n_nodes), mp, _stream(stream),
+                                            ctypes.byref(h)), "pwc_table_create_gauss")
+        super().__init__(None, 0, _handle=h)
+        n1, npair, e = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().pwc_gauss_info(h, ctypes.byref(n1), ctypes.byref(npair), ctypes.byref(e)),
+               "pwc_gauss_info")
+        self.n1, self.n_pairs, self.eps = n1.value, npair.value, e.value
+        self.nd = self.n_pairs
+
+    def copy_tables(self, out=None, stream=None):
+        """FP64 tables as a device tensor [Q, P1, P1] over the kept pairs."""
+        if out is None:
+            out = torch.empty((self.Q, self.n_pairs, self.n_pairs), dtype=torch.float64, device="cuda")
+        _check(lib().pwc_table_copy(self.handle, _dev_ptr(out, torch.float64, "out"),
+                                    _stream(stream)), "pwc_table_copy")
+        return out
 
 
 # ---------------------------------------------------------------- serving ----

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "host_mesh.cpp", "server.cpp", "table_kernels.hip",
            "reconstruct_kernels.hip", "direct_kernels.hip", "value_kernels.hip",
-           "pairsum_kernels.hip"]
+           "pairsum_kernels.hip", "gauss_kernels.hip"]
 
 # -ffp-contract=off: the split-FP32 arithmetic relies on unfused products; FMAs
 # are written explicitly where they are wanted.  Packed FP32 instructions are

@@ -543,6 +543,111 @@ pwc_status build_table(Table &t, const TableSetup &su, hipStream_t s, const doub
     return st;
 }
 
+// Separable Gaussian basis.  Host set-up: the kept pairs u <= v with
+// exp(-(a_u a_v / p)(A_u - A_v)^2) >= eps, numbered by u then v, their product
+// parameters (c, p, P) and the pair map; then one allocation holding the map,
+// the pair parameters, mesh, weights, error words, the full tables and the
+// folded rows (the last folded row stays zero).
+pwc_status plan_gauss(const double *a, const double *A, int n1, double L, double eps,
+                      const pwc_mesh &m, Table &t) {
+    if (n1 < 1 || n1 > kGaussMaxN1 || !(L > 0.0) || !std::isfinite(L) || !(eps >= 0.0) || !(eps < 1.0))
+        return PWC_ERR_ARG;
+    for (int u = 0; u < n1; ++u)
+        if (!(a[u] > 0.0) || !std::isfinite(a[u]) || !std::isfinite(A[u])) return PWC_ERR_ARG;
+    t.gauss = true;
+    t.n1 = n1;
+    t.eps = eps;
+    t.L = L;
+    for (int d = 0; d < 3; ++d) {
+        t.Ld[d] = L;
+        t.rho[d] = 1.0;
+    }
+    t.ndir = 1;
+    t.mesh = m;
+    t.N = static_cast<int64_t>(n1) * n1 * n1;
+    t.h_pmap.assign(static_cast<size_t>(n1) * n1, -1);
+    t.h_pair.clear();
+    int P1 = 0;
+    for (int u = 0; u < n1; ++u)
+        for (int v = u; v < n1; ++v) {
+            const double p = a[u] + a[v];
+            const double dA = A[u] - A[v];
+            const double K = std::exp(-(a[u] * a[v] / p) * (dA * dA));
+            if (!(K >= eps)) continue;
+            if (P1 >= kGaussMaxPairs) return PWC_ERR_RANGE;
+            t.h_pmap[static_cast<size_t>(u) * n1 + v] = t.h_pmap[static_cast<size_t>(v) * n1 + u] = P1++;
+            const double c = std::pow(2.0 * a[u] / M_PI, 0.25) * std::pow(2.0 * a[v] / M_PI, 0.25) * K;
+            t.h_pair.push_back(c);
+            t.h_pair.push_back(p);
+            t.h_pair.push_back((a[u] * A[u] + a[v] * A[v]) / p);
+        }
+    t.P1 = P1;
+    if (!build_mesh(m, L, t.h_beta, t.h_W, &t.n_interval1)) return PWC_ERR_ARG;
+    t.Q = static_cast<int>(t.h_beta.size());
+    t.E1 = P1 * (P1 + 1) / 2 + 1;    // folded pairs of pairs, then the zero row
+    t.fl.E = t.flm.E = t.E1;
+    t.fl.Qp = t.flm.Qp = (t.Q + 31) / 32 * 32;
+    t.nd = P1;
+    (void)hipGetDevice(&t.device);
+    if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
+        t.n_cu <= 0)
+        t.n_cu = 256;
+    const size_t Q = static_cast<size_t>(t.Q), Qp = static_cast<size_t>(t.fl.Qp);
+    t.bytes = align256(sizeof(int32_t) * t.h_pmap.size()) + align256(sizeof(double) * t.h_pair.size() + 8) +
+              3 * align256(sizeof(double) * Q) + align256(sizeof(int) * 64) +
+              align256(sizeof(double) * Q * P1 * P1) + align256(sizeof(double) * Qp * t.E1) +
+              align256(sizeof(float2) * Qp * t.E1);
+    return PWC_OK;
+}
+
+pwc_status build_gauss(Table &t, hipStream_t s) {
+    hipError_t e = dev_alloc(t.bytes, &t.d_block, &t.block_bytes);
+    if (e != hipSuccess) {
+        t.d_block = nullptr;
+        return from_hip(e);
+    }
+    t.uses = std::make_shared<UseLog>();
+    const size_t Q = static_cast<size_t>(t.Q), Qp = static_cast<size_t>(t.fl.Qp), P1 = static_cast<size_t>(t.P1);
+    char *base = static_cast<char *>(t.d_block);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { char *p = base + off; off += align256(bytes); return p; };
+    t.d_pmap = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.h_pmap.size()));
+    t.d_pair = reinterpret_cast<double *>(take(sizeof(double) * t.h_pair.size() + 8));
+    t.d_beta = reinterpret_cast<double *>(take(sizeof(double) * Q));
+    t.d_W = reinterpret_cast<double *>(take(sizeof(double) * Q));
+    t.d_Wcbrt = reinterpret_cast<double *>(take(sizeof(double) * Q));
+    t.d_err = reinterpret_cast<int *>(take(sizeof(int) * 64));
+    t.d_tau = reinterpret_cast<double *>(take(sizeof(double) * Q * P1 * P1));
+    t.d_tauF = reinterpret_cast<double *>(take(sizeof(double) * Qp * t.E1));
+    t.d_tauHL = reinterpret_cast<float2 *>(take(sizeof(float2) * Qp * t.E1));
+    // Host image of the inputs (map .. error words), one upload; the folded
+    // rows start as zero (node padding and the zero row).
+    const size_t in_bytes = static_cast<size_t>(reinterpret_cast<char *>(t.d_tau) - base);
+    auto img = std::make_shared<std::vector<char>>(in_bytes, 0);
+    auto put = [&](const void *dst, const void *src, size_t bytes) {
+        std::memcpy(img->data() + (static_cast<const char *>(dst) - base), src, bytes);
+    };
+    std::vector<double> Wcbrt(Q);
+    for (size_t q = 0; q < Q; ++q) Wcbrt[q] = static_cast<double>(std::cbrt(static_cast<long double>(t.h_W[q])));
+    put(t.d_pmap, t.h_pmap.data(), sizeof(int32_t) * t.h_pmap.size());
+    put(t.d_pair, t.h_pair.data(), sizeof(double) * t.h_pair.size());
+    put(t.d_beta, t.h_beta.data(), sizeof(double) * Q);
+    put(t.d_W, t.h_W.data(), sizeof(double) * Q);
+    put(t.d_Wcbrt, Wcbrt.data(), sizeof(double) * Q);
+    t.h_img = img;   // kept until destroy: the copy may still read it
+    pwc_status st = from_hip(hipMemcpyAsync(base, img->data(), in_bytes, hipMemcpyHostToDevice, s));
+    if (st == PWC_OK)
+        st = from_hip(hipMemsetAsync(t.d_tauF, 0, static_cast<size_t>(base + t.bytes - reinterpret_cast<char *>(t.d_tauF)), s));
+    if (st == PWC_OK && t.P1 > 0) st = from_hip(launch_gauss_tables(t, s));
+    if (st == PWC_OK) st = from_hip(hipEventCreateWithFlags(&t.ready, hipEventDisableTiming));
+    if (st == PWC_OK) st = from_hip(hipEventRecord(t.ready, s));
+    if (st != PWC_OK) {
+        (void)hipStreamSynchronize(s);
+        free_table(t);
+    }
+    return st;
+}
+
 }  // namespace pwc
 
 extern "C" {
@@ -609,6 +714,41 @@ pwc_status pwc_table_create_box(double Lx, double Ly, double Lz, int n2max, int 
         return st;
     }
     *out = h;
+    return PWC_OK;
+}
+
+pwc_status pwc_table_create_gauss(const double *h_exp, const double *h_center, int n1, double L,
+                                  double eps, int n_nodes, const pwc_mesh *mesh, void *stream,
+                                  pwc_table **out) {
+    if (!out) return PWC_ERR_ARG;
+    *out = nullptr;
+    if (!h_exp || !h_center) return PWC_ERR_ARG;
+    pwc_mesh m{};
+    if (mesh) {
+        int q = 0;
+        if (!pwc::mesh_valid(*mesh, &q)) return PWC_ERR_ARG;
+        if (n_nodes != 0 && n_nodes != q) return PWC_ERR_ARG;
+        m = *mesh;
+    } else if (pwc_mesh_default(n_nodes, &m) != PWC_OK) {
+        return PWC_ERR_ARG;
+    }
+    pwc_table *h = new (std::nothrow) pwc_table;
+    if (!h) return PWC_ERR_NOMEM;
+    pwc_status st = pwc::plan_gauss(h_exp, h_center, n1, L, eps, m, h->t);
+    if (st == PWC_OK) st = pwc::build_gauss(h->t, static_cast<hipStream_t>(stream));
+    if (st != PWC_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return PWC_OK;
+}
+
+pwc_status pwc_gauss_info(const pwc_table *t, int *n1, int *n_pairs, double *eps) {
+    if (!t || !t->t.gauss) return PWC_ERR_ARG;
+    if (n1) *n1 = t->t.n1;
+    if (n_pairs) *n_pairs = t->t.P1;
+    if (eps) *eps = t->t.eps;
     return PWC_OK;
 }
 
@@ -761,7 +901,7 @@ pwc_status table_load(const char *path, void *stream, pwc_table **out) {
 }  // namespace
 
 pwc_status pwc_table_save(const pwc_table *t, const char *path) {
-    if (!t || !path) return PWC_ERR_ARG;
+    if (!t || !path || t->t.gauss) return PWC_ERR_ARG;
     try {
         return table_save(t->t, path);
     } catch (const std::bad_alloc &) {
@@ -820,7 +960,7 @@ pwc_status pwc_basis_enumerate(int n2max, int32_t *h_n, int64_t *N) {
 }
 
 pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
-    if (!t) return PWC_ERR_ARG;
+    if (!t || t->t.gauss) return PWC_ERR_ARG;
     pwc::Table &tb = t->t;
     if (tb.d_val) return PWC_OK;
     const size_t bytes = sizeof(double) * static_cast<size_t>(pwc::value_count(tb));
@@ -855,7 +995,7 @@ pwc_status pwc_table_build_values(pwc_table *t, void *stream) {
 pwc_status pwc_table_values_info(const pwc_table *t, int *built, size_t *bytes) {
     if (!t) return PWC_ERR_ARG;
     if (built) *built = t->t.d_val != nullptr;
-    if (bytes) *bytes = sizeof(double) * static_cast<size_t>(pwc::value_count(t->t));
+    if (bytes) *bytes = t->t.gauss ? 0 : sizeof(double) * static_cast<size_t>(pwc::value_count(t->t));
     return PWC_OK;
 }
 
@@ -880,7 +1020,7 @@ pwc_status pwc_release_cached_memory(void) {
 
 pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int *words,
                             int *nodes_per_pass, int *passes, int *entry_bytes) {
-    if (!t || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
     const pwc::FoldLayout &fl = p == PWC_MIXED ? t->t.flm : t->t.fl;
     if (lanes) *lanes = fl.G;
     if (words) *words = fl.W;
@@ -891,7 +1031,7 @@ pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int
 }
 
 pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
-    if (!t) return PWC_ERR_ARG;
+    if (!t || t->t.gauss) return PWC_ERR_ARG;
     if (lanes == 0 && words != 0) return PWC_ERR_ARG;
     if (lanes != 0) {
         const bool ok = (lanes == 16 && words == 1) || ((lanes == 8 || lanes == 4) && (words == 1 || words == 2)) ||
@@ -922,7 +1062,7 @@ pwc_status pwc_table_box(const pwc_table *t, double *sides) {
 }
 
 pwc_status pwc_basis(const pwc_table *t, int32_t *h_n) {
-    if (!t || !h_n) return PWC_ERR_ARG;
+    if (!t || !h_n || t->t.gauss) return PWC_ERR_ARG;
     std::memcpy(h_n, t->t.h_basis->n.data(), sizeof(int32_t) * t->t.h_basis->n.size());
     return PWC_OK;
 }
@@ -936,6 +1076,7 @@ pwc_status pwc_mesh_nodes(const pwc_table *t, double *h_beta, double *h_W) {
 
 pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
     if (!t || !d_dst) return PWC_ERR_ARG;
+    // [ndir][Q][nd][nd]; a Gaussian table: [Q][P1][P1] (nd = P1, ndir = 1)
     const size_t bytes = sizeof(double) * t->t.ndir * t->t.Q * t->t.nd * t->t.nd;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = pwc::wait_ready(t->t, s);
@@ -955,7 +1096,9 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
     const hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = pwc::wait_ready(t->t, s);
     if (e != hipSuccess) return from_hip(e);
-    if (t->t.d_val && p == PWC_FP64) {   // every distinct value is at hand: one read each
+    if (t->t.gauss) {                    // separable Gaussians: rows from global memory
+        e = pwc::launch_rec_gauss(t->t, d_quads, n, d_out, p, s);
+    } else if (t->t.d_val && p == PWC_FP64) {   // every distinct value is at hand: one read each
         e = pwc::launch_rec_values(t->t, d_quads, n, d_out, s);
     } else if (n <= t->t.direct_max) {   // small list: four lanes per quadruple, no node passes
         pwc::DirectBatch b{};
@@ -971,7 +1114,7 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
 
 pwc_status pwc_reconstruct_noalloc(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                    double *d_out, pwc_precision p, void *stream) {
-    if (!t || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
     if (n > PWC_NOALLOC_MAX_QUADS) return PWC_ERR_LIMIT;
     if (n == 0) return PWC_OK;
     if (!d_quads || !d_out) return PWC_ERR_ARG;
@@ -996,7 +1139,7 @@ pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n) {
 pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                    double *d_out, pwc_precision p, void *stream, double *h_ms,
                                    int max_stages, int *n_stages) {
-    if (!t || !h_ms || !n_stages || n <= 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || !h_ms || !n_stages || n <= 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
@@ -1024,7 +1167,7 @@ pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, i
 pwc_status pwc_energies_ex(const pwc_table *t, const int32_t *d_occ, const double *d_f,
                            int64_t M, pwc_precision p, pwc_pair_algo algo, double *d_out,
                            void *stream) {
-    if (!t || !d_out || M < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || !d_out || M < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
     if (algo != PWC_PAIR_AUTO && algo != PWC_PAIR_NODESUM && algo != PWC_PAIR_KTABLE)
         return PWC_ERR_ARG;
     if (algo == PWC_PAIR_KTABLE && t->t.kt_n == 0) return PWC_ERR_ARG;

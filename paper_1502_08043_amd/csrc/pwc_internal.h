@@ -61,6 +61,8 @@ struct FoldLayout {
     int nchunk = 0;     // passes P = ceil(Q / c)
 };
 constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
+constexpr int kGaussMaxN1 = PWC_GAUSS_MAX_N1;
+constexpr int kGaussMaxPairs = PWC_GAUSS_MAX_PAIRS;
 constexpr int64_t kRecSlab = int64_t(1) << 27;   // quadruples per scratch slab
 
 struct DiagLayout {
@@ -138,6 +140,16 @@ struct Table {
     hipEvent_t ready = nullptr;
     std::shared_ptr<const std::vector<char>> h_img;   // upload source, alive until destroy
     std::shared_ptr<UseLog> uses;   // created by build_table
+    // Separable Gaussian basis (pwc_table_create_gauss): the same node sums
+    // over a table of kept one-dimensional pair products.  Fields of the
+    // planewave layout that a Gaussian table does not use stay empty.
+    bool gauss = false;
+    int n1 = 0, P1 = 0;             // functions per direction, kept pairs
+    double eps = 0.0;               // pair screening threshold
+    std::vector<int32_t> h_pmap;    // [n1][n1] pair index or -1
+    std::vector<double> h_pair;     // [P1][3] (c, p, P)
+    int32_t *d_pmap = nullptr;
+    double *d_pair = nullptr;
 };
 
 // Record that work on the table's memory was queued on stream s (after the
@@ -175,6 +187,11 @@ void dev_release(void *p, size_t bytes, EventSet *es = nullptr);
 
 // table_kernels.hip
 hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau);
+// gauss_kernels.hip: the Gaussian tables (full [Q][P1][P1], folded rows with
+// W^(1/3), split FP32) and the reconstruction from them.
+hipError_t launch_gauss_tables(const Table &t, hipStream_t s);
+hipError_t launch_rec_gauss(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
+                            pwc_precision p, hipStream_t s, int *d_err = nullptr);
 // reconstruct_kernels.hip
 // Bytes of one decoded quadruple in the scratch stream (4 when E <= 1024).
 int packed_entry_bytes(int E);
