@@ -194,63 +194,77 @@ def fixed_error_leg(pw, w, quads, n, steps, warmup, ref=None):
     families = {"mesh2": [(f"geometric 8x{(Q - 8) // 8}+8", pw.mesh_default(Q)) for Q in FIXED_ERROR_Q],
                 "mesh3": [(f"root 4x{q}+4 ratio 7", pw.Mesh.geometric_root(q, 4, n_sub=4, ratio=7.0))
                           for q in ROOT_MESH_Q_SUB]}
+    # errors of each mesh: the FP64 paths (value table; node sums and split
+    # FP32 agree with it to 1e-12) and the single-FP32 path (its table
+    # rounding adds up to 4.2e-7 of the node terms)
     errs = {}
     for fam, meshes in families.items():
         for name, mesh in meshes:
             with pw.Table(w.L, w.n2max, 0, mesh=mesh) as t:
+                t.set_direct_max(0)
+                got32 = t.reconstruct(sample, precision=pw.FP32).cpu().numpy()
                 t.build_values()
                 got = t.reconstruct(sample).cpu().numpy()
                 _, ex = t.energies(occ)
                 t.sync()
-                e = {"Q": t.Q, "integrals_max_abs": float(np.max(np.abs(got - ref["integrals"])))}
+                e = {"integrals_max_abs": float(np.max(np.abs(got - ref["integrals"])))}
+                e32 = {"integrals_max_abs": float(np.max(np.abs(got32 - ref["integrals"])))}
+                q_nodes = t.Q
             if ref.get("ratio") is not None:
-                e["ex_over_eks_abs"] = abs(ex / e_ks - ref["ratio"])
-            errs[name] = e
+                e["ex_over_eks_abs"] = e32["ex_over_eks_abs"] = abs(ex / e_ks - ref["ratio"])
+            errs[name] = {"Q": q_nodes, "fp64": e, "fp32": e32}
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     eout = torch.empty(2, dtype=torch.float64, device="cuda")
-    paths = (("fp64_value_table", pw.FP64, True), ("fp64_node_sums", pw.FP64, False),
-             ("mixed_node_sums", pw.MIXED, False))
+    # (name, precision, value table, which error decides its mesh); the FP32
+    # step takes its energies in FP64 (the FP32 table serves reconstruction)
+    paths = (("fp64_value_table", pw.FP64, True, "fp64"), ("fp64_node_sums", pw.FP64, False, "fp64"),
+             ("mixed_node_sums", pw.MIXED, False, "fp64"), ("fp32_node_sums", pw.FP32, False, "fp32"))
 
-    def rates_on(mesh):
-        rates = {}
-        for name, prec, values in paths:
-            def step():
-                t = pw.Table(w.L, w.n2max, 0, mesh=mesh)
-                if values:
-                    t.build_values()
-                t.reconstruct(quads, out, precision=prec)
-                t.energies_async(occ, None, prec, eout)
-                t.sync()
-                t.close()
-            for _ in range(warmup):
-                step()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                step()
-            torch.cuda.synchronize()
-            rates[name] = n * steps / (time.perf_counter() - t0)
-        return rates
+    def rate(mesh, prec, values):
+        def step():
+            t = pw.Table(w.L, w.n2max, 0, mesh=mesh)
+            if values:
+                t.build_values()
+            t.reconstruct(quads, out, precision=prec)
+            t.energies_async(occ, None, pw.FP64 if prec == pw.FP32 else prec, eout)
+            t.sync()
+            t.close()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return n * steps / (time.perf_counter() - t0)
 
     points = {}
     for label, target in FIXED_ERROR_TARGETS:
         pt = {"target": target}
         for fam, meshes in families.items():
-            hit = next(((nm, m) for nm, m in meshes
-                        if all(v <= target for k, v in errs[nm].items() if k != "Q")), None)
-            if hit is None:
-                pt[fam] = {"mesh": None}
-                continue
-            rates = rates_on(hit[1])
-            node = {k: v for k, v in rates.items() if k != "fp64_value_table"}
-            pt[fam] = {"mesh": hit[0], "Q": errs[hit[0]]["Q"], "errors": errs[hit[0]],
-                       "integrals_per_s": rates,
-                       "mixed_vs_fp64_node_sums": rates["mixed_node_sums"] / rates["fp64_node_sums"],
-                       "faster_node_sum_path": max(node, key=node.get),
-                       "fastest_path": max(rates, key=rates.get)}
-        if pt.get("mesh2", {}).get("Q") and pt.get("mesh3", {}).get("Q"):
-            pt["mesh3_vs_mesh2_speedup"] = {k: pt["mesh3"]["integrals_per_s"][k] / pt["mesh2"]["integrals_per_s"][k]
-                                            for k in pt["mesh2"]["integrals_per_s"]}
+            res = {"integrals_per_s": {}, "mesh": {}, "Q": {}, "errors": {}}
+            for name, prec, values, which in paths:
+                hit = next((nm for nm, m in meshes
+                            if all(v <= target for v in errs[nm][which].values())), None)
+                if hit is None:
+                    continue
+                mesh = dict(meshes)[hit]
+                res["integrals_per_s"][name] = rate(mesh, prec, values)
+                res["mesh"][name], res["Q"][name] = hit, errs[hit]["Q"]
+                res["errors"][name] = errs[hit][which]
+            r = res["integrals_per_s"]
+            node = {k: v for k, v in r.items() if k != "fp64_value_table"}
+            if "mixed_node_sums" in r and "fp64_node_sums" in r:
+                res["mixed_vs_fp64_node_sums"] = r["mixed_node_sums"] / r["fp64_node_sums"]
+            if "fp32_node_sums" in r and "fp64_node_sums" in r:
+                res["fp32_vs_fp64_node_sums"] = r["fp32_node_sums"] / r["fp64_node_sums"]
+            if node:
+                res["faster_node_sum_path"] = max(node, key=node.get)
+            if r:
+                res["fastest_path"] = max(r, key=r.get)
+            pt[fam] = res
+        r2, r3 = pt["mesh2"]["integrals_per_s"], pt["mesh3"]["integrals_per_s"]
+        pt["mesh3_vs_mesh2_speedup"] = {k: r3[k] / r2[k] for k in r2 if k in r3}
         points[label] = pt
     return {"reference": ref["source"], "sample_rows": len(ref["rows"]), "occupied_M": M,
             "errors_vs_converged": errs, "points": points}
@@ -308,6 +322,49 @@ def configs_leg(pw, steps, warmup):
         log(f"[bench] {w.name}: " + ", ".join(f"{k} {v['integrals_per_s']:.3g}/s"
                                                for k, v in legs.items()))
     return res, outs
+
+
+def gauss_leg(pw, steps, warmup):
+    """The separable Gaussian basis (Sec. II): 24 one-dimensional s-type
+    Gaussians per direction (12 centers 1.5 bohr apart, exponents 0.8 and
+    3.0; 13,824 basis functions), reference length 20 bohr, Mesh 3 with 46
+    nodes, pairs screened at 1e-15; 1e7 local quadruples (the four
+    functions within three one-dimensional indices of each other, so most
+    integrals are kept).  One step = table build + reconstruction."""
+    import torch
+    gs = workloads.GAUSS_BENCH
+    a, A = workloads.gaussian_set(gs)
+    n1 = len(a)
+    g = workloads.rng(2718)
+    n = 10_000_000
+    base = g.integers(0, n1, (n, 1, 3))
+    l = np.clip(base + g.integers(-3, 4, (n, 4, 3)), 0, n1 - 1)
+    qh = ((l[..., 0] * n1 + l[..., 1]) * n1 + l[..., 2]).astype(np.int32)
+    q = torch.from_numpy(qh).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    mesh = pw.Mesh.geometric_root(10, 6)
+    res = {"set": gs.name, "n1": n1, "basis_N": n1 ** 3, "L": 20.0, "mesh": "root 4x10+6 ratio 7",
+           "eps": 1e-15, "n_quads": n}
+    for name, prec in (("fp64", pw.FP64), ("mixed", pw.MIXED)):
+        def step():
+            t = pw.GaussTable(a, A, 20.0, eps=1e-15, mesh=mesh)
+            t.reconstruct(q, out, precision=prec)
+            t.sync()
+            res["n_pairs"], res["Q"], res["table_device_bytes"] = t.n_pairs, t.Q, t.device_bytes
+            t.close()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms_per_step": dt * 1e3, "integrals_per_s": n / dt}
+    res["nonzero_fraction"] = float((out != 0).double().mean().item())
+    log(f"[bench] gauss: {res['n_pairs']} pairs, fp64 {res['fp64']['integrals_per_s']:.3g}/s, "
+        f"mixed {res['mixed']['integrals_per_s']:.3g}/s")
+    return res, qh, out
 
 
 def serving_leg(pw, n_requests, warmup_requests=100):
@@ -408,6 +465,26 @@ def serving_leg(pw, n_requests, warmup_requests=100):
         f"p99 {out['budget_64MiB_fp64_load_80']['p99_ms']:.3f} ms, "
         f"evictions {out['budget_64MiB_fp64_load_80']['evictions']}")
     return out
+
+
+def gauss_oracle_errors(qh, out):
+    """Part of the CPU-baseline leg: the oracle on 20,000 sampled quadruples
+    of the Gaussian leg's stream (the last step's FP64 outputs)."""
+    import oracle
+    a, A = workloads.gaussian_set(workloads.GAUSS_BENCH)
+    pairs, pmap = oracle.gauss_pairs(a, A, 1e-15)
+    beta, W, _ = oracle.mesh3(10, 6)
+    tau = oracle.gauss_tau(beta, a, A, pairs, L=20.0)
+    rows = workloads.sample_rows(len(qh), 20_000, seed=9)
+    ref = oracle.gauss_reconstruct(tau, W, pmap, len(a), qh[rows], L=20.0)
+    got = out.cpu().numpy()[rows]
+    nz = ref != 0
+    big = np.abs(ref) >= 1e-22          # split FP32 keeps FP32's exponent range
+    small = nz & ~big
+    return {"sample": len(rows), "zeros_match": bool(np.array_equal(got[~nz], ref[~nz])),
+            "max_rel_above_1e-22": float(np.max(np.abs(got[big] - ref[big]) / np.abs(ref[big]))),
+            "max_abs_below_1e-22": float(np.max(np.abs(got[small] - ref[small]))) if small.any() else 0.0,
+            "path": "mixed (the leg's last step)"}
 
 
 def cpu_baseline_leg(w, quads_h, N, M, n, gpu_out, cfg_outs):
@@ -548,7 +625,8 @@ def main():
     quads = torch.from_numpy(quads_h).cuda()
     occ = torch.arange(M, dtype=torch.int32, device="cuda")
     occ_all = torch.arange(N, dtype=torch.int32, device="cuda")
-    LEGS = (("fp64", pw.FP64, True), ("fp64_node_sums", pw.FP64, False), ("mixed", pw.MIXED, False))
+    LEGS = (("fp64", pw.FP64, True), ("fp64_node_sums", pw.FP64, False), ("mixed", pw.MIXED, False),
+            ("fp32", pw.FP32, False))
     out = {name: torch.empty(n, dtype=torch.float64, device="cuda") for name, _, _ in LEGS}
     eout = torch.empty(2, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -558,7 +636,7 @@ def main():
         if values:
             t.build_values()                             # every distinct integral, Eq. 14
         t.reconstruct(quads, o, precision=prec)          # value reads, or decode + node passes
-        t.energies_async(occ, None, prec, eout)          # pair sums + reductions
+        t.energies_async(occ, None, pw.FP64 if prec == pw.FP32 else prec, eout)   # pair sums
         t.sync()                                         # surfaces kernel errors
         t.close()
 
@@ -608,6 +686,10 @@ def main():
         legs[name]["decode_ms"] = float(stages[0])
         legs[name]["pass_ms"] = [float(v) for v in stages[1:]]
         legs[name]["layout"] = t.layout(prec)
+        if prec == pw.FP32:      # the FP32 table serves reconstruction only
+            log(f"[bench] {name}: reconstruct {legs[name]['reconstruct_ms']:.3f} ms "
+                f"(decode {stages[0]:.3f} + passes {', '.join(f'{v:.3f}' for v in stages[1:])})")
+            continue
         for MM, o, key in ((M, occ, "exchange_M925"), (N, occ_all, "exchange_M9171")):
             for algo, an in ((pw.PAIR_KTABLE, "ktable"), (pw.PAIR_NODESUM, "nodesum")):
                 t.energies_async(o, None, prec, eout, algo=algo)
@@ -688,8 +770,20 @@ def main():
                   "achieved": m_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                   "frac": m_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": mpass_ms,
                   "lds_read_TBps": 3 * 8 * mlay["nodes_per_pass"] * n / (mpass_ms * 1e-3) / 1e12}
+    # The single-FP32 pass: 4-byte entries, so 12 bytes of LDS per node term.
+    slay = legs["fp32"]["layout"]
+    ssteady = legs["fp32"]["pass_ms"][1:] or legs["fp32"]["pass_ms"]
+    spass_ms = float(np.mean(ssteady))
+    s_tf = 4.0 * slay["nodes_per_pass"] * n / (spass_ms * 1e-3) / 1e12
+    fp32_pass = {"kernel": f"k_rec_pass<F32, G={slay['lanes']}, W={slay['words']}> "
+                           f"{'steady' if len(legs['fp32']['pass_ms']) > 1 else 'decoding'} node pass",
+                 "achieved": s_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": s_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": spass_ms,
+                 "nodes_per_pass": slay["nodes_per_pass"], "passes": len(legs["fp32"]["pass_ms"]),
+                 "lds_read_TBps": 3 * 4 * slay["nodes_per_pass"] * n / (spass_ms * 1e-3) / 1e12}
 
     cfg, cfg_outs = (None, {}) if args.no_configs else configs_leg(pw, args.steps, args.warmup)
+    gauss, gauss_q, gauss_out = (None, None, None) if args.no_configs else gauss_leg(pw, args.steps, args.warmup)
 
     cpu, converged, cfg_errs = None, None, None
     if not args.no_cpu_baseline:
@@ -699,14 +793,17 @@ def main():
         for name, e in cfg_errs.items():
             cfg[name]["error_vs_oracle"] = e
     del cfg_outs
+    if gauss is not None and not args.no_cpu_baseline:
+        gauss["error_vs_oracle"] = gauss_oracle_errors(gauss_q, gauss_out)
+    gauss_q = gauss_out = None
 
     fixed_error = None
     if not args.no_fixed_error:
         fixed_error = fixed_error_leg(pw, w, quads, n, args.steps, args.warmup, converged)
         for label, pt in fixed_error["points"].items():
             for fam in ("mesh2", "mesh3"):
-                log(f"[bench] fixed error {label} {fam}: {pt[fam].get('mesh')} (Q = {pt[fam].get('Q')}), "
-                    f"rates {pt[fam].get('integrals_per_s')}")
+                log(f"[bench] fixed error {label} {fam}: Q {pt[fam]['Q']}, "
+                    f"rates {pt[fam]['integrals_per_s']}")
 
     serving = None
     if not args.no_serve:
@@ -745,17 +842,21 @@ def main():
         "mixed_vs_fp64": {"integrals_per_s_ratio_node_sums": legs["mixed"]["integrals_per_s"] /
                           legs["fp64_node_sums"]["integrals_per_s"],
                           "integrals_per_s_ratio_vs_value_table": legs["mixed"]["integrals_per_s"] /
-                          legs["fp64"]["integrals_per_s"]},
+                          legs["fp64"]["integrals_per_s"],
+                          "fp32_table_vs_fp64_node_sums": legs["fp32"]["integrals_per_s"] /
+                          legs["fp64_node_sums"]["integrals_per_s"]},
         "p99_ms": serving["fp64_load_80"]["p99_ms"] if serving else None,
         "legs": legs,
         "table_build_ms": table_ms,
         "energies_fp64_M925": {"E_H": e_fp64[0], "E_x": e_fp64[1]},
         "configs": cfg,
+        "gauss": gauss,
         "serving": serving,
         "roofline": roofline,
         "value_build": value_build,
         "node_pass_roofline": node_pass_roofline,
         "mixed_pass": mixed_pass,
+        "fp32_pass": fp32_pass,
         "fixed_error": fixed_error,
         "cpu_baseline": cpu,
     }

@@ -73,9 +73,16 @@ typedef enum {
 
 typedef enum {
     PWC_FP64 = 0,   /* FP64 tables, FP64 node products and accumulation */
-    PWC_MIXED = 1   /* FP32 hi/lo split tables; node products and sums in
+    PWC_MIXED = 1,  /* FP32 hi/lo split tables; node products and sums in
                        float-float (error-free FP32 transformations), final
                        scaling and energy reductions in FP64 */
+    PWC_FP32 = 2    /* one FP32 table (W^(1/3) tau rounded once: 4 bytes an
+                       entry, half the bytes the node passes read); node
+                       products and sums of four nodes in FP32, accumulated in
+                       FP64.  Error at most about 4.2e-7 of the sum of the
+                       node terms' magnitudes (seven FP32 roundings per term):
+                       for work at six places.  Reconstruction of planewave
+                       tables only (PWC_ERR_ARG elsewhere). */
 } pwc_precision;
 
 /*
@@ -289,8 +296,8 @@ PWC_API pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n);
 /*
  * Reconstruction layout of a table for precision p (Eq. 14 evaluated in node
  * passes; each precision has its own default): lanes = G lanes of a
- * wavefront share one quadruple; words = W two-node
- * words per lane; nodes_per_pass = 2 G W nodes of every folded table entry
+ * wavefront share one quadruple; words = W 16-byte words (two nodes, four
+ * for PWC_FP32) per lane; nodes_per_pass = 2 G W (4 G W) nodes of every folded table entry
  * are held on chip per pass; passes = ceil(Q / (2 G W)); entry_bytes = size
  * of one decoded quadruple in the reconstruction's scratch stream (4 when the
  * table has at most 1024 folded entries per node, else 8).  Any output
@@ -300,8 +307,11 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
                                     int *nodes_per_pass, int *passes, int *entry_bytes);
 
 /*
- * Force the reconstruction layout of both precisions: (lanes, words) = (16, 1), (8, 2), (8, 1),
- * (4, 2), (2, 4), (1, 8) or (4, 1); (0, 0) restores the default choice.  Results agree
+ * Force the reconstruction layout of every precision: (lanes, words) = (16, 1), (8, 2), (8, 1),
+ * (4, 2), (2, 4), (1, 8) or (4, 1); (0, 0) restores the default choice.  A
+ * PWC_FP32 pass covers 4 lanes x words nodes (four per 16-byte word), twice the
+ * others; where that would run past the table's node padding (Q rounded up
+ * to 32) PWC_FP32 keeps its default layout.  Results agree
  * between layouts to rounding; only speed differs.  PWC_ERR_ARG for other
  * pairs, PWC_ERR_RANGE if the per-pass slab of that layout does not fit on
  * chip (the layout is then unchanged).  Must not overlap a reconstruction

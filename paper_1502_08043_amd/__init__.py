@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpwcoul.so")
 
 FP64 = 0
 MIXED = 1
+FP32 = 2
 MESH_GEOMETRIC = 0
 MESH_TWO_INTERVAL = 1
 MESH_GEOMETRIC_ROOT = 2

@@ -58,17 +58,23 @@ namespace pwc {
 // lanes = words = 0 takes the cheapest layout whose slab fits; otherwise
 // the given one.
 bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl) {
-    static const struct { int G, W; double fp64, mixed; } kLayouts[] = {
-        {8, 2, 0.49, 0.83}, {16, 1, 0.61, 0.97}, {1, 8, 0.575, 0.835}, {4, 2, 0.58, 0.86},
-        {2, 4, 0.58, 0.79}, {8, 1, 0.66, 1.02}, {4, 1, 0.80, 1.10}};
+    // fp32: ms per 16 nodes of 1e8 quadruples with four nodes per word.
+    static const struct { int G, W; double fp64, mixed, fp32; } kLayouts[] = {
+        {8, 2, 0.49, 0.83, 0.32}, {16, 1, 0.61, 0.97, 0.40}, {1, 8, 0.575, 0.835, 0.33},
+        {4, 2, 0.58, 0.86, 0.34}, {2, 4, 0.58, 0.79, 0.33}, {8, 1, 0.66, 1.02, 0.42},
+        {4, 1, 0.80, 1.10, 0.50}};
     constexpr double kPassStream = 0.30;   // ms per pass of 1e8 quadruples
+    const int npw = nodes_per_word(p);
+    const int Qp = (Q + 31) / 32 * 32;
     double best = -1.0;
     for (const auto &l : kLayouts) {
         if (lanes && (l.G != lanes || l.W != words)) continue;
-        const int c = 2 * l.G * l.W;
-        if (static_cast<size_t>(E) * c * 8 > static_cast<size_t>(kLdsMax)) continue;
+        const int c = npw * l.G * l.W;
+        // the slab row is G W 16-byte words whatever the precision
+        if (static_cast<size_t>(E) * l.G * l.W * 16 > static_cast<size_t>(kLdsMax)) continue;
         const int P = (Q + c - 1) / c;
-        const double per16 = p == PWC_MIXED ? l.mixed : l.fp64;
+        if (P * c > Qp) continue;   // the passes read nodes up to P c of each padded row
+        const double per16 = p == PWC_MIXED ? l.mixed : p == PWC_FP32 ? l.fp32 : l.fp64;
         const double cost = P * std::max(per16 * c / 16.0, kPassStream);
         if (best < 0.0 || cost < best) {
             best = cost;
@@ -79,7 +85,7 @@ bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &
         }
     }
     fl.E = E;
-    fl.Qp = (Q + 31) / 32 * 32;
+    fl.Qp = Qp;
     return best >= 0.0;
 }
 
@@ -389,6 +395,7 @@ size_t carve(Table &t, size_t n_reps, char *base) {
     const size_t o_tau = take(sizeof(double) * D * Q * nd * nd);
     const size_t o_tauF = take(sizeof(double) * Qp * E);
     const size_t o_tauHL = take(sizeof(float2) * Qp * E);
+    const size_t o_tau32 = take(sizeof(float) * Qp * E);
     const size_t o_diag = take(sizeof(double) * Qd * D * (K + 1));
     const size_t o_diagHL = take(sizeof(float2) * Qd * D * (K + 1));
     const size_t o_kt64 = take(sizeof(double) * static_cast<size_t>(t.kt_n));
@@ -404,6 +411,7 @@ size_t carve(Table &t, size_t n_reps, char *base) {
         t.d_tau = reinterpret_cast<double *>(base + o_tau);
         t.d_tauF = reinterpret_cast<double *>(base + o_tauF);
         t.d_tauHL = reinterpret_cast<float2 *>(base + o_tauHL);
+        t.d_tau32 = reinterpret_cast<float *>(base + o_tau32);
         t.d_Wcbrt = reinterpret_cast<double *>(base + o_Wcbrt);
         t.d_diag = reinterpret_cast<double *>(base + o_diag);
         t.d_diagHL = reinterpret_cast<float2 *>(base + o_diagHL);
@@ -447,9 +455,10 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
     if (hipDeviceGetAttribute(&t.n_cu, hipDeviceAttributeMultiprocessorCount, t.device) != hipSuccess ||
         t.n_cu <= 0)
         t.n_cu = 256;
-    t.flm.E = t.fl.E;
+    t.flm.E = t.fls.E = t.fl.E;
     t.direct_max = kDirectDefault;
     if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, t.flm) ||
+        !plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP32, t.fls) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.ndir) * (t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
     // Exchange kernel table when it fits in one workgroup's LDS: K(a <= b <= c)
@@ -1020,8 +1029,8 @@ pwc_status pwc_release_cached_memory(void) {
 
 pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int *words,
                             int *nodes_per_pass, int *passes, int *entry_bytes) {
-    if (!t || t->t.gauss || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
-    const pwc::FoldLayout &fl = p == PWC_MIXED ? t->t.flm : t->t.fl;
+    if (!t || t->t.gauss || !pwc::valid_precision(p)) return PWC_ERR_ARG;
+    const pwc::FoldLayout &fl = p == PWC_MIXED ? t->t.flm : p == PWC_FP32 ? t->t.fls : t->t.fl;
     if (lanes) *lanes = fl.G;
     if (words) *words = fl.W;
     if (nodes_per_pass) *nodes_per_pass = fl.c;
@@ -1038,12 +1047,18 @@ pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
                         (lanes == 2 && words == 4) || (lanes == 1 && words == 8);
         if (!ok) return PWC_ERR_ARG;
     }
-    pwc::FoldLayout fl = t->t.fl, flm = t->t.flm;
+    pwc::FoldLayout fl = t->t.fl, flm = t->t.flm, fls = t->t.fls;
     if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP64, fl) ||
         !pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_MIXED, flm))
         return PWC_ERR_RANGE;
+    // FP32 passes cover twice the nodes; a layout whose passes would run past
+    // the padded rows leaves FP32 on its default choice.
+    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP32, fls) &&
+        !pwc::plan_fold(t->t.Q, t->t.fl.E, 0, 0, PWC_FP32, fls))
+        return PWC_ERR_RANGE;
     t->t.fl = fl;
     t->t.flm = flm;
+    t->t.fls = fls;
     return PWC_OK;
 }
 
@@ -1088,7 +1103,7 @@ pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *stream) {
 
 pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n, double *d_out,
                            pwc_precision p, void *stream) {
-    if (!t || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || n < 0 || !pwc::valid_precision(p) || (p == PWC_FP32 && t->t.gauss)) return PWC_ERR_ARG;
     if (n == 0) return PWC_OK;
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
@@ -1114,7 +1129,7 @@ pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n
 
 pwc_status pwc_reconstruct_noalloc(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                    double *d_out, pwc_precision p, void *stream) {
-    if (!t || t->t.gauss || n < 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || n < 0 || !pwc::valid_precision(p)) return PWC_ERR_ARG;
     if (n > PWC_NOALLOC_MAX_QUADS) return PWC_ERR_LIMIT;
     if (n == 0) return PWC_OK;
     if (!d_quads || !d_out) return PWC_ERR_ARG;
@@ -1139,11 +1154,11 @@ pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n) {
 pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_quads, int64_t n,
                                    double *d_out, pwc_precision p, void *stream, double *h_ms,
                                    int max_stages, int *n_stages) {
-    if (!t || t->t.gauss || !h_ms || !n_stages || n <= 0 || (p != PWC_FP64 && p != PWC_MIXED)) return PWC_ERR_ARG;
+    if (!t || t->t.gauss || !h_ms || !n_stages || n <= 0 || !pwc::valid_precision(p)) return PWC_ERR_ARG;
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
-    const int stages = 1 + (p == PWC_MIXED ? t->t.flm : t->t.fl).nchunk;
+    const int stages = 1 + (p == PWC_MIXED ? t->t.flm : p == PWC_FP32 ? t->t.fls : t->t.fl).nchunk;
     *n_stages = stages;
     if (max_stages < stages) return PWC_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -61,10 +61,25 @@ __global__ __launch_bounds__(kDirectThreads) void k_rec_direct(DirectBatch b) {
     const int f0 = J.fold[(sx(nk) - sx(ni) + K) * nd + (sx(nl) - sx(nj) + K)];
     const int f1 = J.fold[(sy(nk) - sy(ni) + K) * nd + (sy(nl) - sy(nj) + K)] + J.ystride;
     const int f2 = J.fold[(sz(nk) - sz(ni) + K) * nd + (sz(nl) - sz(nj) + K)] + 2 * J.ystride;
-    const int words = (J.Q + 1) / 2;            // node pairs; entries past Q are zero
-    const size_t row = static_cast<size_t>(J.Qp / 2);
     double r;
-    if (!J.mixed) {
+    if (J.mixed == 2) {   // single FP32 table: four nodes per word, word sums in FP32
+        const int words = (J.Q + 3) / 4;
+        const size_t row = static_cast<size_t>(J.Qp / 4);
+        const float4 *x = static_cast<const float4 *>(J.tab) + f0 * row;
+        const float4 *y = static_cast<const float4 *>(J.tab) + f1 * row;
+        const float4 *z = static_cast<const float4 *>(J.tab) + f2 * row;
+        double acc = 0.0;
+#pragma unroll 2
+        for (int w = s; w < words; w += kDirectLanes) {
+            const float4 a = x[w], c = y[w], d = z[w];
+            const float p0 = (a.x * c.x) * d.x, p1 = (a.y * c.y) * d.y;
+            const float p2 = (a.z * c.z) * d.z, p3 = (a.w * c.w) * d.w;
+            acc += static_cast<double>((p0 + p1) + (p2 + p3));
+        }
+        r = acc;
+    } else if (!J.mixed) {
+        const int words = (J.Q + 1) / 2;            // node pairs; entries past Q are zero
+        const size_t row = static_cast<size_t>(J.Qp / 2);
         const double2 *x = static_cast<const double2 *>(J.tab) + f0 * row;
         const double2 *y = static_cast<const double2 *>(J.tab) + f1 * row;
         const double2 *z = static_cast<const double2 *>(J.tab) + f2 * row;
@@ -77,6 +92,8 @@ __global__ __launch_bounds__(kDirectThreads) void k_rec_direct(DirectBatch b) {
         }
         r = acc;
     } else {
+        const int words = (J.Q + 1) / 2;
+        const size_t row = static_cast<size_t>(J.Qp / 2);
         const float4 *x = static_cast<const float4 *>(J.tab) + f0 * row;
         const float4 *y = static_cast<const float4 *>(J.tab) + f1 * row;
         const float4 *z = static_cast<const float4 *>(J.tab) + f2 * row;
@@ -102,8 +119,9 @@ DirectJob direct_job(const Table &t, const int32_t *d_quads, int64_t n, double *
     j.quads = d_quads;
     j.out = d_out;
     j.n = n;
-    j.mixed = p == PWC_MIXED;
-    j.tab = j.mixed ? static_cast<const void *>(t.d_tauHL) : static_cast<const void *>(t.d_tauF);
+    j.mixed = p == PWC_MIXED ? 1 : p == PWC_FP32 ? 2 : 0;
+    j.tab = p == PWC_MIXED ? static_cast<const void *>(t.d_tauHL)
+            : p == PWC_FP32 ? static_cast<const void *>(t.d_tau32) : static_cast<const void *>(t.d_tauF);
     j.basis = t.d_basis;
     j.fold = t.d_fold;
     j.err = d_err ? d_err : t.d_err;

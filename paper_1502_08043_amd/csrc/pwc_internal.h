@@ -55,11 +55,14 @@ constexpr int kGlPanels = 128;        // panels over the Gaussian's support
 struct FoldLayout {
     int E = 0;          // folded entries per node
     int Qp = 0;         // nodes padded to a multiple of 32 (zero weight, zero tau)
-    int G = 0;          // lanes per quadruple: 4, 8 or 16
-    int W = 0;          // words (node pairs) per lane and row: 1 or 2
-    int c = 0;          // nodes per pass, 2 G W
+    int G = 0;          // lanes per quadruple: 1 .. 16
+    int W = 0;          // 16-byte words per lane and row: 1 .. 8
+    int c = 0;          // nodes per pass, npw G W (npw = 2 nodes per word, 4 for FP32)
     int nchunk = 0;     // passes P = ceil(Q / c)
 };
+// Nodes in one 16-byte word of the folded table of precision p.
+inline int nodes_per_word(pwc_precision p) { return p == PWC_FP32 ? 4 : 2; }
+inline bool valid_precision(int p) { return p == PWC_FP64 || p == PWC_MIXED || p == PWC_FP32; }
 constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
 constexpr int kGaussMaxN1 = PWC_GAUSS_MAX_N1;
 constexpr int kGaussMaxPairs = PWC_GAUSS_MAX_PAIRS;
@@ -100,6 +103,7 @@ struct Table {
     std::vector<double> h_beta, h_W;
     FoldLayout fl;       // reconstruction layout of the FP64 path
     FoldLayout flm;      // and of the split-FP32 path (same E, Qp)
+    FoldLayout fls;      // and of the single-FP32 path (4 nodes per 16-byte word)
     DiagLayout dl;
     int device = 0;
     int n_cu = 0;
@@ -117,6 +121,7 @@ struct Table {
     double *d_tau = nullptr;        // [ndir][Q][nd][nd]
     double *d_tauF = nullptr;       // [ndir * E1][Qp]  folded W_q^(1/3) tau_q, FP64
     float2 *d_tauHL = nullptr;      // [ndir * E1][Qp]  same, (hi, lo)
+    float *d_tau32 = nullptr;       // [ndir * E1][Qp]  same, rounded to FP32
     double *d_Wcbrt = nullptr;      // [Q]      W_q^(1/3)
     double *d_diag = nullptr;       // [dl.nchunk][ndir][K + 1][dl.c]  tau_q(m, -m), m >= 0
     float2 *d_diagHL = nullptr;     // same, (hi, lo)
@@ -225,7 +230,7 @@ struct DirectJob {
     const int32_t *fold;
     int *err;                 // error word of this job
     double pref;
-    int N, K, nd, Qp, Q, mixed;
+    int N, K, nd, Qp, Q, mixed;  // mixed: 0 FP64, 1 split FP32, 2 single FP32
     int ystride;              // rows between direction tables (E1 for a box, 0 for a cube)
     uint32_t block0;          // first block of the job (set by launch_direct)
 };

@@ -97,7 +97,7 @@ struct PassArgs {
     const int32_t *fold;
     int K, nd;
     const void *tab;   // [E][Qp] double or float2: W_q^(1/3) tau_q
-    int E, Qp, q0;     // this pass: nodes [q0, q0 + 2G)
+    int E, Qp, q0;     // this pass: nodes [q0, q0 + c) of every row
     void *scratch;     // [n] packed folded entries
     double pref;
     double *out;
@@ -135,6 +135,24 @@ struct FF {
     }
     __device__ static double value(const Acc &a) { return ff_to_double(a.h, a.l); }
 };
+
+// Single-FP32 arithmetic: table entries W_q^(1/3) tau_q rounded once to FP32,
+// four nodes per 16-byte word.  The four node products of a word are formed
+// and summed pairwise in FP32 and the word's sum is added in FP64: per term
+// 3 roundings of the entries, 2 of the product and 2 of the word sum.
+struct F32 {
+    using V = float4;    // four adjacent nodes
+    struct Acc { double v; };
+    __device__ static void zero(Acc &a) { a.v = 0.0; }
+    __device__ static void add2(Acc &a, V x, V y, V z) {
+        const float p0 = (x.x * y.x) * z.x, p1 = (x.y * y.y) * z.y;
+        const float p2 = (x.z * y.z) * z.z, p3 = (x.w * y.w) * z.w;
+        a.v += static_cast<double>((p0 + p1) + (p2 + p3));
+    }
+    __device__ static double value(const Acc &a) { return a.v; }
+};
+template <typename A> constexpr int npw() { return 2; }
+template <> constexpr int npw<F32>() { return 4; }
 
 // Packed folded entries of one quadruple.  Pk32: three 10-bit fields and
 // a flag in bit 30 (E <= 1024); Pk64: 16-bit fields, the flag in bit 31 of
@@ -462,8 +480,8 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
         if (base + i * stride < a.n) load(st[i], base + i * stride);
     {
         V *dst = reinterpret_cast<V *>(lds_raw);
-        const V *src = static_cast<const V *>(a.tab) + a.q0 / 2;
-        const int row = a.Qp / 2;
+        const V *src = static_cast<const V *>(a.tab) + a.q0 / npw<A>();
+        const int row = a.Qp / npw<A>();
         for (int i = threadIdx.x; i < words; i += kThreads) {
             const int e = i / (G * W), j = i % (G * W);
             dst[i] = src[static_cast<size_t>(e) * row + j];
@@ -625,7 +643,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, const FoldLayout &fl, 
         }
         if (ev && (err = hipEventRecord(ev[1], s)) != hipSuccess) return err;
         for (int p = 0; p < P; ++p) {
-            a.q0 = p * 2 * G * W;
+            a.q0 = p * npw<A>() * G * W;
             const bool dec = p == 0 && inline_decode;
             const int64_t tl = dec ? tile_d : tile, cover = dec ? a.n_pad : a.n;
             const unsigned grid = static_cast<unsigned>(std::min<int64_t>((cover + tl - 1) / tl, int64_t(t.n_cu) * per_cu));
@@ -712,7 +730,7 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.ndir = t.ndir;
     a.Qp = t.fl.Qp;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
-    a.ord_g = (p == PWC_MIXED ? t.flm : t.fl).G;
+    a.ord_g = (p == PWC_MIXED ? t.flm : p == PWC_FP32 ? t.fls : t.fl).G;
     a.out = d_out;
     a.err = d_err ? d_err : t.d_err;
     // The decoded stream: the caller's fixed scratch (it holds the whole
@@ -728,6 +746,9 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     if (p == PWC_MIXED) {
         a.tab = t.d_tauHL;
         err = run_layout<FF>(a, t, t.flm, s, stage_ev);
+    } else if (p == PWC_FP32) {
+        a.tab = t.d_tau32;
+        err = run_layout<F32>(a, t, t.fls, s, stage_ev);
     } else {
         a.tab = t.d_tauF;
         err = run_layout<F64>(a, t, t.fl, s, stage_ev);

@@ -483,7 +483,8 @@ pwc_status pwc_server_submit(pwc_server *s, const pwc_request *r, uint64_t *tick
     if (!(r->L > 0.0) || !std::isfinite(r->L) || r->n2max < 1 || r->n2max > PWC_MAX_N2MAX || r->n < 0) return PWC_ERR_ARG;
     if (!(r->Ly >= 0.0) || !(r->Lz >= 0.0) || !std::isfinite(r->Ly) || !std::isfinite(r->Lz))
         return PWC_ERR_ARG;
-    if (r->prec != PWC_FP64 && r->prec != PWC_MIXED) return PWC_ERR_ARG;
+    if (!pwc::valid_precision(r->prec)) return PWC_ERR_ARG;
+    if (r->kind == PWC_REQ_ENERGIES && r->prec == PWC_FP32) return PWC_ERR_ARG;   // reconstruction only
     if (!r->d_out || (r->n > 0 && !r->d_idx)) return PWC_ERR_ARG;
     if (r->kind == PWC_REQ_RECONSTRUCT && (reinterpret_cast<uintptr_t>(r->d_idx) & 15))
         return PWC_ERR_ARG;

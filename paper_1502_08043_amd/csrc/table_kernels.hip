@@ -110,6 +110,7 @@ struct AsmArgs {
     double *tau;
     double *tauF;
     float2 *tauHL;
+    float *tau32;
     double *diag;
     float2 *diagHL;
 };
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(AsmArgs a) {
         const double vw = v * a.wcbrt[q];
         a.tauF[idx] = vw;
         a.tauHL[idx] = split_hilo(vw);
+        a.tau32[idx] = static_cast<float>(vw);
     }
     // Diagonal tau(m, -m) for m >= 0 (the exchange entries; even in m).
     if (s == 0 && m >= 0) {
@@ -168,7 +170,7 @@ hipError_t launch_table_build(Table &t, hipStream_t s, bool from_tau) {
         if (err != hipSuccess) return err;
     }
     AsmArgs a{t.d_beta, t.d_Wcbrt, t.d_prim, t.d_fold, t.d_reps, t.K, t.nd, t.E1, t.fl.Qp, t.dl.c,
-              t.Q, t.ndir, from_tau ? 1 : 0, t.d_tau, t.d_tauF, t.d_tauHL, t.d_diag, t.d_diagHL};
+              t.Q, t.ndir, from_tau ? 1 : 0, t.d_tau, t.d_tauF, t.d_tauHL, t.d_tau32, t.d_diag, t.d_diagHL};
     dim3 ga((t.nd * t.nd + kThreads - 1) / kThreads, t.Q, t.ndir);
     hipLaunchKernelGGL(k_assemble, ga, dim3(kThreads), 0, s, a);
     return hipGetLastError();

@@ -151,14 +151,14 @@ def _check_reconstruct(pw, t, o, quads, L=1.0, label=""):
     ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], quads, L=L)
     scale = P.cond_scale(o["tau"], o["W"], o["basis"], quads, L=L)
     errs = {}
-    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED)):
+    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED), (pw.FP32, P.TOL_FP32)):
         out = t.reconstruct(dq, precision=prec)
         t.sync()
         got = out.cpu().numpy()
         errs[prec] = P.worst_cond_err(got, ref, scale)
         assert errs[prec] < tol, (label, prec, errs[prec])
     say(f"[parity] reconstruct {label}: n={len(quads)} fp64 {errs[pw.FP64]:.2e} "
-        f"mixed {errs[pw.MIXED]:.2e} (condition-aware)")
+        f"mixed {errs[pw.MIXED]:.2e} fp32 {errs[pw.FP32]:.2e} (condition-aware)")
     return errs
 
 
@@ -208,10 +208,10 @@ def test_direct_and_node_passes_agree(pw, n2max, Q):
         for path, m in (("direct", DIRECT_DEFAULT), ("passes", 0)):
             t.set_direct_max(m)
             _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} {path}")
-            for prec in (pw.FP64, pw.MIXED):
+            for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 out[path, prec] = t.reconstruct(dq, precision=prec)
         t.sync()
-        for prec, tol in ((pw.FP64, 1e-13), (pw.MIXED, 1e-12)):
+        for prec, tol in ((pw.FP64, 1e-13), (pw.MIXED, 1e-12), (pw.FP32, 1e-6)):
             a, b = out["direct", prec], out["passes", prec]
             assert (a - b).abs().max().item() <= tol * b.abs().max().item()
         with pytest.raises(pw.PwcError):
@@ -265,17 +265,19 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
         base = {}
         for G, W in fits:
             t.set_layout(G, W)
-            for prec in (pw.FP64, pw.MIXED):
+            for prec, npw in ((pw.FP64, 2), (pw.MIXED, 2), (pw.FP32, 4)):
                 lay = t.layout(prec)
+                if prec == pw.FP32 and -(-Q // (npw * G * W)) * npw * G * W > -(-Q // 32) * 32:
+                    continue   # its passes would run past the padded rows: FP32 keeps its default
                 assert (lay["lanes"], lay["words"]) == (G, W)
-                assert lay["nodes_per_pass"] == 2 * G * W
-                assert lay["passes"] == -(-Q // (2 * G * W))
+                assert lay["nodes_per_pass"] == npw * G * W
+                assert lay["passes"] == -(-Q // (npw * G * W))
             _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} layout={G}x{W}")
-            for prec in (pw.FP64, pw.MIXED):
+            for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 out = t.reconstruct(dq, precision=prec)
                 t.sync()
                 if prec in base:   # layouts differ only in rounding order
-                    tol = 1e-13 if prec == pw.FP64 else 1e-12
+                    tol = {pw.FP64: 1e-13, pw.MIXED: 1e-12, pw.FP32: 1e-6}[prec]
                     assert (out - base[prec]).abs().max().item() <= tol * base[prec].abs().max().item()
                 else:
                     base[prec] = out
@@ -306,7 +308,7 @@ def _sampled_stream_check(pw, t, o, quads_host, sample, label):
     ref = oracle.reconstruct(o["tau"], o["W"], o["basis"], q)
     scale = P.cond_scale(o["tau"], o["W"], o["basis"], q)
     outs = {}
-    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED)):
+    for prec, tol in ((pw.FP64, P.TOL_FP64), (pw.MIXED, P.TOL_MIXED), (pw.FP32, P.TOL_FP32)):
         out = t.reconstruct(dq, precision=prec)
         t.sync()
         got = out[torch.from_numpy(rows).cuda()].cpu().numpy()

@@ -57,7 +57,7 @@ def test_noalloc_matches_the_allocating_call(pw, sides, n2max, Q):
         for n, seed in ((pw.NOALLOC_MAX_QUADS - 1000, 1), (300_001, 2)):
             qh = workloads.lookup_stream(N, min(N, 925), n, seed=seed)
             q = torch.from_numpy(qh).cuda()
-            for prec in (pw.FP64, pw.MIXED):
+            for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 out = torch.full((n,), -7.0, dtype=torch.float64, device="cuda")
                 say(f"[noalloc] sides={sides} n2max={n2max} Q={Q} n={n} prec={prec}")
                 assert _noalloc(pw, t, q, out, prec) == pw.OK
@@ -68,7 +68,7 @@ def test_noalloc_matches_the_allocating_call(pw, sides, n2max, Q):
                 oref = oracle.reconstruct(tau, o["W"], o["basis"], qh[rows], L=L0)
                 err = P.worst_cond_err(out.cpu().numpy()[rows], oref,
                                        P.cond_scale(tau, o["W"], o["basis"], qh[rows], L=L0))
-                assert err < (P.TOL_FP64 if prec == pw.FP64 else P.TOL_MIXED), err
+                assert err < {pw.FP64: P.TOL_FP64, pw.MIXED: P.TOL_MIXED, pw.FP32: P.TOL_FP32}[prec], err
 
 
 def test_noalloc_limits_and_errors(pw):
