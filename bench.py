@@ -138,7 +138,8 @@ def reachable_values(n2max):
 
 def pmc_workload():
     """A plain copy of known size, three FP64 node-sum reconstructions of the
-    stream, then the value table and three reconstructions that read it."""
+    stream, three single-FP32 ones, then the value table and three
+    reconstructions that read it."""
     import torch
     import paper_1502_08043_amd as pw
     w = workloads.C4_STREAM
@@ -151,6 +152,8 @@ def pmc_workload():
     out = torch.empty(w.n_quads, dtype=torch.float64, device="cuda")
     for _ in range(3):
         t.reconstruct(q, out, pw.FP64)
+    for _ in range(3):
+        t.reconstruct(q, out, pw.FP32)
     t.build_values()
     for _ in range(3):
         t.reconstruct(q, out, pw.FP64)
