@@ -388,18 +388,21 @@ PWC_API pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *strea
  * holding (i, j, k, l) per row, 16-byte aligned; d_out is double [n], 8-byte
  * aligned.  Async on `stream`.  n = 0 is a no-op.  An index outside [0, N)
  * makes that output NaN and sets the table's error word (see pwc_sync).
- * p = PWC_FP64 or PWC_MIXED.  An FP64 call on a table with its value table
- * built reads one value per quadruple; otherwise lists of at most
- * direct_max quadruples run the direct kernel and longer ones the node
- * passes (pwc_table_set_direct_max).
+ * p = PWC_FP64, PWC_MIXED or PWC_FP32.  An FP64 call on a table with its
+ * value table built reads one value per quadruple; otherwise lists of at
+ * most direct_max quadruples run the direct kernel and longer ones the node
+ * passes (pwc_table_set_direct_max).  With the one-lane layout, when its
+ * slab and the decode's basis and fold map fit in one workgroup's LDS, the
+ * passes run fused in one launch that keeps no decoded stream; the results
+ * are those of the separate launches, bit for bit.
  */
 PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n,
                            double *d_out, pwc_precision p, void *stream);
 
 /*
  * The node-pass reconstruction (whatever the direct-kernel size, and with or
- * without a value table) that also
- * reports how long each of its launches took on `stream` (HIP events
+ * without a value table; always as separate launches, never fused) that
+ * also reports how long each of its launches took on `stream` (HIP events
  * between the launches), then waits for the stream.  h_ms[0] is the
  * standalone decode launch (near zero when the first pass decodes the
  * stream itself) and h_ms[1 .. P] are the P passes (first slab of at most
@@ -420,8 +423,9 @@ PWC_API pwc_status pwc_reconstruct_profile(const pwc_table *t, const int32_t *d_
  * without a value table: the same kernels and results as pwc_reconstruct
  * with direct_max = 0) whose decoded-quadruple stream lives in a fixed
  * device array of the library (64 MiB per device, held until the process
- * ends) instead of a per-call allocation; no call allocates or frees device
- * or host memory.  Arguments, layouts, errors and ownership as
+ * ends) instead of a per-call allocation (a table whose passes run fused
+ * keeps no such stream); no call allocates or frees device or host
+ * memory.  Arguments, layouts, errors and ownership as
  * pwc_reconstruct; async on `stream`.  n > PWC_NOALLOC_MAX_QUADS returns
  * PWC_ERR_LIMIT with nothing enqueued (split longer lists into calls of at
  * most that many).  Every call on one device shares that device's array:

@@ -55,15 +55,21 @@ namespace pwc {
 // 16 nodes of 1e8 quadruples, in ms, measured on MI355X for each arithmetic
 // (the 4x1 layout estimated); the 16-node layouts on the 9171-planewave
 // table and the 32-node ones on the 5575-planewave table, both Q = 96.
+// The first pass decodes the stream as well, about kDecodeExtra more.  The
+// one-lane layout runs fused (one launch, no stream between passes) when
+// its slab and the decode maps fit in LDS together: its cost is then P
+// times the fused figures, measured the same way for the whole call.
 // lanes = words = 0 takes the cheapest layout whose slab fits; otherwise
 // the given one.
-bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl) {
+bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, size_t maps_bytes, FoldLayout &fl) {
     // fp32: ms per 16 nodes of 1e8 quadruples with four nodes per word.
     static const struct { int G, W; double fp64, mixed, fp32; } kLayouts[] = {
         {8, 2, 0.49, 0.83, 0.32}, {16, 1, 0.61, 0.97, 0.40}, {1, 8, 0.575, 0.835, 0.33},
         {4, 2, 0.58, 0.86, 0.34}, {2, 4, 0.58, 0.79, 0.33}, {8, 1, 0.66, 1.02, 0.42},
         {4, 1, 0.80, 1.10, 0.50}};
+    static const struct { double fp64, mixed, fp32; } kFused = {0.58, 0.73, 0.33};
     constexpr double kPassStream = 0.30;   // ms per pass of 1e8 quadruples
+    constexpr double kDecodeExtra = 0.25;  // ms per call of 1e8 quadruples
     const int npw = nodes_per_word(p);
     const int Qp = (Q + 31) / 32 * 32;
     double best = -1.0;
@@ -74,8 +80,15 @@ bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &
         if (static_cast<size_t>(E) * l.G * l.W * 16 > static_cast<size_t>(kLdsMax)) continue;
         const int P = (Q + c - 1) / c;
         if (P * c > Qp) continue;   // the passes read nodes up to P c of each padded row
-        const double per16 = p == PWC_MIXED ? l.mixed : p == PWC_FP32 ? l.fp32 : l.fp64;
-        const double cost = P * std::max(per16 * c / 16.0, kPassStream);
+        FoldLayout cand;
+        cand.G = l.G;
+        cand.W = l.W;
+        cand.E = E;
+        const bool fused = fused_layout(cand, maps_bytes);
+        const double per16 = fused ? (p == PWC_MIXED ? kFused.mixed : p == PWC_FP32 ? kFused.fp32 : kFused.fp64)
+                                   : (p == PWC_MIXED ? l.mixed : p == PWC_FP32 ? l.fp32 : l.fp64);
+        const double cost = fused ? P * per16 * c / 16.0
+                                  : P * std::max(per16 * c / 16.0, kPassStream) + kDecodeExtra;
         if (best < 0.0 || cost < best) {
             best = cost;
             fl.G = l.G;
@@ -457,8 +470,9 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
         t.n_cu = 256;
     t.flm.E = t.fls.E = t.fl.E;
     t.direct_max = kDirectDefault;
-    if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, t.flm) ||
-        !plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP32, t.fls) ||
+    const size_t maps = fold_maps_bytes(t.N, t.nd);
+    if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, maps, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, maps, t.flm) ||
+        !plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP32, maps, t.fls) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.ndir) * (t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
     // Exchange kernel table when it fits in one workgroup's LDS: K(a <= b <= c)
@@ -1048,13 +1062,14 @@ pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
         if (!ok) return PWC_ERR_ARG;
     }
     pwc::FoldLayout fl = t->t.fl, flm = t->t.flm, fls = t->t.fls;
-    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP64, fl) ||
-        !pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_MIXED, flm))
+    const size_t maps = pwc::fold_maps_bytes(t->t.N, t->t.nd);
+    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP64, maps, fl) ||
+        !pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_MIXED, maps, flm))
         return PWC_ERR_RANGE;
     // FP32 passes cover twice the nodes; a layout whose passes would run past
     // the padded rows leaves FP32 on its default choice.
-    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP32, fls) &&
-        !pwc::plan_fold(t->t.Q, t->t.fl.E, 0, 0, PWC_FP32, fls))
+    if (!pwc::plan_fold(t->t.Q, t->t.fl.E, lanes, words, PWC_FP32, maps, fls) &&
+        !pwc::plan_fold(t->t.Q, t->t.fl.E, 0, 0, PWC_FP32, maps, fls))
         return PWC_ERR_RANGE;
     t->t.fl = fl;
     t->t.flm = flm;
@@ -1135,7 +1150,7 @@ pwc_status pwc_reconstruct_noalloc(const pwc_table *t, const int32_t *d_quads, i
     if (!d_quads || !d_out) return PWC_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(d_quads) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 7))
         return PWC_ERR_ARG;
-    if (pwc::reconstruct_scratch_bytes(t->t, n) > pwc::kNoAllocScratchBytes) return PWC_ERR_LIMIT;
+    if (pwc::reconstruct_scratch_bytes(t->t, n, p) > pwc::kNoAllocScratchBytes) return PWC_ERR_LIMIT;
     void *scratch = nullptr;
     hipError_t e = pwc::noalloc_scratch(&scratch);
     const hipStream_t s = static_cast<hipStream_t>(stream);

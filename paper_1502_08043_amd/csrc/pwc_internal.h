@@ -64,6 +64,19 @@ struct FoldLayout {
 inline int nodes_per_word(pwc_precision p) { return p == PWC_FP32 ? 4 : 2; }
 inline bool valid_precision(int p) { return p == PWC_FP64 || p == PWC_MIXED || p == PWC_FP32; }
 constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
+// LDS bytes of the decode's basis (int32 per planewave) and fold map (int16
+// per (m, m') pair).
+inline size_t fold_maps_bytes(int64_t N, int nd) {
+    return sizeof(int32_t) * static_cast<size_t>(N) + sizeof(int16_t) * static_cast<size_t>(nd) * nd;
+}
+// True when a reconstruction with layout fl runs as one fused launch: the
+// one-lane layout (1 lane, 8 words of 16 bytes per row), its slab and the
+// decode maps together in one workgroup's LDS, at most 8 slab words staged
+// per lane.  It keeps no decoded stream.
+inline bool fused_layout(const FoldLayout &fl, size_t maps_bytes) {
+    return fl.G == 1 && fl.W == 8 && fl.E <= 1024 &&
+           static_cast<size_t>(fl.E) * 128 + maps_bytes <= static_cast<size_t>(kLdsMax);
+}
 constexpr int kGaussMaxN1 = PWC_GAUSS_MAX_N1;
 constexpr int kGaussMaxPairs = PWC_GAUSS_MAX_PAIRS;
 constexpr int64_t kRecSlab = int64_t(1) << 27;   // quadruples per scratch slab
@@ -176,7 +189,9 @@ inline hipError_t wait_ready(const Table &t, hipStream_t s) {
 struct TableSetup {
     std::vector<int32_t> fold, reps;
 };
-bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, FoldLayout &fl);
+// maps_bytes: fold_maps_bytes of the table (the one-lane layout is priced
+// as the fused schedule when it qualifies).
+bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, size_t maps_bytes, FoldLayout &fl);
 pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table &t, TableSetup &su);
 // h_tau: the FP64 tables [Q][nd][nd] of a loaded table (the 1-D integrals are
 // then not recomputed), or nullptr.
@@ -205,14 +220,15 @@ int packed_entry_bytes(int E);
 // Every launch_* that checks indices raises d_err when given, else the
 // table's own error word.
 // d_scratch: a caller-owned buffer for the decoded stream of at least
-// reconstruct_scratch_bytes(t, n) bytes, or nullptr (a stream-ordered
-// allocation per call).
+// reconstruct_scratch_bytes(t, n, p) bytes, or nullptr (a stream-ordered
+// allocation per call, none for the fused schedule).
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
                               double *d_out, pwc_precision p, hipStream_t s,
                               hipEvent_t *stage_ev = nullptr, int *d_err = nullptr,
                               void *d_scratch = nullptr);
-// Device bytes of the decoded stream of one node-pass call of n quadruples.
-size_t reconstruct_scratch_bytes(const Table &t, int64_t n);
+// Device bytes of the decoded stream of one node-pass call of n quadruples
+// in precision p (0 when it runs fused).
+size_t reconstruct_scratch_bytes(const Table &t, int64_t n, pwc_precision p);
 // pwc_reconstruct_noalloc's fixed scratch: kNoAllocScratchBytes of static
 // device memory per device; *p is its address on the current device (looked
 // up once per device).  Holds the padded decoded stream of

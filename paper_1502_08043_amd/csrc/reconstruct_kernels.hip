@@ -57,9 +57,21 @@
 // quadruple's packed word depends on its stream position only, so the first
 // pass of such a table runs in the one-lane layout (G = 1, W = 8) and
 // decodes the stream itself, the basis and fold map sitting in LDS beside
-// the slab (without the lane pairing: that pass is bound by its instruction
-// count); the later passes use the table's layout, for whose lane groups
+// the slab; the later passes use the table's layout, for whose lane groups
 // the decode orders the entries.  Other tables decode in k_decode first.
+//
+// Fused schedule.  When the table's layout is the one-lane one and the
+// basis and fold map fit in LDS beside its slab, one launch does all the
+// passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
+// lane into registers, keeps their partial sums there, and for each node
+// range restages the slab from L2 (the whole folded table, 0.56 MB at 9171
+// planewaves and Q = 96, stays resident there) and adds its terms.  The
+// stream is then read once and the results written once (24 bytes per
+// quadruple instead of 28 + 20 per later pass), no decoded stream is
+// stored, and the next range's slab is loaded into registers while the
+// current one is read.  Larger chunks spill registers and run slower.  The
+// arithmetic and its order are those of the separate launches, so both
+// schedules give the same bits.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -510,9 +522,8 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
             for (int r = 0; r < R; ++r) pk[r] = st.pk[r];
         }
         // One lane per quadruple: evaluate the quadruple pair_lane deals
-        // this lane, the high lane of each pair in descending parity.  The
-        // decoding pass is bound by its instruction count and skips it.
-        constexpr bool PAIR = G == 1 && !DECODE;
+        // this lane, the high lane of each pair in descending parity.
+        constexpr bool PAIR = G == 1;
         int dest = 0;
         T ev[R];
 #pragma unroll
@@ -580,6 +591,143 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
     }
 }
 
+// Fused one-lane node sums (see the header): NT quadruples per lane and
+// chunk, SPT 16-byte slab words staged per lane.  Every node range of the
+// padded rows (P ranges of 8 words per row) is added to the chunk's partial
+// sums in range order, each range's terms in node order, exactly as the
+// one-lane passes do; the pairing of a chunk's quadruples is formed once.
+constexpr int kFusedChunk = 4;
+
+// Slab words of node range p: word j of row e is 16-byte word p W + j of
+// the padded row (row words); lane i stages words i + 1024 k.
+template <int SPT>
+__device__ __forceinline__ void fetch_slab(uint4 (&pre)[SPT], const uint4 *tab, int row, int p, int words) {
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        pre[k] = i < words ? tab[static_cast<size_t>(i >> 3) * row + p * 8 + (i & 7)] : make_uint4(0, 0, 0, 0);
+    }
+}
+
+// One quadruple's terms of the staged node range, words k0 .. k0 + 3 of its
+// three rows, added to s in word order.
+template <typename A>
+__device__ __forceinline__ void fused_half(typename A::Acc &s, const char *lb, uint32_t a0, uint32_t a1, uint32_t a2,
+                                           int k0) {
+    using V = typename A::V;
+    V x[4], y[4], z[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t o = (k0 + k) * 16;
+        x[k] = *reinterpret_cast<const V *>(lb + (a0 ^ o));
+        y[k] = *reinterpret_cast<const V *>(lb + (a1 ^ o));
+        z[k] = *reinterpret_cast<const V *>(lb + (a2 ^ o));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) A::add2(s, x[k], y[k], z[k]);
+}
+
+// An empty register constraint: the compiler must assume the value changed
+// here, so what it feeds is not hoisted out of the enclosing loop.
+__device__ __forceinline__ void opaque(uint32_t &v) { __asm__ volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(uint2 &v) {
+    __asm__ volatile("" : "+v"(v.x));
+    __asm__ volatile("" : "+v"(v.y));
+}
+
+template <typename A, typename PK, int SPT, int NT>
+__global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
+    using T = typename PK::T;
+    __shared__ uint4 lds_raw[kLdsMax / 16];
+    constexpr int ROWB = 8 * 16;
+    const int words = a.E * 8;
+    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw + words);
+    int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
+    for (int i = threadIdx.x; i < a.N; i += kThreads) lbasis[i] = a.basis[i];
+    for (int i = threadIdx.x; i < a.nd * a.nd; i += kThreads) lfold[i] = static_cast<int16_t>(a.fold[i]);
+    const uint4 *tab = static_cast<const uint4 *>(a.tab);
+    const int row = a.Qp / npw<A>();
+    uint4 pre[SPT];
+    fetch_slab<SPT>(pre, tab, row, 0, words);
+    __syncthreads();   // the maps, before the first decode
+
+    const char *lb = reinterpret_cast<const char *>(lds_raw);
+    const uint32_t lane_b = static_cast<uint32_t>((threadIdx.x & 7) * 16);   // word k ^ (lane mod 8) at step k
+    const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
+    bool staged = false;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n;
+         base += static_cast<int64_t>(gridDim.x) * chunk) {
+        // Decode and pair: lane dest[t] evaluates this lane's quadruple t.
+        T ev[NT];
+        int dest[NT];
+        double acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t e = base + t * kThreads + threadIdx.x;
+            int4 q = make_int4(0, 0, 0, 0);
+            if (e < a.n) {   // streamed once
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                const v4i u = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
+                q = make_int4(u.x, u.y, u.z, u.w);
+            }
+            const T pk = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
+            dest[t] = pair_lane(PK::odd(pk));
+            ev[t] = PK::send(pk, dest[t]);
+            if (threadIdx.x & 8) ev[t] = PK::flip(ev[t]);
+            acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
+        }
+        for (int p = 0; p < P; ++p) {
+            if (P > 1 || !staged) {
+                __syncthreads();   // every wave is done with the previous range
+#pragma unroll
+                for (int k = 0; k < SPT; ++k) {
+                    const int i = threadIdx.x + k * kThreads;
+                    if (i < words) lds_raw[i] = pre[k];
+                }
+                __syncthreads();
+                staged = true;
+                if (P > 1) fetch_slab<SPT>(pre, tab, row, p + 1 < P ? p + 1 : 0, words);   // next range, or the next chunk's first
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                int f0, f1, f2;
+                opaque(ev[t]);   // row addresses are formed per range, not kept for all eight
+                PK::unpack(ev[t], f0, f1, f2);
+                const uint32_t a0 = f0 * ROWB + lane_b, a1 = f1 * ROWB + lane_b, a2 = f2 * ROWB + lane_b;
+                typename A::Acc s;
+                A::zero(s);
+                fused_half<A>(s, lb, a0, a1, a2, 0);
+                // Each half's twelve reads in a block of their own: more in
+                // flight would spill.
+                __builtin_amdgcn_sched_barrier(0);
+                fused_half<A>(s, lb, a0, a1, a2, 4);
+                acc[t] = acc[t] + A::value(s);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double v = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2hiint(acc[t])),
+                                              __builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2loint(acc[t])));
+            const int64_t e = base + t * kThreads + threadIdx.x;
+            if (e < a.n) __builtin_nontemporal_store(v * a.pref, a.out + e);
+        }
+    }
+}
+
+template <typename A, typename PK, int NT = kFusedChunk>
+hipError_t launch_fused(const PassArgs &a, const Table &t, int P, hipStream_t s) {
+    const int words = a.E * 8;
+    const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.n + chunk - 1) / chunk, t.n_cu));
+    if (words <= 6 * kThreads)
+        hipLaunchKernelGGL((k_rec_fused<A, PK, 6, NT>), dim3(grid), dim3(kThreads), 0, s, a, P);
+    else if (words <= 8 * kThreads)
+        hipLaunchKernelGGL((k_rec_fused<A, PK, 8, NT>), dim3(grid), dim3(kThreads), 0, s, a, P);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 using PassKernel = void (*)(PassArgs);
 
 template <typename A, int G, int W, typename PK>
@@ -605,8 +753,7 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, const FoldLayout &fl, 
     constexpr int64_t tile = static_cast<int64_t>(kThreads / G) * rows_per_group<G>();
     // LDS copy of the basis (int32) and the fold map (int16) for the decode:
     // inside the first pass when they fit beside its slab, else in k_decode.
-    const size_t maps_bytes = sizeof(int32_t) * static_cast<size_t>(t.N) +
-                              sizeof(int16_t) * static_cast<size_t>(t.nd) * t.nd;
+    const size_t maps_bytes = fold_maps_bytes(t.N, t.nd);
     const bool inline_decode = G * W == 8 && lds + maps_bytes <= static_cast<size_t>(kLdsMax);
     const size_t dmaps = (maps_bytes + 15) / 16 * 16;
     const bool maps_fit = dmaps <= static_cast<size_t>(kLdsMax);
@@ -616,6 +763,9 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, const FoldLayout &fl, 
                                                    static_cast<int>(dmaps));
         if (err != hipSuccess) return err;
     }
+    // One launch for every pass, unless per-launch timing is asked for.
+    if (!stage_ev && fused_layout(fl, maps_bytes)) return launch_fused<A, PK>(a0, t, P, s);
+    if (!a0.scratch) return hipErrorInvalidValue;   // the separate launches need the decoded stream
     const int per_cu = 1;   // the static slab takes the CU's LDS
     // Slabs bound the scratch array: at most kRecSlab quadruples per slab.
     for (int64_t off = 0; off < a0.n; off += kRecSlab) {
@@ -707,10 +857,22 @@ hipError_t noalloc_scratch(void **p) {
     return hipSuccess;
 }
 
-size_t reconstruct_scratch_bytes(const Table &t, int64_t n) {
+namespace {
+const FoldLayout &layout_of(const Table &t, pwc_precision p) {
+    return p == PWC_MIXED ? t.flm : p == PWC_FP32 ? t.fls : t.fl;
+}
+
+// The decoded stream of the separate launches: one slab, padded.
+size_t passes_scratch_bytes(const Table &t, int64_t n) {
     const int64_t slab = std::min<int64_t>(n, kRecSlab);
     return static_cast<size_t>(packed_entry_bytes(t.fl.E)) *
            static_cast<size_t>((slab + kStreamPad - 1) / kStreamPad * kStreamPad);
+}
+}  // namespace
+
+size_t reconstruct_scratch_bytes(const Table &t, int64_t n, pwc_precision p) {
+    if (fused_layout(layout_of(t, p), fold_maps_bytes(t.N, t.nd))) return 0;
+    return passes_scratch_bytes(t, n);
 }
 
 hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n, double *d_out,
@@ -730,17 +892,20 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.ndir = t.ndir;
     a.Qp = t.fl.Qp;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
-    a.ord_g = (p == PWC_MIXED ? t.flm : p == PWC_FP32 ? t.fls : t.fl).G;
+    a.ord_g = layout_of(t, p).G;
     a.out = d_out;
     a.err = d_err ? d_err : t.d_err;
     // The decoded stream: the caller's fixed scratch (it holds the whole
     // padded stream, checked by the caller), else a stream-ordered
     // allocation of one slab, freed behind the passes.
     hipError_t err = hipSuccess;
-    if (d_scratch) {
-        a.scratch = d_scratch;
+    // Per-launch timing always takes the separate launches, which keep the
+    // decoded stream even where the fused schedule would not.
+    const bool fused = !stage_ev && fused_layout(layout_of(t, p), fold_maps_bytes(t.N, t.nd));
+    if (d_scratch || fused) {
+        a.scratch = d_scratch;   // the fused schedule keeps no decoded stream
     } else {
-        err = hipMallocAsync(&a.scratch, reconstruct_scratch_bytes(t, n), s);
+        err = hipMallocAsync(&a.scratch, passes_scratch_bytes(t, n), s);
         if (err != hipSuccess) return err;
     }
     if (p == PWC_MIXED) {
@@ -753,7 +918,7 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
         a.tab = t.d_tauF;
         err = run_layout<F64>(a, t, t.fl, s, stage_ev);
     }
-    if (!d_scratch) {
+    if (!d_scratch && !fused) {
         const hipError_t e2 = hipFreeAsync(a.scratch, s);
         if (err == hipSuccess) err = e2;
     }

@@ -141,12 +141,14 @@ struct pwc_server {
 };
 
 // Device scratch the request's kernels allocate on its table (stream-ordered
-// allocations, priced from the path they take): none for the direct kernel,
-// the decoded stream for the node passes, the pair-sum partials for energies
-// (kernel-table or node-sum grid).  Rounded up to 64 KiB.
+// allocations, priced from the path they take): none for the direct kernel
+// or the fused node sums, the decoded stream for the node passes, the
+// pair-sum partials for energies (kernel-table or node-sum grid).  Rounded
+// up to 64 KiB.
 size_t pwc_server::scratch_bytes(const pwc::Table &t, const pwc_request &r) const {
     size_t b = 0;
-    if (r.kind == PWC_REQ_RECONSTRUCT) b = r.n <= t.direct_max ? 0 : pwc::reconstruct_scratch_bytes(t, r.n);
+    if (r.kind == PWC_REQ_RECONSTRUCT)
+        b = r.n <= t.direct_max ? 0 : pwc::reconstruct_scratch_bytes(t, r.n, static_cast<pwc_precision>(r.prec));
     else b = pwc::energies_scratch_bytes(t, r.n, static_cast<pwc_pair_algo>(r.algo));
     return (b + 65535) / 65536 * 65536;
 }

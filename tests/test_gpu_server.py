@@ -354,10 +354,11 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     """Admission prices each request's device scratch from the kernels it
     will run on its table: the node-sum pair partials grow as (M/32)^2
     (1.3 MB at M = 9171), the kernel-table ones stay small, the direct
-    kernel needs none and the node passes need the decoded stream.  With a
-    budget of the table plus 0.6 MB, what cannot fit beside the table fails
-    with ERR_NOMEM at once and the rest runs; with 2 MB more it all runs,
-    and the results are the library's."""
+    kernel and the fused node sums of the cube need none, and the node
+    passes of a box (2187 folded rows: no fused schedule) need the decoded
+    stream, 8 bytes per quadruple.  With a budget of the table plus 0.6 MB,
+    what cannot fit beside the table fails with ERR_NOMEM at once and the
+    rest runs; with more it all runs, and the results are the library's."""
     import torch
     pw.release_cached_memory()                 # no recycled (larger) blocks
     key = (1.0, 169, 32)
@@ -388,14 +389,31 @@ def test_scratch_is_priced_by_the_path_taken(pw):
 
     st, outs, o_small, o_big = run(tb + 600_000)
     say(f"[server] table {tb} B + 0.6 MB: {st}")
-    assert st == {"kt": pw.OK, "node": pw.ERR_NOMEM, "small": pw.OK, "big": pw.ERR_NOMEM}
+    assert st == {"kt": pw.OK, "node": pw.ERR_NOMEM, "small": pw.OK, "big": pw.OK}
     assert np.array_equal(outs["kt"].cpu().numpy(), e_kt)
-    assert torch.equal(o_small, r_small)
+    assert torch.equal(o_small, r_small) and torch.equal(o_big, r_big)
     st, outs, o_small, o_big = run(tb + 6_000_000)
     assert all(v == pw.OK for v in st.values()), st
     assert np.array_equal(outs["node"].cpu().numpy(), e_node)
     assert np.array_equal(outs["kt"].cpu().numpy(), e_kt)
     assert torch.equal(o_big, r_big) and torch.equal(o_small, r_small)
+
+    # The box's node passes keep the decoded stream: 8 MB for 1e6 quadruples.
+    sides = (1.0, 1.3, 0.8)
+    pw.release_cached_memory()
+    with pw.Table.box(*sides, 169, 32) as t:
+        tbb = t.device_bytes
+        t.set_direct_max(0)
+        r_box = t.reconstruct(big)
+        t.sync()
+    for budget, status in ((tbb + 600_000, pw.ERR_NOMEM), (tbb + 12_000_000, pw.OK)):
+        o_box = torch.full((1_000_000,), -1.0, dtype=torch.float64, device="cuda")
+        with pw.Server(budget, max_inflight=2) as srv:
+            got = srv.wait(srv.submit_reconstruct(sides, 169, big, o_box, n_nodes=32)).status
+        say(f"[server] box table {tbb} B + {budget - tbb} B: {got}")
+        assert got == status
+        if status == pw.OK:
+            assert torch.equal(o_box, r_box)
 
 
 def test_eviction_does_not_wait_for_other_tables(pw):

@@ -1,6 +1,7 @@
 """pwc_reconstruct_noalloc: the node passes with the library's fixed device
-scratch, against pwc_reconstruct (the same node passes with a per-call
-allocation) and the FP64 oracle, on two calls in a row, the second smaller."""
+scratch (tables whose passes run fused need none), against pwc_reconstruct
+(the same kernels, with a per-call allocation where they keep a decoded
+stream) and the FP64 oracle, on two calls in a row, the second smaller."""
 import ctypes
 import sys
 
@@ -41,8 +42,10 @@ def test_noalloc_matches_the_allocating_call(pw, sides, n2max, Q):
     """Two calls in a row (the second with a smaller input, so stale scratch
     from the first would show), both precisions: bitwise equal to
     pwc_reconstruct on the node passes, and within the parity bar of the
-    oracle on a sample.  The 9171-planewave box has 2187 folded rows, so its
-    decoded stream takes 8 bytes per quadruple; the cubes take 4."""
+    oracle on a sample.  The 9171-planewave box has 2187 folded rows: its
+    passes keep a decoded stream of 8 bytes per quadruple in the fixed
+    scratch.  The cubes' one-lane layout runs fused and keeps none (their
+    other layouts keep 4 bytes per quadruple)."""
     import torch
     o = P.setup(n2max, Q)
     if len(sides) == 3:
