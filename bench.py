@@ -21,7 +21,10 @@ The JSON line also carries
                    taken live with HIP events; algorithmic bytes are 16 of
                    indices in and 8 out per quadruple; value_build and
                    node_pass_roofline give the FP64 rates of the value-table
-                   build and of the steady node pass;
+                   build and of the node sums (one fused launch per call on
+                   this table; the separate launches of the profiling entry
+                   point are reported beside it), mixed_pass and fp32_pass
+                   those of the two FP32 arithmetics;
   cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the same stream,
                    on all host cores and on one, median of 5 runs after one
                    warm-up; the errors of every GPU result against it;
@@ -65,7 +68,7 @@ CSRC = os.path.join(ROOT, "paper_1502_08043_amd", "csrc")
 SOURCES = {"values": (os.path.join(CSRC, "value_kernels.hip"),
                       os.path.join(ROOT, "profiles", "k_rec_values_lookup_stream_9171pw_traffic.txt")),
            "passes": (os.path.join(CSRC, "reconstruct_kernels.hip"),
-                      os.path.join(ROOT, "profiles", "k_rec_pass_lookup_stream_9171pw_traffic.txt"))}
+                      os.path.join(ROOT, "profiles", "k_rec_fused_lookup_stream_9171pw_traffic.txt"))}
 
 
 def log(*a):
@@ -138,8 +141,8 @@ def reachable_values(n2max):
 
 def pmc_workload():
     """A plain copy of known size, three FP64 node-sum reconstructions of the
-    stream, three single-FP32 ones, then the value table and three
-    reconstructions that read it."""
+    stream, three single-FP32 ones (one fused launch each on this table),
+    then the value table and three reconstructions that read it."""
     import torch
     import paper_1502_08043_amd as pw
     w = workloads.C4_STREAM
@@ -689,6 +692,7 @@ def main():
         legs[name]["decode_ms"] = float(stages[0])
         legs[name]["pass_ms"] = [float(v) for v in stages[1:]]
         legs[name]["layout"] = t.layout(prec)
+        legs[name]["fused"] = t.fused(prec)
         if prec == pw.FP32:      # the FP32 table serves reconstruction only
             log(f"[bench] {name}: reconstruct {legs[name]['reconstruct_ms']:.3f} ms "
                 f"(decode {stages[0]:.3f} + passes {', '.join(f'{v:.3f}' for v in stages[1:])})")
@@ -741,49 +745,43 @@ def main():
                    "frac": vb_tf / FP64_PEAK_TFLOPS, "bound": "mfma",
                    "algorithmic_flops_per_launch": 2.0 * Q * nreach,
                    "eq14_equivalent_TFLOPs": 2.0 * vb_tf}
-    # The steady FP64 node pass (node sums without a value table).  Algorithmic
-    # work of Eq. 14: 4 flops per node term, c nodes per pass and integral.
-    lay = legs["fp64_node_sums"]["layout"]
-    c = lay["nodes_per_pass"]
-    P = len(legs["fp64_node_sums"]["pass_ms"])
-    steady = legs["fp64_node_sums"]["pass_ms"][1:] or legs["fp64_node_sums"]["pass_ms"]
-    pass_ms = float(np.mean(steady))
-    flops = 4.0 * c * n
-    np_tf = flops / (pass_ms * 1e-3) / 1e12
-    node_pass_roofline = {
-        "bound": "alu", "achieved": np_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": np_tf / FP64_PEAK_TFLOPS, "traffic": recorded_traffic("passes"),
-        "kernel": f"k_rec_pass<F64, G={lay['lanes']}, W={lay['words']}> steady node pass",
-        "launches_per_call": P, "nodes_per_launch": c,
-        "algorithmic_flops_per_launch": flops, "avg_launch_ms": pass_ms,
-        "first_pass_with_decode_ms": legs["fp64_node_sums"]["pass_ms"][0],
-        "lds_read_TBps": 3 * 8 * c * n / (pass_ms * 1e-3) / 1e12,
-        "hbm_algorithmic_GBps": 20.0 * n / (pass_ms * 1e-3) / 1e9,
-        "whole_call_TFLOPs": 4.0 * Q * n / (legs["fp64_node_sums"]["reconstruct_ms"] * 1e-3) / 1e12,
-        "kernel_source_sha256_16": kernel_hash("passes")}
-    # The split-FP32 steady pass, counted the same way (4 algorithmic flops per
-    # node term) against the FP32 vector peak; a float-float node term takes
-    # about 16 FP32 instructions.
-    mlay = legs["mixed"]["layout"]
-    msteady = legs["mixed"]["pass_ms"][1:] or legs["mixed"]["pass_ms"]
-    mpass_ms = float(np.mean(msteady))
-    mflops = 4.0 * mlay["nodes_per_pass"] * n
-    m_tf = mflops / (mpass_ms * 1e-3) / 1e12
-    mixed_pass = {"kernel": f"k_rec_pass<FF, G={mlay['lanes']}, W={mlay['words']}> steady node pass",
-                  "achieved": m_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                  "frac": m_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": mpass_ms,
-                  "lds_read_TBps": 3 * 8 * mlay["nodes_per_pass"] * n / (mpass_ms * 1e-3) / 1e12}
-    # The single-FP32 pass: 4-byte entries, so 12 bytes of LDS per node term.
-    slay = legs["fp32"]["layout"]
-    ssteady = legs["fp32"]["pass_ms"][1:] or legs["fp32"]["pass_ms"]
-    spass_ms = float(np.mean(ssteady))
-    s_tf = 4.0 * slay["nodes_per_pass"] * n / (spass_ms * 1e-3) / 1e12
-    fp32_pass = {"kernel": f"k_rec_pass<F32, G={slay['lanes']}, W={slay['words']}> "
-                           f"{'steady' if len(legs['fp32']['pass_ms']) > 1 else 'decoding'} node pass",
-                 "achieved": s_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": s_tf / FP32_PEAK_TFLOPS, "avg_launch_ms": spass_ms,
-                 "nodes_per_pass": slay["nodes_per_pass"], "passes": len(legs["fp32"]["pass_ms"]),
-                 "lds_read_TBps": 3 * 4 * slay["nodes_per_pass"] * n / (spass_ms * 1e-3) / 1e12}
+    # The node sums without a value table.  Algorithmic work of Eq. 14: 4
+    # flops per node term (two products and an add), Q terms per integral; the
+    # LDS reads are three entries per node term.  When the table runs fused
+    # the whole call is one launch; the separate launches (per-launch timing
+    # entry point, same results) are reported beside it.
+    def node_entry(name, arith, peak, entry_bytes):
+        lay, leg = legs[name]["layout"], legs[name]
+        P, c = lay["passes"], lay["nodes_per_pass"]
+        sep_ms = float(leg["decode_ms"] + np.sum(leg["pass_ms"]))
+        steady = leg["pass_ms"][1:] or leg["pass_ms"]
+        if leg["fused"]:
+            ms, nodes, launches = leg["reconstruct_ms"], Q, 1
+            kernel = f"k_rec_fused<{arith}> (all {P} node ranges of {c} in one launch)"
+            hbm = 24.0 * n                      # indices in, integrals out
+        else:
+            ms, nodes, launches = float(np.mean(steady)), c, P
+            kernel = f"k_rec_pass<{arith}, G={lay['lanes']}, W={lay['words']}> steady node pass"
+            hbm = 20.0 * n                      # packed entries and partial sums in, sums out
+        tf = 4.0 * nodes * n / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                "kernel": kernel, "launches_per_call": launches, "nodes_per_launch": nodes,
+                "algorithmic_flops_per_launch": 4.0 * nodes * n, "avg_launch_ms": ms,
+                "lds_read_TBps": 3 * entry_bytes * (P * c if leg["fused"] else c) * n / (ms * 1e-3) / 1e12,
+                "hbm_algorithmic_GBps": hbm / (ms * 1e-3) / 1e9,
+                "whole_call_ms": leg["reconstruct_ms"],
+                "whole_call_TFLOPs": 4.0 * Q * n / (leg["reconstruct_ms"] * 1e-3) / 1e12,
+                "separate_launches_ms": sep_ms,
+                "separate_steady_pass_ms": float(np.mean(steady)),
+                "separate_first_pass_with_decode_ms": leg["pass_ms"][0]}
+    node_pass_roofline = node_entry("fp64_node_sums", "F64", FP64_PEAK_TFLOPS, 8)
+    node_pass_roofline["traffic"] = recorded_traffic("passes")
+    node_pass_roofline["kernel_source_sha256_16"] = kernel_hash("passes")
+    # The two FP32 arithmetics against the FP32 vector peak: split FP32
+    # (a float-float node term takes about 16 FP32 instructions; 8-byte
+    # entries) and the single-FP32 table (4-byte entries).
+    mixed_pass = node_entry("mixed", "FF", FP32_PEAK_TFLOPS, 8)
+    fp32_pass = node_entry("fp32", "F32", FP32_PEAK_TFLOPS, 4)
 
     cfg, cfg_outs = (None, {}) if args.no_configs else configs_leg(pw, args.steps, args.warmup)
     gauss, gauss_q, gauss_out = (None, None, None) if args.no_configs else gauss_leg(pw, args.steps, args.warmup)

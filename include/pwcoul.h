@@ -307,6 +307,16 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
                                     int *nodes_per_pass, int *passes, int *entry_bytes);
 
 /*
+ * *fused = 1 when a node-pass reconstruction of precision p on this table
+ * runs fused: the one-lane layout (lanes 1, words 8) whose slab, basis and
+ * fold map fit in one workgroup's LDS, every pass in one launch with the
+ * partial sums in registers and no decoded stream (pwc_reconstruct and
+ * pwc_reconstruct_noalloc; pwc_reconstruct_profile always runs the separate
+ * launches, with the same results bit for bit); else 0.
+ */
+PWC_API pwc_status pwc_table_fused(const pwc_table *t, pwc_precision p, int *fused);
+
+/*
  * Force the reconstruction layout of every precision: (lanes, words) = (16, 1), (8, 2), (8, 1),
  * (4, 2), (2, 4), (1, 8) or (4, 1); (0, 0) restores the default choice.  A
  * PWC_FP32 pass covers 4 lanes x words nodes (four per 16-byte word), twice the

@@ -83,6 +83,7 @@ def lib():
             "pwc_table_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]),
             "pwc_table_layout": (i32, [vp, i32] + [ctypes.POINTER(i32)] * 5),
+            "pwc_table_fused": (i32, [vp, i32, ctypes.POINTER(i32)]),
             "pwc_table_set_layout": (i32, [vp, i32, i32]),
             "pwc_table_set_direct_max": (i32, [vp, i64]),
             "pwc_table_build_values": (i32, [vp, vp]),
@@ -258,6 +259,13 @@ class Table:
                "pwc_table_layout")
         return dict(zip(("lanes", "words", "nodes_per_pass", "passes", "entry_bytes"),
                         (x.value for x in v)))
+
+    def fused(self, precision=0):
+        """True when node-pass reconstructions of this precision run as one
+        fused launch (pwc_table_fused)."""
+        v = ctypes.c_int()
+        _check(lib().pwc_table_fused(self.handle, int(precision), ctypes.byref(v)), "pwc_table_fused")
+        return bool(v.value)
 
     def set_layout(self, lanes=0, words=0):
         """Force the reconstruction layout, (lanes, words) in (16, 1), (8, 2), (8, 1),

@@ -1053,6 +1053,13 @@ pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *lanes, int
     return PWC_OK;
 }
 
+pwc_status pwc_table_fused(const pwc_table *t, pwc_precision p, int *fused) {
+    if (!t || t->t.gauss || !fused || !pwc::valid_precision(p)) return PWC_ERR_ARG;
+    const pwc::FoldLayout &fl = p == PWC_MIXED ? t->t.flm : p == PWC_FP32 ? t->t.fls : t->t.fl;
+    *fused = pwc::fused_layout(fl, pwc::fold_maps_bytes(t->t.N, t->t.nd)) ? 1 : 0;
+    return PWC_OK;
+}
+
 pwc_status pwc_table_set_layout(pwc_table *t, int lanes, int words) {
     if (!t || t->t.gauss) return PWC_ERR_ARG;
     if (lanes == 0 && words != 0) return PWC_ERR_ARG;
