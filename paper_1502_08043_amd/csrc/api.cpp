@@ -84,6 +84,7 @@ bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, size_t maps_
         cand.G = l.G;
         cand.W = l.W;
         cand.E = E;
+        cand.nchunk = P;
         const bool fused = fused_layout(cand, maps_bytes);
         const double per16 = fused ? (p == PWC_MIXED ? kFused.mixed : p == PWC_FP32 ? kFused.fp32 : kFused.fp64)
                                    : (p == PWC_MIXED ? l.mixed : p == PWC_FP32 ? l.fp32 : l.fp64);

@@ -60,17 +60,18 @@
 // the slab; the later passes use the table's layout, for whose lane groups
 // the decode orders the entries.  Other tables decode in k_decode first.
 //
-// Fused schedule.  When the table's layout is the one-lane one and the
-// basis and fold map fit in LDS beside its slab, one launch does all the
-// passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
+// Fused schedule.  When the table's layout is the one-lane one, the basis
+// and fold map fit in LDS beside its slab and there is one pass or at least
+// four, one launch does all the passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
 // lane into registers, keeps their partial sums there, and for each node
 // range restages the slab from L2 (the whole folded table, 0.56 MB at 9171
 // planewaves and Q = 96, stays resident there) and adds its terms.  The
 // stream is then read once and the results written once (24 bytes per
 // quadruple instead of 28 + 20 per later pass), no decoded stream is
 // stored, and the next range's slab is loaded into registers while the
-// current one is read.  Larger chunks spill registers and run slower.  The
-// arithmetic and its order are those of the separate launches, so both
+// current one is read.  Larger chunks spill registers and run slower.  A
+// last range with fewer real nodes reads only its first 1, 2 or 4 words.
+// The arithmetic and its order are those of the separate launches, so both
 // schedules give the same bits.
 #include <algorithm>
 #include <cmath>
@@ -110,6 +111,7 @@ struct PassArgs {
     int K, nd;
     const void *tab;   // [E][Qp] double or float2: W_q^(1/3) tau_q
     int E, Qp, q0;     // this pass: nodes [q0, q0 + c) of every row
+    int Q;             // nodes of the mesh (the rest of a padded row is zero)
     void *scratch;     // [n] packed folded entries
     double pref;
     double *out;
@@ -609,22 +611,22 @@ __device__ __forceinline__ void fetch_slab(uint4 (&pre)[SPT], const uint4 *tab, 
     }
 }
 
-// One quadruple's terms of the staged node range, words k0 .. k0 + 3 of its
-// three rows, added to s in word order.
-template <typename A>
+// One quadruple's terms of the staged node range, steps k0 .. k0 + N - 1
+// of its three rows, added to s in step order.
+template <typename A, int N>
 __device__ __forceinline__ void fused_half(typename A::Acc &s, const char *lb, uint32_t a0, uint32_t a1, uint32_t a2,
                                            int k0) {
     using V = typename A::V;
-    V x[4], y[4], z[4];
+    V x[N], y[N], z[N];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < N; ++k) {
         const uint32_t o = (k0 + k) * 16;
         x[k] = *reinterpret_cast<const V *>(lb + (a0 ^ o));
         y[k] = *reinterpret_cast<const V *>(lb + (a1 ^ o));
         z[k] = *reinterpret_cast<const V *>(lb + (a2 ^ o));
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) A::add2(s, x[k], y[k], z[k]);
+    for (int k = 0; k < N; ++k) A::add2(s, x[k], y[k], z[k]);
 }
 
 // An empty register constraint: the compiler must assume the value changed
@@ -635,7 +637,7 @@ __device__ __forceinline__ void opaque(uint2 &v) {
     __asm__ volatile("" : "+v"(v.y));
 }
 
-template <typename A, typename PK, int SPT, int NT>
+template <typename A, typename PK, int SPT, int NT, int WL>
 __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     using T = typename PK::T;
     __shared__ uint4 lds_raw[kLdsMax / 16];
@@ -652,7 +654,6 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     __syncthreads();   // the maps, before the first decode
 
     const char *lb = reinterpret_cast<const char *>(lds_raw);
-    const uint32_t lane_b = static_cast<uint32_t>((threadIdx.x & 7) * 16);   // word k ^ (lane mod 8) at step k
     const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
     bool staged = false;
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n;
@@ -688,19 +689,40 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
                 staged = true;
                 if (P > 1) fetch_slab<SPT>(pre, tab, row, p + 1 < P ? p + 1 : 0, words);   // next range, or the next chunk's first
             }
+            // A short last range (fewer than 8 words of real nodes) reads its
+            // first wk = 1, 2 or 4 words only, word k ^ (lane mod wk) at step
+            // k: the order in which the full range meets those words, the
+            // others holding zero-weight padding, so the sum is the full
+            // range's.
+            if (WL < 8 && p == P - 1) {
+                const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & (WL - 1)) * 16);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    int f0, f1, f2;
+                    opaque(ev[t]);
+                    PK::unpack(ev[t], f0, f1, f2);
+                    typename A::Acc s;
+                    A::zero(s);
+                    fused_half<A, WL < 4 ? WL : 4>(s, lb, f0 * ROWB + lane_r, f1 * ROWB + lane_r, f2 * ROWB + lane_r, 0);
+                    acc[t] = acc[t] + A::value(s);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                continue;
+            }
+            const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & 7) * 16);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 int f0, f1, f2;
                 opaque(ev[t]);   // row addresses are formed per range, not kept for all eight
                 PK::unpack(ev[t], f0, f1, f2);
-                const uint32_t a0 = f0 * ROWB + lane_b, a1 = f1 * ROWB + lane_b, a2 = f2 * ROWB + lane_b;
+                const uint32_t a0 = f0 * ROWB + lane_r, a1 = f1 * ROWB + lane_r, a2 = f2 * ROWB + lane_r;
                 typename A::Acc s;
                 A::zero(s);
-                fused_half<A>(s, lb, a0, a1, a2, 0);
+                fused_half<A, 4>(s, lb, a0, a1, a2, 0);
                 // Each half's twelve reads in a block of their own: more in
                 // flight would spill.
                 __builtin_amdgcn_sched_barrier(0);
-                fused_half<A>(s, lb, a0, a1, a2, 4);
+                fused_half<A, 4>(s, lb, a0, a1, a2, 4);
                 acc[t] = acc[t] + A::value(s);
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -720,12 +742,20 @@ hipError_t launch_fused(const PassArgs &a, const Table &t, int P, hipStream_t s)
     const int words = a.E * 8;
     const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
     const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.n + chunk - 1) / chunk, t.n_cu));
-    if (words <= 6 * kThreads)
-        hipLaunchKernelGGL((k_rec_fused<A, PK, 6, NT>), dim3(grid), dim3(kThreads), 0, s, a, P);
-    else if (words <= 8 * kThreads)
-        hipLaunchKernelGGL((k_rec_fused<A, PK, 8, NT>), dim3(grid), dim3(kThreads), 0, s, a, P);
-    else
-        return hipErrorInvalidValue;
+    // Words of the last range that hold real nodes, rounded up to 1, 2, 4 or 8.
+    const int c = 8 * npw<A>();
+    const int real = (a.Q - (P - 1) * c + npw<A>() - 1) / npw<A>();
+    if (P < 1 || real < 1 || real > 8) return hipErrorInvalidValue;
+    const int wlast = real <= 1 ? 1 : real <= 2 ? 2 : real <= 4 ? 4 : 8;
+    if (words > 8 * kThreads) return hipErrorInvalidValue;
+    using K = void (*)(PassArgs, int);
+    static const K k6[4] = {k_rec_fused<A, PK, 6, NT, 1>, k_rec_fused<A, PK, 6, NT, 2>, k_rec_fused<A, PK, 6, NT, 4>,
+                            k_rec_fused<A, PK, 6, NT, 8>};
+    static const K k8[4] = {k_rec_fused<A, PK, 8, NT, 1>, k_rec_fused<A, PK, 8, NT, 2>, k_rec_fused<A, PK, 8, NT, 4>,
+                            k_rec_fused<A, PK, 8, NT, 8>};
+    const int w = wlast == 1 ? 0 : wlast == 2 ? 1 : wlast == 4 ? 2 : 3;
+    const K kern = words <= 6 * kThreads ? k6[w] : k8[w];
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, a, P);
     return hipGetLastError();
 }
 using PassKernel = void (*)(PassArgs);
@@ -891,6 +921,7 @@ hipError_t launch_reconstruct(const Table &t, const int32_t *d_quads, int64_t n,
     a.E1 = t.E1;
     a.ndir = t.ndir;
     a.Qp = t.fl.Qp;
+    a.Q = t.Q;
     a.pref = 1.0 / (std::sqrt(M_PI) * t.L);
     a.ord_g = layout_of(t, p).G;
     a.out = d_out;

@@ -354,14 +354,14 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     """Admission prices each request's device scratch from the kernels it
     will run on its table: the node-sum pair partials grow as (M/32)^2
     (1.3 MB at M = 9171), the kernel-table ones stay small, the direct
-    kernel and the fused node sums of the cube need none, and the node
-    passes of a box (2187 folded rows: no fused schedule) need the decoded
-    stream, 8 bytes per quadruple.  With a budget of the table plus 0.6 MB,
+    kernel and the fused node sums of the cube (Q = 64: four ranges) need
+    none, and the node passes of a box (2187 folded rows: no fused schedule)
+    need the decoded stream, 8 bytes per quadruple.  With a budget of the table plus 0.6 MB,
     what cannot fit beside the table fails with ERR_NOMEM at once and the
     rest runs; with more it all runs, and the results are the library's."""
     import torch
     pw.release_cached_memory()                 # no recycled (larger) blocks
-    key = (1.0, 169, 32)
+    key = (1.0, 169, 64)                      # FP64 node sums: four ranges, fused
     with pw.Table(*key) as t:
         tb = t.device_bytes
         occ = torch.arange(t.N, dtype=torch.int32, device="cuda")
@@ -401,7 +401,7 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     # The box's node passes keep the decoded stream: 8 MB for 1e6 quadruples.
     sides = (1.0, 1.3, 0.8)
     pw.release_cached_memory()
-    with pw.Table.box(*sides, 169, 32) as t:
+    with pw.Table.box(*sides, 169, 64) as t:
         tbb = t.device_bytes
         t.set_direct_max(0)
         r_box = t.reconstruct(big)
@@ -409,7 +409,7 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     for budget, status in ((tbb + 600_000, pw.ERR_NOMEM), (tbb + 12_000_000, pw.OK)):
         o_box = torch.full((1_000_000,), -1.0, dtype=torch.float64, device="cuda")
         with pw.Server(budget, max_inflight=2) as srv:
-            got = srv.wait(srv.submit_reconstruct(sides, 169, big, o_box, n_nodes=32)).status
+            got = srv.wait(srv.submit_reconstruct(sides, 169, big, o_box, n_nodes=64)).status
         say(f"[server] box table {tbb} B + {budget - tbb} B: {got}")
         assert got == status
         if status == pw.OK:
