@@ -303,6 +303,47 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
             assert not any(t.fused(p) for p in (pw.FP64, pw.MIXED, pw.FP32))
 
 
+# Meshes whose last node range is short in the fused one-lane schedule:
+# (mesh spec, Q, {precision: (fused, words of the last range)}).  FP64 and
+# split FP32 take 16 nodes a range, single FP32 32.
+SHORT_RANGES = [
+    (("root", 16, 4, 4, 7.0), 68, {"fp64": (True, 2), "fp32": (False, None)}),
+    (("root", 16, 2, 4, 7.0), 66, {"fp64": (True, 1), "fp32": (False, None)}),
+    (("geometric", 8, 8), 72, {"fp64": (True, 4), "fp32": (False, None)}),
+    (("root", 1, 4, 4, 7.0), 8, {"fp64": (True, 4), "fp32": (True, 2)}),
+    (("root", 24, 4, 4, 7.0), 100, {"fp64": (True, 2), "fp32": (True, 1)}),
+]
+
+
+@pytest.mark.parametrize("mesh,Q,expect", SHORT_RANGES)
+def test_fused_short_last_range(pw, mesh, Q, expect):
+    """The fused schedule reads only the real words of a short last node
+    range (1, 2 or 4 of 8): bit for bit the separate launches (which read
+    the zero padding too), and within the bar of the oracle, in all three
+    arithmetics, on a ragged stream."""
+    import torch
+    n2max = 25
+    o = P.setup(n2max, mesh=mesh)
+    assert len(o["W"]) == Q
+    kind, args = mesh[0], mesh[1:]
+    m = pw.Mesh.geometric_root(*args) if kind == "root" else pw.Mesh.geometric(*args)
+    quads = workloads.uniform_quads(len(o["basis"]), 30001, seed=Q)
+    dq = _dev(quads, torch.int32)
+    with pw.Table(1.0, n2max, mesh=m) as t:
+        assert t.Q == Q
+        t.set_direct_max(0)
+        t.set_layout(1, 8)
+        for name, prec in (("fp64", pw.FP64), ("mixed", pw.MIXED), ("fp32", pw.FP32)):
+            fused, _ = expect["fp64" if name == "mixed" else name]
+            assert t.fused(prec) == fused, (name, t.layout(prec))
+            a = t.reconstruct(dq, precision=prec)
+            b, _ = t.reconstruct_profile(dq, precision=prec)
+            t.sync()
+            assert torch.equal(a, b), (mesh, name)
+        _check_reconstruct(pw, t, o, quads, label=f"Q={Q} short last range")
+        t.set_layout(0, 0)
+
+
 def test_reconstruct_empty(pw, tables):
     import torch
     t = tables(9, 48)
