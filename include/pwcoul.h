@@ -309,8 +309,7 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
 /*
  * *fused = 1 when a node-pass reconstruction of precision p on this table
  * runs fused: the one-lane layout (lanes 1, words 8) whose slab, basis and
- * fold map fit in one workgroup's LDS, with one pass or at least four,
- * every pass in one launch with the
+ * fold map fit in one workgroup's LDS, every pass in one launch with the
  * partial sums in registers and no decoded stream (pwc_reconstruct and
  * pwc_reconstruct_noalloc; pwc_reconstruct_profile always runs the separate
  * launches, with the same results bit for bit); else 0.
@@ -403,10 +402,10 @@ PWC_API pwc_status pwc_table_copy(const pwc_table *t, double *d_dst, void *strea
  * value table built reads one value per quadruple; otherwise lists of at
  * most direct_max quadruples run the direct kernel and longer ones the node
  * passes (pwc_table_set_direct_max).  With the one-lane layout, when its
- * slab and the decode's basis and fold map fit in one workgroup's LDS and
- * there is one pass or at least four (pwc_table_fused), the passes run
- * fused in one launch that keeps no decoded stream; the results are those
- * of the separate launches, bit for bit.
+ * slab and the decode's basis and fold map fit in one workgroup's LDS
+ * (pwc_table_fused), the passes run fused in one launch that keeps no
+ * decoded stream; the results are those of the separate launches, bit for
+ * bit.
  */
 PWC_API pwc_status pwc_reconstruct(const pwc_table *t, const int32_t *d_quads, int64_t n,
                            double *d_out, pwc_precision p, void *stream);

@@ -72,11 +72,9 @@ inline size_t fold_maps_bytes(int64_t N, int nd) {
 // True when a reconstruction with layout fl runs as one fused launch: the
 // one-lane layout (1 lane, 8 words of 16 bytes per row), its slab and the
 // decode maps together in one workgroup's LDS, at most 8 slab words staged
-// per lane, and one node range or at least four (with two or three, the
-// fused launch's per-chunk decode and restaging cost more than the separate
-// launches' stream round trips on MI355X).  It keeps no decoded stream.
+// per lane.  It keeps no decoded stream.
 inline bool fused_layout(const FoldLayout &fl, size_t maps_bytes) {
-    return fl.G == 1 && fl.W == 8 && fl.E <= 1024 && (fl.nchunk == 1 || fl.nchunk >= 4) &&
+    return fl.G == 1 && fl.W == 8 && fl.E <= 1024 &&
            static_cast<size_t>(fl.E) * 128 + maps_bytes <= static_cast<size_t>(kLdsMax);
 }
 constexpr int kGaussMaxN1 = PWC_GAUSS_MAX_N1;

@@ -60,9 +60,9 @@
 // the slab; the later passes use the table's layout, for whose lane groups
 // the decode orders the entries.  Other tables decode in k_decode first.
 //
-// Fused schedule.  When the table's layout is the one-lane one, the basis
-// and fold map fit in LDS beside its slab and there is one pass or at least
-// four, one launch does all the passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
+// Fused schedule.  When the table's layout is the one-lane one and the
+// basis and fold map fit in LDS beside its slab, one launch does all the
+// passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
 // lane into registers, keeps their partial sums there, and for each node
 // range restages the slab from L2 (the whole folded table, 0.56 MB at 9171
 // planewaves and Q = 96, stays resident there) and adds its terms.  The

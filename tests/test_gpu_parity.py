@@ -274,8 +274,7 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
                 assert lay["passes"] == -(-Q // (npw * G * W))
             for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 lay = t.layout(prec)
-                assert not t.fused(prec) or ((lay["lanes"], lay["words"]) == (1, 8) and
-                                             (lay["passes"] == 1 or lay["passes"] >= 4))
+                assert not t.fused(prec) or (lay["lanes"], lay["words"]) == (1, 8)
             _check_reconstruct(pw, t, o, quads, label=f"n2max={n2max} Q={Q} layout={G}x{W}")
             for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 out = t.reconstruct(dq, precision=prec)
@@ -294,11 +293,10 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
         assert ei.value.status == pw.ERR_ARG
         t.set_layout(0, 0)
         assert (lanes_words(t, pw.FP64), lanes_words(t, pw.MIXED)) == (d64, dmx)
-        # the 9171-planewave table (729 folded rows) runs FP64 and split FP32
-        # fused (six ranges), not single FP32 (three); tables with more than
-        # 1024 rows never do
+        # the 9171-planewave table (729 folded rows) runs every precision
+        # fused; tables with more than 1024 rows never do
         if n2max == 169:
-            assert t.fused(pw.FP64) and t.fused(pw.MIXED) and not t.fused(pw.FP32)
+            assert all(t.fused(p) for p in (pw.FP64, pw.MIXED, pw.FP32))
         if t.layout(pw.FP64)["entry_bytes"] == 8:
             assert not any(t.fused(p) for p in (pw.FP64, pw.MIXED, pw.FP32))
 
@@ -307,9 +305,9 @@ def test_reconstruct_every_lane_layout(pw, n2max, Q, d64, dmx, eb, fits):
 # (mesh spec, Q, {precision: (fused, words of the last range)}).  FP64 and
 # split FP32 take 16 nodes a range, single FP32 32.
 SHORT_RANGES = [
-    (("root", 16, 4, 4, 7.0), 68, {"fp64": (True, 2), "fp32": (False, None)}),
-    (("root", 16, 2, 4, 7.0), 66, {"fp64": (True, 1), "fp32": (False, None)}),
-    (("geometric", 8, 8), 72, {"fp64": (True, 4), "fp32": (False, None)}),
+    (("root", 16, 4, 4, 7.0), 68, {"fp64": (True, 2), "fp32": (True, 1)}),
+    (("root", 16, 2, 4, 7.0), 66, {"fp64": (True, 1), "fp32": (True, 1)}),
+    (("geometric", 8, 8), 72, {"fp64": (True, 4), "fp32": (True, 2)}),
     (("root", 1, 4, 4, 7.0), 8, {"fp64": (True, 4), "fp32": (True, 2)}),
     (("root", 24, 4, 4, 7.0), 100, {"fp64": (True, 2), "fp32": (True, 1)}),
 ]

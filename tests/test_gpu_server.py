@@ -354,14 +354,13 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     """Admission prices each request's device scratch from the kernels it
     will run on its table: the node-sum pair partials grow as (M/32)^2
     (1.3 MB at M = 9171), the kernel-table ones stay small, the direct
-    kernel and the fused node sums of the cube (Q = 64: four ranges) need
-    none, and the node passes of a box (2187 folded rows: no fused schedule)
+    kernel and the fused node sums of the cube need none, and the node passes of a box (2187 folded rows: no fused schedule)
     need the decoded stream, 8 bytes per quadruple.  With a budget of the table plus 0.6 MB,
     what cannot fit beside the table fails with ERR_NOMEM at once and the
     rest runs; with more it all runs, and the results are the library's."""
     import torch
     pw.release_cached_memory()                 # no recycled (larger) blocks
-    key = (1.0, 169, 64)                      # FP64 node sums: four ranges, fused
+    key = (1.0, 169, 64)                      # FP64 node sums: fused
     with pw.Table(*key) as t:
         tb = t.device_bytes
         occ = torch.arange(t.N, dtype=torch.int32, device="cuda")

@@ -44,9 +44,8 @@ def test_noalloc_matches_the_allocating_call(pw, sides, n2max, Q):
     pwc_reconstruct on the node passes, and within the parity bar of the
     oracle on a sample.  The 9171-planewave box has 2187 folded rows: its
     passes keep a decoded stream of 8 bytes per quadruple in the fixed
-    scratch.  The cubes' one-lane layout runs fused where it covers one node
-    range or at least four and keeps none; otherwise the cubes keep 4 bytes
-    per quadruple."""
+    scratch.  The cubes' one-lane layout runs fused and keeps none (their
+    other layouts keep 4 bytes per quadruple)."""
     import torch
     o = P.setup(n2max, Q)
     if len(sides) == 3:
