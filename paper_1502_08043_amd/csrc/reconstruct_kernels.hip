@@ -76,6 +76,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "ffloat.h"
 #include "pwc_internal.h"
@@ -794,7 +795,9 @@ hipError_t run_passes(const PassArgs &a0, const Table &t, const FoldLayout &fl, 
         if (err != hipSuccess) return err;
     }
     // One launch for every pass, unless per-launch timing is asked for.
-    if (!stage_ev && fused_layout(fl, maps_bytes)) return launch_fused<A, PK>(a0, t, P, s);
+    // (fused_layout needs E <= 1024, so only the 4-byte packed entries occur)
+    if constexpr (std::is_same<PK, Pk32>::value)
+        if (!stage_ev && fused_layout(fl, maps_bytes)) return launch_fused<A, PK>(a0, t, P, s);
     if (!a0.scratch) return hipErrorInvalidValue;   // the separate launches need the decoded stream
     const int per_cu = 1;   // the static slab takes the CU's LDS
     // Slabs bound the scratch array: at most kRecSlab quadruples per slab.
