@@ -40,14 +40,15 @@
 //           taking chunk k ^ (g mod 4) at step k; groups g and g + 4 of a
 //           phase clash when their entry indices have equal parity;
 //   G = 1, W = 8: one lane per quadruple, word k ^ (g mod 8) at step k;
-//           lanes g and g + 8 of a phase clash on equal parity.
+//           lanes g and g + 24 (g + 8 and g + 16) of a 32-lane half-wave
+//           clash on equal row parity (pair_lane below).
 // The decode stores each quadruple's entries in ascending parity.  With
 // several lanes per quadruple, the groups that may clash hold quadruples of
 // different stream position (bit log2(8 / G) of e), and the stream word of
 // one of them is stored in descending order instead, which puts opposite
 // halves together where it can.  The one-lane passes pair their lanes
-// themselves (pair_lane): a wave's quadruples are dealt so that lanes g and
-// g + 8 hold complementary parity counts.
+// themselves (pair_lane): a wave's quadruples are dealt so that the lanes
+// that can clash hold complementary parity counts.
 // Each lane accumulates one partial sum per quadruple of its group (R); a
 // butterfly of DPP exchanges inside the 16-lane row halves the set at each
 // step, so that after log2(G) steps lane s holds the full sum of one
@@ -404,16 +405,21 @@ __device__ __forceinline__ uint2 bcast_row(uint2 v, int r) {
     return make_uint2(bcast_row<R>(v.x, r), bcast_row<R>(v.y, r));
 }
 
-// Lane pairing of the one-lane layout (G = 1).  Lanes g and g + 8 of a
-// 16-lane phase read the same word position of their rows at every step,
-// so their reads share banks exactly when the two rows have equal parity.
-// A quadruple with c odd entries read in ascending parity and one with
-// 3 - c odd entries read in descending parity meet opposite parities at all
-// three reads.  With random rows most phases would hold such a clash at
-// every read, so the wave's 64 quadruples are dealt to lanes: pairs
-// 0 .. m03 - 1 take classes 0 (low lane) and 3 (high lane), the next m12
-// pairs classes 1 and 2, and the quadruples left over fill the last pairs
-// in order.  Returns the lane that evaluates this lane's quadruple (a
+// Lane pairing of the one-lane layout (G = 1).  On gfx950 a 128-bit LDS
+// read serves the lanes of a 32-lane half-wave in two cycles of two 8-lane
+// groups; with rows of 128 bytes (half the 64 banks) and lane g reading
+// word k ^ (g mod 8) at step k, the read is conflict-free when lanes g and
+// g + 24, and g + 8 and g + 16, of each half-wave hold rows of opposite
+// parity (measured: random rows so paired take no conflict cycles; rows
+// paired at g and g + 8, or not at all, take one per cycle).  A quadruple
+// with c odd entries read in ascending parity and one with 3 - c odd
+// entries read in descending parity meet opposite parities at all three
+// reads, so the wave's 64 quadruples are dealt to lanes: pairs 0 .. m03 - 1
+// take classes 0 (low lane) and 3 (high lane), the next m12 pairs classes 1
+// and 2, and the quadruples left over fill the last pairs in order.  Pair
+// p sits in half-wave p / 16 at lanes i and i + 24 (p mod 16 = i < 8) or
+// i + 8 and i + 16 (p mod 16 = 8 + i); the high lanes are those with bit 4
+// set.  Returns the lane that evaluates this lane's quadruple (a
 // permutation of the wave; every lane must take part).
 __device__ __forceinline__ int pair_lane(int cls) {
     const uint64_t b0 = __builtin_amdgcn_ballot_w64(cls == 0);
@@ -436,7 +442,8 @@ __device__ __forceinline__ int pair_lane(int cls) {
         pair = m03 + m12 + (k >> 1);
         side = k & 1;
     }
-    return (pair & 7) | ((pair >> 3) << 4) | (side << 3);
+    const int i = pair & 7, second = (pair >> 3) & 1;
+    return ((pair >> 4) << 5) | i | (side ? (second ? 16 : 24) : (second ? 8 : 0));
 }
 
 // One node pass.  LDS: the slab [E][G W] of 16-byte words (nodes q0 ..
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
         if (PAIR) {
             dest = pair_lane(PK::odd(pk[0]));
             ev[0] = PK::send(pk[0], dest);
-            if (threadIdx.x & 8) ev[0] = PK::flip(ev[0]);
+            if (threadIdx.x & 16) ev[0] = PK::flip(ev[0]);   // high lane of its pair
         }
         V x[R][W], y[R][W], z[R][W];
 #pragma unroll
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
             const T pk = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
             dest[t] = pair_lane(PK::odd(pk));
             ev[t] = PK::send(pk, dest[t]);
-            if (threadIdx.x & 8) ev[t] = PK::flip(ev[t]);
+            if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
             acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
         }
         for (int p = 0; p < P; ++p) {
