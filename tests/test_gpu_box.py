@@ -70,18 +70,33 @@ def test_box_tables_and_reconstruction(pw, n2max, Q, sides):
         dq = _dev(quads, torch.int32)
         rr = torch.from_numpy(rows).cuda()
         outs = {}
-        for path, dm in (("direct", DIRECT_DEFAULT), ("passes", 0)):
+        tols = {pw.FP64: P.TOL_FP64, pw.MIXED: P.TOL_MIXED, pw.FP32: P.TOL_FP32}
+        # the direct kernel, the default layouts and the one-lane layout (fused
+        # when its slab and the basis maps fit in LDS, else refused)
+        for path, dm, lay in (("direct", DIRECT_DEFAULT, None), ("passes", 0, None), ("one-lane", 0, (1, 8))):
             t.set_direct_max(dm)
-            for prec in (pw.FP64, pw.MIXED):
+            if lay:
+                try:
+                    t.set_layout(*lay)
+                except pw.PwcError as e:   # the slab does not fit in LDS
+                    assert e.status == pw.ERR_RANGE
+                    continue
+            for prec in (pw.FP64, pw.MIXED, pw.FP32):
                 out = t.reconstruct(dq, precision=prec)
                 t.sync()
                 err = P.worst_cond_err(out[rr].cpu().numpy(), ref, cs)
-                say(f"[box] {sides} n2max={n2max} Q={Q} {path} prec={prec}: {err:.2e}")
-                assert err < P.TOL_FP64
+                say(f"[box] {sides} n2max={n2max} Q={Q} {path} prec={prec} fused={t.fused(prec)}: {err:.2e}")
+                assert err < tols[prec]
                 outs[path, prec] = out
-        for prec in (pw.FP64, pw.MIXED):
-            a, b = outs["direct", prec], outs["passes", prec]
-            assert (a - b).abs().max().item() <= 1e-12 * b.abs().max().item()
+            if lay:
+                t.set_layout(0, 0)
+        for prec in (pw.FP64, pw.MIXED, pw.FP32):
+            for path in ("passes", "one-lane"):
+                if (path, prec) not in outs:
+                    continue
+                a, b = outs["direct", prec], outs[path, prec]
+                tol = 1e-6 if prec == pw.FP32 else 1e-12
+                assert (a - b).abs().max().item() <= tol * b.abs().max().item()
 
 
 @pytest.mark.parametrize("n2max,Q,sides", CASES)
