@@ -63,16 +63,17 @@
 //
 // Fused schedule.  When the table's layout is the one-lane one and the
 // basis and fold map fit in LDS beside its slab, one launch does all the
-// passes (k_rec_fused): a workgroup decodes a chunk of 4 quadruples per
-// lane into registers, keeps their partial sums there, and for each node
-// range restages the slab from L2 (the whole folded table, 0.56 MB at 9171
-// planewaves and Q = 96, stays resident there) and adds its terms.  The
-// stream is then read once and the results written once (24 bytes per
-// quadruple instead of 28 + 20 per later pass), no decoded stream is
-// stored, and the next range's slab is loaded into registers while the
-// current one is read.  Larger chunks spill registers and run slower.  A
-// last range with fewer real nodes reads only its first 1, 2 or 4 words.
-// The arithmetic and its order are those of the separate launches, so both
+// passes (k_rec_fused): a workgroup decodes a chunk of 6 quadruples per
+// lane (5 when the slab takes 8 words per lane) into registers, keeps their
+// partial sums there, and for each node range restages the slab from L2
+// (the whole folded table, 0.56 MB at 9171 planewaves and Q = 96, stays
+// resident there) and adds its terms.  The stream is then read once and the
+// results written once (24 bytes per quadruple instead of 28 + 20 per later
+// pass), no decoded stream is stored, the next range's slab is loaded into
+// registers while the current one is read, and the next chunk's quadruples
+// while the last range is.  Larger chunks spill registers.  A last range
+// with fewer real nodes reads only its first 1, 2 or 4 words.  The
+// arithmetic and its order are those of the separate launches, so both
 // schedules give the same bits.
 #include <algorithm>
 #include <cmath>
@@ -606,15 +607,30 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
 // padded rows (P ranges of 8 words per row) is added to the chunk's partial
 // sums in range order, each range's terms in node order, exactly as the
 // one-lane passes do; the pairing of a chunk's quadruples is formed once.
-constexpr int kFusedChunk = 4;
+
+// Quadruples per lane and chunk (NT): as many as fit in registers beside the
+// staged slab words, 6 beside 6 words, 5 beside 8; one more spills.
+constexpr int fused_chunk(int spt) { return spt <= 6 ? 6 : 5; }
+
+// An empty register constraint: the compiler must assume the value is read
+// and changed here, so what feeds it is computed before this point and what
+// it feeds is formed after it (not hoisted out of the enclosing loop).
+__device__ __forceinline__ void opaque(uint32_t &v) { __asm__ volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(double &v) { __asm__ volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(uint2 &v) {
+    __asm__ volatile("" : "+v"(v.x));
+    __asm__ volatile("" : "+v"(v.y));
+}
 
 // Slab words of node range p: word j of row e is 16-byte word p W + j of
 // the padded row (row words); lane i stages words i + 1024 k.
 template <int SPT>
 __device__ __forceinline__ void fetch_slab(uint4 (&pre)[SPT], const uint4 *tab, int row, int p, int words) {
+    uint32_t i0 = threadIdx.x;
+    opaque(i0);   // the addresses are formed here, not kept in registers between fetches
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-        const int i = threadIdx.x + k * kThreads;
+        const int i = static_cast<int>(i0) + k * kThreads;
         pre[k] = i < words ? tab[static_cast<size_t>(i >> 3) * row + p * 8 + (i & 7)] : make_uint4(0, 0, 0, 0);
     }
 }
@@ -637,17 +653,13 @@ __device__ __forceinline__ void fused_half(typename A::Acc &s, const char *lb, u
     for (int k = 0; k < N; ++k) A::add2(s, x[k], y[k], z[k]);
 }
 
-// An empty register constraint: the compiler must assume the value changed
-// here, so what it feeds is not hoisted out of the enclosing loop.
-__device__ __forceinline__ void opaque(uint32_t &v) { __asm__ volatile("" : "+v"(v)); }
-__device__ __forceinline__ void opaque(uint2 &v) {
-    __asm__ volatile("" : "+v"(v.x));
-    __asm__ volatile("" : "+v"(v.y));
-}
-
-template <typename A, typename PK, int SPT, int NT, int WL>
+// MULTI: more than one node range (the slab is restaged for every range of
+// every chunk); else the one range is staged once.  WL: words of real nodes
+// in the last range, rounded up to 1, 2, 4 or 8.
+template <typename A, typename PK, int SPT, int NT, int WL, bool MULTI>
 __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     using T = typename PK::T;
+    typedef int v4i __attribute__((ext_vector_type(4)));
     __shared__ uint4 lds_raw[kLdsMax / 16];
     constexpr int ROWB = 8 * 16;
     const int words = a.E * 8;
@@ -657,83 +669,107 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     for (int i = threadIdx.x; i < a.nd * a.nd; i += kThreads) lfold[i] = static_cast<int16_t>(a.fold[i]);
     const uint4 *tab = static_cast<const uint4 *>(a.tab);
     const int row = a.Qp / npw<A>();
-    uint4 pre[SPT];
-    fetch_slab<SPT>(pre, tab, row, 0, words);
-    __syncthreads();   // the maps, before the first decode
-
     const char *lb = reinterpret_cast<const char *>(lds_raw);
     const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
-    bool staged = false;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n;
-         base += static_cast<int64_t>(gridDim.x) * chunk) {
+    const int64_t step = static_cast<int64_t>(gridDim.x) * chunk;
+
+    // A chunk's quadruples are streamed once, loaded while the previous
+    // chunk's last range is summed.
+    v4i qn[NT];
+    auto load_quads = [&](int64_t b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t e = b + t * kThreads + threadIdx.x;
+            qn[t] = e < a.n ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e) : v4i{0, 0, 0, 0};
+        }
+    };
+    uint4 pre[SPT];
+    auto stage = [&]() __attribute__((always_inline)) {   // the staged range into LDS, once every wave is done with the last
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int i = threadIdx.x + k * kThreads;
+            if (i < words) lds_raw[i] = pre[k];
+        }
+        __syncthreads();
+    };
+    fetch_slab<SPT>(pre, tab, row, 0, words);
+    load_quads(static_cast<int64_t>(blockIdx.x) * chunk);
+    if (!MULTI) stage();   // also orders the maps before the first decode
+    else __syncthreads();  // the maps, before the first decode
+
+    T ev[NT];
+    double acc[NT];
+    // One full range: each quadruple's terms in step order, its twelve reads
+    // of a half in a block of their own (more in flight would spill).
+    auto full_range = [&]() __attribute__((always_inline)) {
+        const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & 7) * 16);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            int f0, f1, f2;
+            opaque(ev[t]);   // row addresses are formed per range, not kept for all eight
+            PK::unpack(ev[t], f0, f1, f2);
+            const uint32_t a0 = f0 * ROWB + lane_r, a1 = f1 * ROWB + lane_r, a2 = f2 * ROWB + lane_r;
+            typename A::Acc s;
+            A::zero(s);
+            fused_half<A, 4>(s, lb, a0, a1, a2, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            fused_half<A, 4>(s, lb, a0, a1, a2, 4);
+            acc[t] = acc[t] + A::value(s);
+            opaque(acc[t]);   // summed here, not where it is stored
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // The last range.  A short one (fewer than 8 words of real nodes) reads
+    // its first WL words only, word k ^ (lane mod WL) at step k: the order in
+    // which the full range meets those words, the others holding zero-weight
+    // padding, so the sum is the full range's.
+    auto last_range = [&]() __attribute__((always_inline)) {
+        if constexpr (WL == 8) {
+            full_range();
+        } else {
+            const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & (WL - 1)) * 16);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                int f0, f1, f2;
+                opaque(ev[t]);
+                PK::unpack(ev[t], f0, f1, f2);
+                typename A::Acc s;
+                A::zero(s);
+                fused_half<A, WL < 4 ? WL : 4>(s, lb, f0 * ROWB + lane_r, f1 * ROWB + lane_r, f2 * ROWB + lane_r, 0);
+                acc[t] = acc[t] + A::value(s);
+                opaque(acc[t]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n; base += step) {
         // Decode and pair: lane dest[t] evaluates this lane's quadruple t.
-        T ev[NT];
         int dest[NT];
-        double acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int64_t e = base + t * kThreads + threadIdx.x;
-            int4 q = make_int4(0, 0, 0, 0);
-            if (e < a.n) {   // streamed once
-                typedef int v4i __attribute__((ext_vector_type(4)));
-                const v4i u = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
-                q = make_int4(u.x, u.y, u.z, u.w);
-            }
+            const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
             const T pk = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
             dest[t] = pair_lane(PK::odd(pk));
             ev[t] = PK::send(pk, dest[t]);
             if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
             acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
         }
-        for (int p = 0; p < P; ++p) {
-            if (P > 1 || !staged) {
-                __syncthreads();   // every wave is done with the previous range
-#pragma unroll
-                for (int k = 0; k < SPT; ++k) {
-                    const int i = threadIdx.x + k * kThreads;
-                    if (i < words) lds_raw[i] = pre[k];
-                }
-                __syncthreads();
-                staged = true;
-                if (P > 1) fetch_slab<SPT>(pre, tab, row, p + 1 < P ? p + 1 : 0, words);   // next range, or the next chunk's first
+        if constexpr (MULTI) {
+            for (int p = 0; p + 1 < P; ++p) {
+                stage();
+                fetch_slab<SPT>(pre, tab, row, p + 1, words);   // the next range
+                full_range();
             }
-            // A short last range (fewer than 8 words of real nodes) reads its
-            // first wk = 1, 2 or 4 words only, word k ^ (lane mod wk) at step
-            // k: the order in which the full range meets those words, the
-            // others holding zero-weight padding, so the sum is the full
-            // range's.
-            if (WL < 8 && p == P - 1) {
-                const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & (WL - 1)) * 16);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    int f0, f1, f2;
-                    opaque(ev[t]);
-                    PK::unpack(ev[t], f0, f1, f2);
-                    typename A::Acc s;
-                    A::zero(s);
-                    fused_half<A, WL < 4 ? WL : 4>(s, lb, f0 * ROWB + lane_r, f1 * ROWB + lane_r, f2 * ROWB + lane_r, 0);
-                    acc[t] = acc[t] + A::value(s);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                continue;
-            }
-            const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & 7) * 16);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                int f0, f1, f2;
-                opaque(ev[t]);   // row addresses are formed per range, not kept for all eight
-                PK::unpack(ev[t], f0, f1, f2);
-                const uint32_t a0 = f0 * ROWB + lane_r, a1 = f1 * ROWB + lane_r, a2 = f2 * ROWB + lane_r;
-                typename A::Acc s;
-                A::zero(s);
-                fused_half<A, 4>(s, lb, a0, a1, a2, 0);
-                // Each half's twelve reads in a block of their own: more in
-                // flight would spill.
-                __builtin_amdgcn_sched_barrier(0);
-                fused_half<A, 4>(s, lb, a0, a1, a2, 4);
-                acc[t] = acc[t] + A::value(s);
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            stage();
+            load_quads(base + step);
+            last_range();
+            fetch_slab<SPT>(pre, tab, row, 0, words);   // the next chunk's first range
+        } else {
+            load_quads(base + step);
+            last_range();
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -745,24 +781,32 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     }
 }
 
-template <typename A, typename PK, int NT = kFusedChunk>
+template <typename A, typename PK>
 hipError_t launch_fused(const PassArgs &a, const Table &t, int P, hipStream_t s) {
     const int words = a.E * 8;
-    const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
+    if (words > 8 * kThreads) return hipErrorInvalidValue;
+    const bool six = words <= 6 * kThreads;   // staged words per lane: 6, else 8
+    const int64_t chunk = static_cast<int64_t>(kThreads) * (six ? fused_chunk(6) : fused_chunk(8));
     const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.n + chunk - 1) / chunk, t.n_cu));
     // Words of the last range that hold real nodes, rounded up to 1, 2, 4 or 8.
     const int c = 8 * npw<A>();
     const int real = (a.Q - (P - 1) * c + npw<A>() - 1) / npw<A>();
     if (P < 1 || real < 1 || real > 8) return hipErrorInvalidValue;
     const int wlast = real <= 1 ? 1 : real <= 2 ? 2 : real <= 4 ? 4 : 8;
-    if (words > 8 * kThreads) return hipErrorInvalidValue;
     using K = void (*)(PassArgs, int);
-    static const K k6[4] = {k_rec_fused<A, PK, 6, NT, 1>, k_rec_fused<A, PK, 6, NT, 2>, k_rec_fused<A, PK, 6, NT, 4>,
-                            k_rec_fused<A, PK, 6, NT, 8>};
-    static const K k8[4] = {k_rec_fused<A, PK, 8, NT, 1>, k_rec_fused<A, PK, 8, NT, 2>, k_rec_fused<A, PK, 8, NT, 4>,
-                            k_rec_fused<A, PK, 8, NT, 8>};
+    constexpr int N6 = fused_chunk(6), N8 = fused_chunk(8);
+    // [staged words per lane 6 or 8][one range or several][last range's words]
+    static const K kern_of[2][2][4] = {
+        {{k_rec_fused<A, PK, 6, N6, 1, false>, k_rec_fused<A, PK, 6, N6, 2, false>,
+          k_rec_fused<A, PK, 6, N6, 4, false>, k_rec_fused<A, PK, 6, N6, 8, false>},
+         {k_rec_fused<A, PK, 6, N6, 1, true>, k_rec_fused<A, PK, 6, N6, 2, true>,
+          k_rec_fused<A, PK, 6, N6, 4, true>, k_rec_fused<A, PK, 6, N6, 8, true>}},
+        {{k_rec_fused<A, PK, 8, N8, 1, false>, k_rec_fused<A, PK, 8, N8, 2, false>,
+          k_rec_fused<A, PK, 8, N8, 4, false>, k_rec_fused<A, PK, 8, N8, 8, false>},
+         {k_rec_fused<A, PK, 8, N8, 1, true>, k_rec_fused<A, PK, 8, N8, 2, true>,
+          k_rec_fused<A, PK, 8, N8, 4, true>, k_rec_fused<A, PK, 8, N8, 8, true>}}};
     const int w = wlast == 1 ? 0 : wlast == 2 ? 1 : wlast == 4 ? 2 : 3;
-    const K kern = words <= 6 * kThreads ? k6[w] : k8[w];
+    const K kern = kern_of[six ? 0 : 1][P > 1 ? 1 : 0][w];
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, a, P);
     return hipGetLastError();
 }

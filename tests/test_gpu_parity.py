@@ -342,6 +342,45 @@ def test_fused_short_last_range(pw, mesh, Q, expect):
         t.set_layout(0, 0)
 
 
+# A table whose fused slab takes 8 staged words per lane: 841 folded rows at
+# n2max = 200, the decode maps still beside them in LDS.  One range and
+# several, full and short last ranges, in the three arithmetics:
+# Q: {precision: (node ranges, words of the last range)}.
+EIGHT_WORD = {
+    16: {"fp64": (1, 8), "fp32": (1, 4)},
+    72: {"fp64": (5, 4), "fp32": (3, 2)},
+    96: {"fp64": (6, 8), "fp32": (3, 8)},
+}
+
+
+@pytest.mark.parametrize("Q", sorted(EIGHT_WORD))
+def test_fused_eight_word_slab(pw, Q):
+    """The fused kernels that stage 8 slab words per lane (and hold 5
+    quadruples per lane, not 6): bit for bit the separate launches, and
+    within the bar of the oracle, on a ragged stream."""
+    import torch
+    n2max = 200
+    o = P.setup(n2max, Q)
+    quads = workloads.uniform_quads(len(o["basis"]), 30001, seed=Q + 200)
+    dq = _dev(quads, torch.int32)
+    with pw.Table(1.0, n2max, Q) as t:
+        t.set_direct_max(0)
+        t.set_layout(1, 8)
+        for name, prec in (("fp64", pw.FP64), ("mixed", pw.MIXED), ("fp32", pw.FP32)):
+            ranges, words = EIGHT_WORD[Q]["fp64" if name == "mixed" else name]
+            lay = t.layout(prec)
+            assert t.fused(prec) and lay["passes"] == ranges, (name, lay)
+            npw = 4 if name == "fp32" else 2   # nodes per 16-byte word
+            last = Q - (ranges - 1) * 8 * npw
+            assert min(w for w in (1, 2, 4, 8) if w * npw >= last) == words
+            a = t.reconstruct(dq, precision=prec)
+            b, _ = t.reconstruct_profile(dq, precision=prec)
+            t.sync()
+            assert torch.equal(a, b), (Q, name)
+        _check_reconstruct(pw, t, o, quads, label=f"n2max=200 Q={Q} eight-word slab")
+        t.set_layout(0, 0)
+
+
 def test_reconstruct_empty(pw, tables):
     import torch
     t = tables(9, 48)
