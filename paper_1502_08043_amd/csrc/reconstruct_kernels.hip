@@ -608,6 +608,12 @@ __global__ __launch_bounds__(kThreads) void k_rec_pass(PassArgs a) {
 // sums in range order, each range's terms in node order, exactly as the
 // one-lane passes do; the pairing of a chunk's quadruples is formed once.
 
+// Word 3 of a raw buffer resource on gfx9 parts (untyped access; the
+// other fields are the base, a zero stride and the size in bytes), and the
+// cache policy of a streaming (non-temporal) access.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+constexpr int kCachePolicyNT = 2;
+
 // Quadruples per lane and chunk (NT): as many as fit in registers beside the
 // staged slab words, 6 beside 6 words, 5 beside 8; one more spills.
 constexpr int fused_chunk(int spt) { return spt <= 6 ? 6 : 5; }
@@ -623,15 +629,20 @@ __device__ __forceinline__ void opaque(uint2 &v) {
 }
 
 // Slab words of node range p: word j of row e is 16-byte word p W + j of
-// the padded row (row words); lane i stages words i + 1024 k.
+// the padded row (row words); lane i stages words i + 1024 k.  The loads go
+// through a buffer resource over the table (rsrc), which returns zero past
+// its end: with no branch around a load, a wait for an earlier load counts
+// exactly the loads issued after it, so the wait for the next chunk's
+// quadruples does not also wait for these words.
 template <int SPT>
-__device__ __forceinline__ void fetch_slab(uint4 (&pre)[SPT], const uint4 *tab, int row, int p, int words) {
+__device__ __forceinline__ void fetch_slab(uint4 (&pre)[SPT], __amdgpu_buffer_rsrc_t rsrc, int row, int p) {
     uint32_t i0 = threadIdx.x;
     opaque(i0);   // the addresses are formed here, not kept in registers between fetches
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const int i = static_cast<int>(i0) + k * kThreads;
-        pre[k] = i < words ? tab[static_cast<size_t>(i >> 3) * row + p * 8 + (i & 7)] : make_uint4(0, 0, 0, 0);
+        const int word = (i >> 3) * row + p * 8 + (i & 7);
+        pre[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, word * 16, 0, 0));
     }
 }
 
@@ -667,21 +678,36 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
     for (int i = threadIdx.x; i < a.N; i += kThreads) lbasis[i] = a.basis[i];
     for (int i = threadIdx.x; i < a.nd * a.nd; i += kThreads) lfold[i] = static_cast<int16_t>(a.fold[i]);
-    const uint4 *tab = static_cast<const uint4 *>(a.tab);
     const int row = a.Qp / npw<A>();
+    // The whole folded table (E rows of row words): words past the slab read zero.
+    const __amdgpu_buffer_rsrc_t slab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.tab), 0, a.E * row * 16, kBufferRsrcWord3);
     const char *lb = reinterpret_cast<const char *>(lds_raw);
     const int64_t chunk = static_cast<int64_t>(kThreads) * NT;
     const int64_t step = static_cast<int64_t>(gridDim.x) * chunk;
 
     // A chunk's quadruples are streamed once, loaded while the previous
-    // chunk's last range is summed.
+    // chunk's last range is summed (every lane loads; past the stream, its
+    // last quadruple, which the decode then ignores).
     v4i qn[NT];
     auto load_quads = [&](int64_t b) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int64_t e = b + t * kThreads + threadIdx.x;
-            qn[t] = e < a.n ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e) : v4i{0, 0, 0, 0};
+            const int64_t e = min(b + t * kThreads + threadIdx.x, a.n - 1);
+            qn[t] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
         }
+    };
+    // A chunk's results go out through a buffer resource that covers the
+    // chunk's part of the stream: stores past its end are dropped by the
+    // hardware, with no branch around them (see fetch_slab).
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    auto store_results = [&](int64_t b, const double (&v)[NT]) __attribute__((always_inline)) {
+        const int bytes = static_cast<int>(min(a.n - b, chunk) * static_cast<int64_t>(sizeof(double)));
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(a.out + b, 0, bytes, kBufferRsrcWord3);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v[t]), r,
+                                                  (t * kThreads + static_cast<int>(threadIdx.x)) * 8, 0, kCachePolicyNT);
     };
     uint4 pre[SPT];
     auto stage = [&]() __attribute__((always_inline)) {   // the staged range into LDS, once every wave is done with the last
@@ -693,8 +719,8 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
         }
         __syncthreads();
     };
-    fetch_slab<SPT>(pre, tab, row, 0, words);
-    load_quads(static_cast<int64_t>(blockIdx.x) * chunk);
+    load_quads(static_cast<int64_t>(blockIdx.x) * chunk);   // in the order of the loop's back edge
+    fetch_slab<SPT>(pre, slab_rsrc, row, 0);
     if (!MULTI) stage();   // also orders the maps before the first decode
     else __syncthreads();  // the maps, before the first decode
 
@@ -760,24 +786,24 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
         if constexpr (MULTI) {
             for (int p = 0; p + 1 < P; ++p) {
                 stage();
-                fetch_slab<SPT>(pre, tab, row, p + 1, words);   // the next range
+                fetch_slab<SPT>(pre, slab_rsrc, row, p + 1);   // the next range
                 full_range();
             }
             stage();
             load_quads(base + step);
             last_range();
-            fetch_slab<SPT>(pre, tab, row, 0, words);   // the next chunk's first range
+            fetch_slab<SPT>(pre, slab_rsrc, row, 0);   // the next chunk's first range
         } else {
             load_quads(base + step);
             last_range();
         }
+        double res[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const double v = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2hiint(acc[t])),
-                                              __builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2loint(acc[t])));
-            const int64_t e = base + t * kThreads + threadIdx.x;
-            if (e < a.n) __builtin_nontemporal_store(v * a.pref, a.out + e);
-        }
+        for (int t = 0; t < NT; ++t)
+            res[t] = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2hiint(acc[t])),
+                                      __builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2loint(acc[t]))) *
+                     a.pref;
+        store_results(base, res);
     }
 }
 
