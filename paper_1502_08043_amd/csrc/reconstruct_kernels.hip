@@ -328,9 +328,10 @@ __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const in
     }
     const int K = a.K, nd = a.nd;
     const int ni = basis[v.x], nj = basis[v.y], nk = basis[v.z], nl = basis[v.w];
-    const int ix = (bx(nk) - bx(ni) + K) * nd + (bx(nl) - bx(nj) + K);
-    const int iy = (by(nk) - by(ni) + K) * nd + (by(nl) - by(nj) + K);
-    const int iz = (bz(nk) - bz(ni) + K) * nd + (bz(nl) - bz(nj) + K);
+    // (difference + K) lies in [0, 2K] and nd = 2K + 1 is small: 24-bit products
+    const int ix = __umul24(bx(nk) - bx(ni) + K, nd) + (bx(nl) - bx(nj) + K);
+    const int iy = __umul24(by(nk) - by(ni) + K, nd) + (by(nl) - by(nj) + K);
+    const int iz = __umul24(bz(nk) - bz(ni) + K, nd) + (bz(nl) - bz(nj) + K);
     int fx = lfold ? lfold[ix] : gfold[ix];
     int fy = lfold ? lfold[iy] : gfold[iy];
     int fz = lfold ? lfold[iz] : gfold[iz];
@@ -423,16 +424,17 @@ __device__ __forceinline__ uint2 bcast_row(uint2 v, int r) {
 // set.  Returns the lane that evaluates this lane's quadruple (a
 // permutation of the wave; every lane must take part).
 __device__ __forceinline__ int pair_lane(int cls) {
-    const uint64_t b0 = __builtin_amdgcn_ballot_w64(cls == 0);
-    const uint64_t b1 = __builtin_amdgcn_ballot_w64(cls == 1);
-    const uint64_t b2 = __builtin_amdgcn_ballot_w64(cls == 2);
-    const uint64_t b3 = __builtin_amdgcn_ballot_w64(cls == 3);
-    const int n0 = __popcll(b0), n1 = __popcll(b1), n2 = __popcll(b2), n3 = __popcll(b3);
+    // Two ballots carry every lane's class: its low bit in lo, its high bit in hi.
+    const uint64_t lo = __builtin_amdgcn_ballot_w64(cls & 1), hi = __builtin_amdgcn_ballot_w64(cls & 2);
+    const int n3 = __popcll(lo & hi), n1 = __popcll(lo & ~hi), n2 = __popcll(~lo & hi);
+    const int n0 = 64 - n1 - n2 - n3;
     const int m03 = min(n0, n3), m12 = min(n1, n2), l03 = n0 + n3 - 2 * m03;
     const bool outer = cls == 0 || cls == 3;
-    const uint64_t same = cls == 0 ? b0 : cls == 1 ? b1 : cls == 2 ? b2 : b3;
-    const int r = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(same >> 32),
-                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(same), 0));
+    // The lanes of this lane's class: both bits equal to its own.
+    const uint32_t m1 = 0u - static_cast<uint32_t>(cls & 1), m2 = 0u - static_cast<uint32_t>((cls >> 1) & 1);
+    const uint32_t same_lo = ~((static_cast<uint32_t>(lo) ^ m1) | (static_cast<uint32_t>(hi) ^ m2));
+    const uint32_t same_hi = ~((static_cast<uint32_t>(lo >> 32) ^ m1) | (static_cast<uint32_t>(hi >> 32) ^ m2));
+    const int r = __builtin_amdgcn_mbcnt_hi(same_hi, __builtin_amdgcn_mbcnt_lo(same_lo, 0));
     const int m = outer ? m03 : m12;
     int pair, side;
     if (r < m) {                      // a matched pair: classes 0 and 1 low, 2 and 3 high
@@ -687,23 +689,28 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     const int64_t step = static_cast<int64_t>(gridDim.x) * chunk;
 
     // A chunk's quadruples are streamed once, loaded while the previous
-    // chunk's last range is summed (every lane loads; past the stream, its
-    // last quadruple, which the decode then ignores).
+    // chunk's last range is summed, through a buffer resource over the
+    // chunk's part of the stream (past its end the loads return zero, and
+    // the decode skips those lanes).
+    auto chunk_len = [&](int64_t b) __attribute__((always_inline)) {   // quadruples of the chunk at b
+        return static_cast<int>(max<int64_t>(0, min(a.n - b, chunk)));
+    };
     v4i qn[NT];
     auto load_quads = [&](int64_t b) __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int4 *>(a.quads + min(b, a.n)), 0, chunk_len(b) * static_cast<int>(sizeof(int4)), kBufferRsrcWord3);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int64_t e = min(b + t * kThreads + threadIdx.x, a.n - 1);
-            qn[t] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(a.quads) + e);
-        }
+        for (int t = 0; t < NT; ++t)
+            qn[t] = __builtin_amdgcn_raw_buffer_load_b128(r, (t * kThreads + static_cast<int>(threadIdx.x)) * 16, 0,
+                                                          kCachePolicyNT);
     };
     // A chunk's results go out through a buffer resource that covers the
     // chunk's part of the stream: stores past its end are dropped by the
     // hardware, with no branch around them (see fetch_slab).
     typedef unsigned int v2u __attribute__((ext_vector_type(2)));
     auto store_results = [&](int64_t b, const double (&v)[NT]) __attribute__((always_inline)) {
-        const int bytes = static_cast<int>(min(a.n - b, chunk) * static_cast<int64_t>(sizeof(double)));
-        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(a.out + b, 0, bytes, kBufferRsrcWord3);
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            a.out + b, 0, chunk_len(b) * static_cast<int>(sizeof(double)), kBufferRsrcWord3);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v[t]), r,
@@ -773,11 +780,12 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n; base += step) {
         // Decode and pair: lane dest[t] evaluates this lane's quadruple t.
         int dest[NT];
+        const int len = chunk_len(base);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int64_t e = base + t * kThreads + threadIdx.x;
             const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
-            const T pk = e < a.n ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
+            const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
+            const T pk = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
             dest[t] = pair_lane(PK::odd(pk));
             ev[t] = PK::send(pk, dest[t]);
             if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
