@@ -24,7 +24,8 @@ The JSON line also carries
                    build and of the node sums (one fused launch per call on
                    this table; the separate launches of the profiling entry
                    point are reported beside it), mixed_pass and fp32_pass
-                   those of the two FP32 arithmetics;
+                   those of the two FP32 arithmetics; the node sums also
+                   carry their LDS read rate against the LDS read peak;
   cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the same stream,
                    on all host cores and on one, median of 5 runs after one
                    warm-up; the errors of every GPU result against it;
@@ -63,6 +64,9 @@ import workloads  # noqa: E402
 FP64_PEAK_TFLOPS = 78.6                     # MI355X FP64 vector, dense
 FP32_PEAK_TFLOPS = 157.3                    # MI355X FP32 vector, dense
 HBM_PEAK_GBPS = 8000.0
+# LDS reads: a conflict-free ds_read_b128 wavefront instruction (1 KiB) takes 4
+# LDS cycles, so 256 B per clock per CU; 256 CUs at 2.4 GHz.
+LDS_PEAK_TBPS = 256 * 256 * 2.4e9 / 1e12
 CSRC = os.path.join(ROOT, "paper_1502_08043_amd", "csrc")
 # kernel source -> committed counter summary of its kernel on the lookup stream
 SOURCES = {"values": (os.path.join(CSRC, "value_kernels.hip"),
@@ -764,10 +768,11 @@ def main():
             kernel = f"k_rec_pass<{arith}, G={lay['lanes']}, W={lay['words']}> steady node pass"
             hbm = 20.0 * n                      # packed entries and partial sums in, sums out
         tf = 4.0 * nodes * n / (ms * 1e-3) / 1e12
+        lds = 3 * entry_bytes * (P * c if leg["fused"] else c) * n / (ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                 "kernel": kernel, "launches_per_call": launches, "nodes_per_launch": nodes,
                 "algorithmic_flops_per_launch": 4.0 * nodes * n, "avg_launch_ms": ms,
-                "lds_read_TBps": 3 * entry_bytes * (P * c if leg["fused"] else c) * n / (ms * 1e-3) / 1e12,
+                "lds_read_TBps": lds, "lds_peak_TBps": LDS_PEAK_TBPS, "lds_frac": lds / LDS_PEAK_TBPS,
                 "hbm_algorithmic_GBps": hbm / (ms * 1e-3) / 1e9,
                 "whole_call_ms": leg["reconstruct_ms"],
                 "whole_call_TFLOPs": 4.0 * Q * n / (leg["reconstruct_ms"] * 1e-3) / 1e12,
