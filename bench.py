@@ -40,7 +40,7 @@ The JSON line also carries
                    boxes, cutoffs and node counts at 50, 80 and 95% load, a
                    64 MiB budget, and FP64 against split-FP32.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--kernel-reps R] [--gpus 1] [--no-cpu-baseline]
                     [--serve-requests R | --no-serve] [--no-configs] [--no-fixed-error]
     python bench.py --pmc-workload     # the short run the counter profiles use
 """
@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quads", type=int, default=workloads.C4_STREAM.n_quads)
     ap.add_argument("--serve-requests", type=int, default=2000)
