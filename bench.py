@@ -35,7 +35,8 @@ The JSON line also carries
   fixed_error   -- every path timed at the node count that reaches a target
                    error against the converged oracle (1e-9 absolute, and six
                    places), node sums against node sums;
-  legs          -- per-leg step and kernel times, pair-sum rates;
+  legs          -- per-leg step and kernel times (the reconstruction also per
+                   half of the stream), pair-sum rates;
   serving       -- p50/p99 latency of a Poisson request stream over many
                    boxes, cutoffs and node counts at 50, 80 and 95% load, a
                    64 MiB budget, and FP64 against split-FP32.
@@ -683,6 +684,20 @@ def main():
     legs["fp64"]["value_table_bytes"] = nvalues * 8
     t.reconstruct(quads, out["fp64"])
     legs["fp64"]["reconstruct_ms"] = timed(lambda: t.reconstruct(quads, out["fp64"]), args.kernel_reps)
+    half = n // 2
+
+    def per_half(name, prec):
+        """The two halves of the stream timed apart: uniform over the basis,
+        then over the occupied orbitals."""
+        res = {}
+        for key, sl in (("uniform", slice(0, half)), ("occupied", slice(half, n))):
+            q, o = quads[sl], out[name][sl]
+            ms = timed(lambda: t.reconstruct(q, o, precision=prec), args.kernel_reps)
+            res[key] = {"reconstruct_ms": ms, "integrals_per_s": (sl.stop - sl.start) / (ms * 1e-3)}
+        log(f"[bench] {name} per half: uniform {res['uniform']['reconstruct_ms']:.3f} ms, "
+            f"occupied {res['occupied']['reconstruct_ms']:.3f} ms")
+        return res
+    legs["fp64"]["per_half"] = per_half("fp64", pw.FP64)
     log(f"[bench] fp64 values: build {legs['fp64']['value_build_ms']:.3f} ms "
         f"({nvalues} values), reads {legs['fp64']['reconstruct_ms']:.3f} ms")
     t.free_values()
@@ -690,6 +705,7 @@ def main():
         t.reconstruct(quads, out[name], precision=prec)
         legs[name]["reconstruct_ms"] = timed(lambda: t.reconstruct(quads, out[name], precision=prec),
                                              args.kernel_reps)
+        legs[name]["per_half"] = per_half(name, prec)
         # per launch: decode, then the node passes
         stages = np.array([t.reconstruct_profile(quads, out[name], precision=prec)[1]
                            for _ in range(args.kernel_reps)]).mean(axis=0)
