@@ -26,6 +26,9 @@ The JSON line also carries
                    point are reported beside it), mixed_pass and fp32_pass
                    those of the two FP32 arithmetics; the node sums also
                    carry their LDS read rate against the LDS read peak;
+  errors_vs_fp64_value_table_all_outputs
+                -- every output of the node-sum legs against the FP64
+                   value-table leg's, over the whole stream, on the GPU;
   cpu_baseline  -- the FP64 CPU oracle on a bounded sample of the same stream,
                    on all host cores and on one, median of 5 runs after one
                    warm-up; the errors of every GPU result against it;
@@ -730,6 +733,15 @@ def main():
             f"exchange M={M} {legs[name]['exchange_M925_ktable_ms'] * 1e3:.1f} us, "
             f"M={N} {legs[name]['exchange_M9171_ktable_ms'] * 1e3:.1f} us (kernel table), "
             f"{legs[name]['exchange_M9171_nodesum_ms']:.3f} ms (node sums)")
+    # Every output of the node-sum legs against the FP64 value-table leg (the
+    # same integrals by another path), on the GPU over all n quadruples.
+    all_vs_fp64 = {}
+    for name in ("fp64_node_sums", "mixed", "fp32"):
+        d = (out[name] - out["fp64"]).abs()
+        all_vs_fp64[name] = {"max_abs": float(d.max()), "mean_abs": float(d.mean()), "n": n}
+        del d
+    log(f"[bench] all {n} outputs against the FP64 value table: "
+        + ", ".join(f"{k} max {v['max_abs']:.2e}" for k, v in all_vs_fp64.items()))
     tb0 = time.perf_counter()
     for _ in range(5):
         pw.Table(w.L, w.n2max, w.n_nodes).close()
@@ -867,6 +879,7 @@ def main():
                           legs["fp64"]["integrals_per_s"],
                           "fp32_table_vs_fp64_node_sums": legs["fp32"]["integrals_per_s"] /
                           legs["fp64_node_sums"]["integrals_per_s"]},
+        "errors_vs_fp64_value_table_all_outputs": all_vs_fp64,
         "p99_ms": serving["fp64_load_80"]["p99_ms"] if serving else None,
         "legs": legs,
         "table_build_ms": table_ms,
