@@ -381,6 +381,32 @@ def test_fused_eight_word_slab(pw, Q):
         t.set_layout(0, 0)
 
 
+def test_reconstruct_offset_views_leave_neighbours(pw, tables):
+    """Quadruples and outputs handed over as views into larger buffers (a
+    ragged last chunk in the fused schedule, whose loads and stores are
+    bounded by the chunk): the results are those of contiguous copies bit
+    for bit, and no word outside the output view is written."""
+    import torch
+    t = tables(169, 96)
+    n = 20001
+    quads = workloads.uniform_quads(t.N, n + 3, seed=77)
+    dq = _dev(quads, torch.int32)
+    t.set_direct_max(0)
+    try:
+        for prec in (pw.FP64, pw.MIXED, pw.FP32):
+            assert t.fused(prec)
+            ref = t.reconstruct(dq[3:].clone(), precision=prec)
+            big = torch.full((n + 4101,), 7.25, dtype=torch.float64, device="cuda")
+            got = t.reconstruct(dq[3:], big[5:5 + n], precision=prec)
+            t.sync()
+            assert torch.equal(got, ref)
+            assert bool((big[:5] == 7.25).all()) and bool((big[5 + n:] == 7.25).all())
+        o = P.setup(169, 96)
+        _check_reconstruct(pw, t, o, quads[3:3 + 2000], label="offset views")
+    finally:
+        t.set_direct_max(DIRECT_DEFAULT)
+
+
 def test_reconstruct_empty(pw, tables):
     import torch
     t = tables(9, 48)
