@@ -286,9 +286,11 @@ PWC_API pwc_status pwc_table_info(const pwc_table *t, int64_t *N, int *nmax, int
  * list of n <= direct_max quadruples with four lanes per quadruple reading
  * the tables from global memory (Eq. 14 over all nodes in one launch);
  * longer lists run the node-pass kernels.  The two agree to rounding.  The
- * default is 524288 (about where the two take equal time on MI355X); 0 sends
- * every list through the node passes.  n must lie in [0, 1048576]
- * (PWC_ERR_ARG otherwise).  Must not overlap a reconstruction that uses the
+ * default is 524288 for a table whose node sums run fused (pwc_table_fused
+ * for PWC_FP64; about where the two take equal time on MI355X) and 1048576,
+ * the largest, for the others, whose separate node passes the direct kernel
+ * outruns up to that size; 0 sends every list through the node passes.  n
+ * must lie in [0, 1048576] (PWC_ERR_ARG otherwise).  Must not overlap a reconstruction that uses the
  * same table.
  */
 PWC_API pwc_status pwc_table_set_direct_max(pwc_table *t, int64_t n);
@@ -494,8 +496,8 @@ PWC_API pwc_status pwc_sync(const pwc_table *t, void *stream);
  * request holds are evicted to make room) and its kernels are launched on
  * the slot's stream, so work of different requests and tables overlaps on
  * the device.  A small reconstruction (at most the table's direct-kernel
- * size, pwc_table_set_direct_max: 524288 quadruples for the tables the
- * server builds) admitted from the head of the queue takes along up to 23
+ * size, pwc_table_set_direct_max: the default of each table the server
+ * builds) admitted from the head of the queue takes along up to 23
  * later queued small reconstructions whose tables are resident, and one
  * launch of the direct kernel serves them all, each with its own table,
  * precision, buffers and error word.  A request whose table alone exceeds the budget fails with

@@ -470,12 +470,15 @@ pwc_status plan_table(const double sides[3], int n2max, const pwc_mesh &m, Table
         t.n_cu <= 0)
         t.n_cu = 256;
     t.flm.E = t.fls.E = t.fl.E;
-    t.direct_max = kDirectDefault;
     const size_t maps = fold_maps_bytes(t.N, t.nd);
     if (!plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP64, maps, t.fl) || !plan_fold(t.Q, t.fl.E, 0, 0, PWC_MIXED, maps, t.flm) ||
         !plan_fold(t.Q, t.fl.E, 0, 0, PWC_FP32, maps, t.fls) ||
         !plan_chunks(t.Q, static_cast<size_t>(t.ndir) * (t.K + 1) * 8, &t.dl.c, &t.dl.nchunk))
         return PWC_ERR_ARG;
+    // The direct kernel beats the fused node sums up to about 2^19
+    // quadruples, and the separate node passes (each restaging a slab) up to
+    // the largest list it takes.
+    t.direct_max = fused_layout(t.fl, maps) ? kDirectDefault : kDirectMaxN;
     // Exchange kernel table when it fits in one workgroup's LDS: K(a <= b <= c)
     // for a cube (the three directions share one table), K(a, b, c) for a box.
     const int64_t n1 = t.K + 1;

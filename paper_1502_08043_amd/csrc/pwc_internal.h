@@ -251,7 +251,7 @@ struct DirectJob {
     uint32_t block0;          // first block of the job (set by launch_direct)
 };
 constexpr int kDirectMaxJobs = 24;
-constexpr int64_t kDirectDefault = int64_t(1) << 19;  // default pwc_reconstruct threshold
+constexpr int64_t kDirectDefault = int64_t(1) << 19;  // direct-kernel threshold of tables with fused node sums
 constexpr int64_t kDirectMaxN = int64_t(1) << 20;   // quadruples per job
 struct DirectBatch {
     DirectJob job[kDirectMaxJobs];

@@ -201,11 +201,11 @@ def test_box_requests_match_the_library(pw):
 
 
 def test_bad_request_beside_a_good_one_on_the_same_table(pw):
-    """Two node-pass requests (above the direct-kernel size) on one table run
-    in two slots at once; the one with a bad index fails and the other does
-    not, as each slot raises its own error word."""
+    """Two node-pass requests (above the largest direct-kernel size) on one
+    table run in two slots at once; the one with a bad index fails and the
+    other does not, as each slot raises its own error word."""
     import torch
-    n = 700_000
+    n = 1_100_000
     good = torch.from_numpy(workloads.uniform_quads(1045, n, seed=21)).cuda()
     bad = good.clone()
     bad[n // 2, 0] = -5
@@ -306,26 +306,39 @@ def test_served_outputs_match_the_oracle(pw):
         M = int((r2 <= 4).sum())
         f = g.uniform(0.25, 1.0, M)
         for prec in (pw.FP64, pw.MIXED, pw.FP32):
-            for n in (3001, 40_000, 600_000):              # two direct sizes, one above it
+            for n in (3001, 40_000, 1_100_000):            # two direct sizes, one above any
                 quads = workloads.lookup_stream(N, M, n, seed=int(g.integers(1 << 30)))
                 jobs.append(("rec", key, L, mesh, prec, quads, None))
             if prec == pw.FP32:
                 continue                                   # reconstruction only
             for algo in (pw.PAIR_AUTO, pw.PAIR_NODESUM):
                 jobs.append(("ene", key, L, mesh, prec, np.arange(M, dtype=np.int32), (algo, f)))
-    outs, tickets = [], []
+    # Inputs staged first, so that the requests go in back to back and queue.
+    staged = []
+    for kind, key, L, mesh, prec, x, extra in jobs:
+        dx = torch.from_numpy(x).cuda()
+        fd = torch.from_numpy(extra[1]).cuda() if kind == "ene" else None
+        out = torch.full((len(x) if kind == "rec" else 2,), -1.0, dtype=torch.float64, device="cuda")
+        staged.append((dx, fd, out))
+    torch.cuda.synchronize()
+    outs = [o for _, _, o in staged]
+    tickets = []
     with pw.Server(2 << 30, max_inflight=6) as srv:
-        for kind, key, L, mesh, prec, x, extra in jobs:
-            dx = torch.from_numpy(x).cuda()
+        # Every table resident first: queued small reconstructions then join
+        # the direct launch of the one at the head of the queue.
+        warm = {}
+        for (kind, key, L, mesh, prec, x, extra), (dx, _, _) in zip(jobs, staged):
+            if kind == "rec" and key not in warm:
+                warm[key] = srv.submit_reconstruct(L, key[1], dx[:64].clone(),
+                                                   torch.empty(64, dtype=torch.float64, device="cuda"),
+                                                   mesh=mesh)
+        assert all(srv.wait(t).status == pw.OK for t in warm.values())
+        for (kind, key, L, mesh, prec, x, extra), (dx, fd, out) in zip(jobs, staged):
             if kind == "rec":
-                out = torch.full((len(x),), -1.0, dtype=torch.float64, device="cuda")
                 tickets.append(srv.submit_reconstruct(L, key[1], dx, out, precision=prec, mesh=mesh))
             else:
-                out = torch.full((2,), -1.0, dtype=torch.float64, device="cuda")
-                fd = torch.from_numpy(extra[1]).cuda()
                 tickets.append(srv.submit_energies(L, key[1], dx, out, f=fd, precision=prec,
                                                    algo=extra[0], mesh=mesh))
-            outs.append(out)
         results = [srv.wait(t) for t in tickets]
         st = srv.stats()
     assert all(r.status == pw.OK for r in results)
@@ -397,18 +410,19 @@ def test_scratch_is_priced_by_the_path_taken(pw):
     assert np.array_equal(outs["kt"].cpu().numpy(), e_kt)
     assert torch.equal(o_big, r_big) and torch.equal(o_small, r_small)
 
-    # The box's node passes keep the decoded stream: 8 MB for 1e6 quadruples.
+    # The box's node passes keep the decoded stream: 8.8 MB for 1.1e6
+    # quadruples (above the largest direct-kernel size).
     sides = (1.0, 1.3, 0.8)
     pw.release_cached_memory()
     with pw.Table.box(*sides, 169, 64) as t:
         tbb = t.device_bytes
-        t.set_direct_max(0)
-        r_box = t.reconstruct(big)
+        big_box = torch.from_numpy(workloads.uniform_quads(t.N, 1_100_000, seed=10)).cuda()
+        r_box = t.reconstruct(big_box)
         t.sync()
     for budget, status in ((tbb + 600_000, pw.ERR_NOMEM), (tbb + 12_000_000, pw.OK)):
-        o_box = torch.full((1_000_000,), -1.0, dtype=torch.float64, device="cuda")
+        o_box = torch.full((1_100_000,), -1.0, dtype=torch.float64, device="cuda")
         with pw.Server(budget, max_inflight=2) as srv:
-            got = srv.wait(srv.submit_reconstruct(sides, 169, big, o_box, n_nodes=64)).status
+            got = srv.wait(srv.submit_reconstruct(sides, 169, big_box, o_box, n_nodes=64)).status
         say(f"[server] box table {tbb} B + {budget - tbb} B: {got}")
         assert got == status
         if status == pw.OK:
