@@ -58,7 +58,10 @@ namespace pwc {
 // The first pass decodes the stream as well, about kDecodeExtra more.  The
 // one-lane layout runs fused (one launch, no stream between passes) when
 // its slab and the decode maps fit in LDS together: its cost is then P
-// times the fused figures, measured the same way for the whole call.
+// times the fused figures, measured the same way for the whole call (1e8
+// quadruples of the lookup stream: 2.65, 4.5 and 1.6 ms).  On uniform
+// streams of 1045 to 7153 planewaves the fused FP64 call beats the 8x2
+// passes by 11-16% from Q = 96 on and trails them by 4% at Q = 64.
 // lanes = words = 0 takes the cheapest layout whose slab fits; otherwise
 // the given one.
 bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, size_t maps_bytes, FoldLayout &fl) {
@@ -67,7 +70,7 @@ bool plan_fold(int Q, int E, int lanes, int words, pwc_precision p, size_t maps_
         {8, 2, 0.49, 0.83, 0.32}, {16, 1, 0.61, 0.97, 0.40}, {1, 8, 0.575, 0.835, 0.33},
         {4, 2, 0.58, 0.86, 0.34}, {2, 4, 0.58, 0.79, 0.33}, {8, 1, 0.66, 1.02, 0.42},
         {4, 1, 0.80, 1.10, 0.50}};
-    static const struct { double fp64, mixed, fp32; } kFused = {0.58, 0.73, 0.33};
+    static const struct { double fp64, mixed, fp32; } kFused = {0.44, 0.75, 0.27};
     constexpr double kPassStream = 0.30;   // ms per pass of 1e8 quadruples
     constexpr double kDecodeExtra = 0.25;  // ms per call of 1e8 quadruples
     const int npw = nodes_per_word(p);

@@ -239,7 +239,7 @@ C16 = [(8, 1), (4, 2), (2, 4), (1, 8)]             # 16 nodes per pass
 # (n2max, Q, default (lanes, words) for FP64 and for split-FP32, bytes per
 #  decoded quadruple, layouts whose slab fits)
 LAYOUTS = [
-    (40, 64, (8, 2), (1, 8), 4, ALL_LAYOUTS),
+    (40, 64, (1, 8), (1, 8), 4, ALL_LAYOUTS),
     (169, 96, (1, 8), (1, 8), 4, C16 + [(4, 1)]),
     (256, 32, (1, 8), (2, 4), 8, C16 + [(4, 1)]),
     (400, 128, (4, 1), (4, 1), 8, [(4, 1)]),
