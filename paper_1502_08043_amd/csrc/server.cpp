@@ -29,6 +29,8 @@
 #include <mutex>
 #include <new>
 #include <thread>
+
+#include <sys/prctl.h>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -426,6 +428,11 @@ bool pwc_server::admit() {
 
 void pwc_server::run() {
     (void)hipSetDevice(device);
+    // While requests run, the loop polls their events every 20 us; Linux's
+    // default timer slack (50 us) would stretch each of those waits to about
+    // 70 us, which is most of a small request's latency (p50 0.10 ms against
+    // 0.07 ms with 1 us).
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL);
     for (;;) {
         const bool a = reap();
         const bool b = admit();
