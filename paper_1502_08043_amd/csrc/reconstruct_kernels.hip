@@ -6,8 +6,9 @@
 // so the table is stored folded: E orbit representatives per node (about a
 // quarter of nd^2).  A rectangular box stacks its three direction tables
 // (E = 3 E1 rows, direction d at rows d E1 ..), and the decode offsets each
-// direction's entry into its own table; the passes see one taller slab.  In HBM the folded table is [E][Qp]: the Qp (Q padded to
-// a multiple of 32, zero) node values of one entry are contiguous.  Each entry
+// direction's entry into its own table; the passes see one taller slab.
+// In HBM the folded table is [E][Qp]: the Qp (Q padded to a multiple of 32,
+// zero) node values of one entry are contiguous.  Each entry
 // carries W_q^(1/3) (the mesh weights are positive), so a node term is the
 // plain product of three entries.
 //
@@ -717,7 +718,8 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
                                                   (t * kThreads + static_cast<int>(threadIdx.x)) * 8, 0, kCachePolicyNT);
     };
     uint4 pre[SPT];
-    auto stage = [&]() __attribute__((always_inline)) {   // the staged range into LDS, once every wave is done with the last
+    // The staged range into LDS, once every wave is done with the last.
+    auto stage = [&]() __attribute__((always_inline)) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
