@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_rec_direct(DirectBatch b) {
     if (static_cast<unsigned>(v.x) >= N || static_cast<unsigned>(v.y) >= N ||
         static_cast<unsigned>(v.z) >= N || static_cast<unsigned>(v.w) >= N) {
         if (s == 0) {
-            atomicOr(J.err, 1);
+            raise_error(J.err);
             J.out[e] = NAN;
         }
         return;

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kGtThreads) void k_rec_gauss(GaussRecArgs a) {
         if (static_cast<unsigned>(v.x) >= N || static_cast<unsigned>(v.y) >= N ||
             static_cast<unsigned>(v.z) >= N || static_cast<unsigned>(v.w) >= N) {
             if (s == 0) {
-                atomicOr(a.err, 1);
+                raise_error(a.err);
                 a.out[e] = NAN;
             }
             continue;

@@ -71,7 +71,7 @@ __device__ __forceinline__ bool pair_setup(const PairArgs &a, int ti, int tj, in
     const int oi = a.occ[i], oj = a.occ[j];
     if (static_cast<unsigned>(oi) >= static_cast<unsigned>(a.N) ||
         static_cast<unsigned>(oj) >= static_cast<unsigned>(a.N)) {
-        atomicOr(a.err, 1);
+        raise_error(a.err);
         return false;
     }
     const int vi = a.basis[oi], vj = a.basis[oj];
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_ktab(KtArgs a) {
             v = a.basis[o];
             wv = w;
         } else {
-            atomicOr(a.err, 1);
+            raise_error(a.err);
             wv = NAN;
         }
     };

@@ -60,6 +60,13 @@ struct FoldLayout {
     int c = 0;          // nodes per pass, npw G W (npw = 2 nodes per word, 4 for FP32)
     int nchunk = 0;     // passes P = ceil(Q / c)
 };
+// A kernel that meets a bad index sets its error word to 1 and never reads
+// it: a plain store at system scope, since the word may be mapped host
+// memory (the server's), where read-modify-write atomics would need PCIe
+// atomics.
+__device__ __forceinline__ void raise_error(int *err) {
+    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 // Nodes in one 16-byte word of the folded table of precision p.
 inline int nodes_per_word(pwc_precision p) { return p == PWC_FP32 ? 4 : 2; }
 inline bool valid_precision(int p) { return p == PWC_FP64 || p == PWC_MIXED || p == PWC_FP32; }

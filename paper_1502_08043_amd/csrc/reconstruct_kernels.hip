@@ -324,7 +324,7 @@ __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const in
     const unsigned N = static_cast<unsigned>(a.N);
     if (static_cast<unsigned>(v.x) >= N || static_cast<unsigned>(v.y) >= N ||
         static_cast<unsigned>(v.z) >= N || static_cast<unsigned>(v.w) >= N) {
-        atomicOr(a.err, 1);
+        raise_error(a.err);
         return PK::flagged();
     }
     const int K = a.K, nd = a.nd;

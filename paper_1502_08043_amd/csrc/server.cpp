@@ -82,8 +82,11 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     double *h_e = nullptr;     // pinned [2]
-    int *h_err = nullptr;      // pinned [kDirectMaxJobs]: error word per member
-    int *d_err = nullptr;      // device [kDirectMaxJobs]: error word per member
+    // Error word per member, in mapped pinned host memory: cleared by the
+    // host before the launch, set by the kernels, read by the host once the
+    // slot's event has fired (no device copy either way).
+    int *h_err = nullptr;      // [kDirectMaxJobs], host address
+    int *d_err = nullptr;      // the same words, device address
     bool busy = false;
     bool direct = false;       // members share one direct-kernel launch
     std::vector<Member> members;
@@ -377,16 +380,14 @@ bool pwc_server::admit() {
                                            static_cast<pwc_precision>(m.r.prec), s.d_err + i);
                 wait_ready(m.r, m.tab->t->t);
             }
-            if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int) * b.njobs, s.stream);
+            std::memset(s.h_err, 0, sizeof(int) * b.njobs);
             if (e == hipSuccess) e = pwc::launch_direct(b, s.stream);
             for (const Member &m : s.members) pwc::note_use(m.tab->t->t, s.stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int) * b.njobs, hipMemcpyDeviceToHost, s.stream);
         } else {
             // The slot's own error word, not the table's: requests on one
             // table may run in several slots at once.
             wait_ready(p.r, t);
-            if (e == hipSuccess) e = hipMemsetAsync(s.d_err, 0, sizeof(int), s.stream);
+            s.h_err[0] = 0;
             if (e == hipSuccess && p.r.kind == PWC_REQ_RECONSTRUCT) {
                 e = pwc::launch_reconstruct(t, p.r.d_idx, p.r.n, p.r.d_out,
                                             static_cast<pwc_precision>(p.r.prec), s.stream,
@@ -400,8 +401,6 @@ bool pwc_server::admit() {
                     e = hipMemcpyAsync(s.h_e, p.r.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
             }
             pwc::note_use(t, s.stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s.h_err, s.d_err, sizeof(int), hipMemcpyDeviceToHost, s.stream);
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e == hipSuccess) {
@@ -466,14 +465,14 @@ pwc_status pwc_server_create(size_t hbm_budget_bytes, int max_inflight, pwc_serv
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_e), 2 * sizeof(double));
         if (e == hipSuccess)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_err), sizeof(int) * pwc::kDirectMaxJobs);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_err), sizeof(int) * pwc::kDirectMaxJobs);
+            e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_err), sizeof(int) * pwc::kDirectMaxJobs,
+                              hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.d_err), sl.h_err, 0);
     }
     if (e != hipSuccess) {
         for (Slot &sl : s->slots) {
             if (sl.h_e) (void)hipHostFree(sl.h_e);
             if (sl.h_err) (void)hipHostFree(sl.h_err);
-            if (sl.d_err) (void)hipFree(sl.d_err);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
@@ -617,7 +616,6 @@ pwc_status pwc_server_destroy(pwc_server *s) {
         (void)hipStreamSynchronize(sl.stream);
         (void)hipHostFree(sl.h_e);
         (void)hipHostFree(sl.h_err);
-        (void)hipFree(sl.d_err);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kVrThreads) void k_rec_values(RecValArgs a) {
             const int4 t = q[k];
             if (static_cast<unsigned>(t.x) >= N || static_cast<unsigned>(t.y) >= N ||
                 static_cast<unsigned>(t.z) >= N || static_cast<unsigned>(t.w) >= N) {
-                atomicOr(a.err, 1);
+                raise_error(a.err);
                 continue;
             }
             const int ni = basis[t.x], nj = basis[t.y], nk = basis[t.z], nl = basis[t.w];
