@@ -45,7 +45,7 @@ The JSON line also carries
                    64 MiB budget, and FP64 against split-FP32.
 
     python bench.py [--steps K] [--warmup W] [--kernel-reps R] [--gpus 1] [--no-cpu-baseline]
-                    [--serve-requests R | --no-serve] [--no-configs] [--no-fixed-error]
+                    [--serve-requests R | --no-serve] [--no-configs] [--no-fixed-error] [--no-per-half]
     python bench.py --pmc-workload     # the short run the counter profiles use
 """
 import argparse
@@ -95,6 +95,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
+    ap.add_argument("--no-per-half", action="store_true",
+                    help="skip the per-half timings (kernel profiles then hold 1e8-quadruple calls only)")
     ap.add_argument("--pmc-workload", action="store_true")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the code hash the recorded counter traffic is keyed on")
@@ -700,7 +702,8 @@ def main():
         log(f"[bench] {name} per half: uniform {res['uniform']['reconstruct_ms']:.3f} ms, "
             f"occupied {res['occupied']['reconstruct_ms']:.3f} ms")
         return res
-    legs["fp64"]["per_half"] = per_half("fp64", pw.FP64)
+    if not args.no_per_half:
+        legs["fp64"]["per_half"] = per_half("fp64", pw.FP64)
     log(f"[bench] fp64 values: build {legs['fp64']['value_build_ms']:.3f} ms "
         f"({nvalues} values), reads {legs['fp64']['reconstruct_ms']:.3f} ms")
     t.free_values()
@@ -708,7 +711,8 @@ def main():
         t.reconstruct(quads, out[name], precision=prec)
         legs[name]["reconstruct_ms"] = timed(lambda: t.reconstruct(quads, out[name], precision=prec),
                                              args.kernel_reps)
-        legs[name]["per_half"] = per_half(name, prec)
+        if not args.no_per_half:
+            legs[name]["per_half"] = per_half(name, prec)
         # per launch: decode, then the node passes
         stages = np.array([t.reconstruct_profile(quads, out[name], precision=prec)[1]
                            for _ in range(args.kernel_reps)]).mean(axis=0)
