@@ -64,8 +64,8 @@
 //
 // Fused schedule.  When the table's layout is the one-lane one and the
 // basis and fold map fit in LDS beside its slab, one launch does all the
-// passes (k_rec_fused): a workgroup decodes a chunk of 6 quadruples per
-// lane (5 when the slab takes 8 words per lane) into registers, keeps their
+// passes (k_rec_fused): a workgroup decodes a chunk of 8 quadruples per
+// lane (6 when the slab takes 8 words per lane) into registers, keeps their
 // partial sums there, and for each node range restages the slab from L2
 // (the whole folded table, 0.56 MB at 9171 planewaves and Q = 96, stays
 // resident there) and adds its terms.  The stream is then read once and the
@@ -618,8 +618,8 @@ constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int kCachePolicyNT = 2;
 
 // Quadruples per lane and chunk (NT): as many as fit in registers beside the
-// staged slab words, 6 beside 6 words, 5 beside 8; one more spills.
-constexpr int fused_chunk(int spt) { return spt <= 6 ? 6 : 5; }
+// staged slab words, 8 beside 6 words, 6 beside 8 (10 beside 6 spill).
+constexpr int fused_chunk(int spt) { return spt <= 6 ? 8 : 6; }
 
 // An empty register constraint: the compiler must assume the value is read
 // and changed here, so what feeds it is computed before this point and what

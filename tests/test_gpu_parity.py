@@ -355,8 +355,8 @@ EIGHT_WORD = {
 
 @pytest.mark.parametrize("Q", sorted(EIGHT_WORD))
 def test_fused_eight_word_slab(pw, Q):
-    """The fused kernels that stage 8 slab words per lane (and hold 5
-    quadruples per lane, not 6): bit for bit the separate launches, and
+    """The fused kernels that stage 8 slab words per lane (and hold 6
+    quadruples per lane, not 8): bit for bit the separate launches, and
     within the bar of the oracle, on a ragged stream."""
     import torch
     n2max = 200
