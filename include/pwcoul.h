@@ -314,7 +314,8 @@ PWC_API pwc_status pwc_table_layout(const pwc_table *t, pwc_precision p, int *la
  * fold map fit in one workgroup's LDS, every pass in one launch with the
  * partial sums in registers and no decoded stream (pwc_reconstruct and
  * pwc_reconstruct_noalloc; pwc_reconstruct_profile always runs the separate
- * launches, with the same results bit for bit); else 0.
+ * launches, whose results agree to the rounding of the order of each
+ * quadruple's node terms, bit for bit with one node range); else 0.
  */
 PWC_API pwc_status pwc_table_fused(const pwc_table *t, pwc_precision p, int *fused);
 

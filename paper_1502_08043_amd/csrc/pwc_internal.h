@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <memory>
@@ -76,13 +77,25 @@ constexpr int kLdsMax = 160 * 1024;          // LDS per workgroup on gfx950
 inline size_t fold_maps_bytes(int64_t N, int nd) {
     return sizeof(int32_t) * static_cast<size_t>(N) + sizeof(int16_t) * static_cast<size_t>(nd) * nd;
 }
+// Quadruples per lane in a chunk of the fused launch (1024 lanes): as many as
+// fit in registers beside the staged slab words, 8 beside 6 words per lane,
+// 6 beside 8.
+inline int fused_chunk_quads(int E) { return E * 8 <= 6 * 1024 ? 8 : 6; }
+// LDS area in front of the decode maps in the fused launch: the slab, and
+// with several node ranges at least the exchange area of the wave-wide
+// pairing (8 bytes per quadruple of a chunk), which reuses it.
+inline size_t fused_area_bytes(const FoldLayout &fl) {
+    const size_t slab = static_cast<size_t>(fl.E) * 128;
+    const size_t xchg = static_cast<size_t>(1024) * fused_chunk_quads(fl.E) * 8;
+    return fl.nchunk > 1 ? std::max(slab, xchg) : slab;
+}
 // True when a reconstruction with layout fl runs as one fused launch: the
-// one-lane layout (1 lane, 8 words of 16 bytes per row), its slab and the
-// decode maps together in one workgroup's LDS, at most 8 slab words staged
-// per lane.  It keeps no decoded stream.
+// one-lane layout (1 lane, 8 words of 16 bytes per row), its slab (or the
+// exchange area) and the decode maps together in one workgroup's LDS, at
+// most 8 slab words staged per lane.  It keeps no decoded stream.
 inline bool fused_layout(const FoldLayout &fl, size_t maps_bytes) {
     return fl.G == 1 && fl.W == 8 && fl.E <= 1024 &&
-           static_cast<size_t>(fl.E) * 128 + maps_bytes <= static_cast<size_t>(kLdsMax);
+           fused_area_bytes(fl) + maps_bytes <= static_cast<size_t>(kLdsMax);
 }
 constexpr int kGaussMaxN1 = PWC_GAUSS_MAX_N1;
 constexpr int kGaussMaxPairs = PWC_GAUSS_MAX_PAIRS;

@@ -73,9 +73,11 @@
 // pass), no decoded stream is stored, the next range's slab is loaded into
 // registers while the current one is read, and the next chunk's quadruples
 // while the last range is.  Larger chunks spill registers.  A last range
-// with fewer real nodes reads only its first 1, 2 or 4 words.  The
-// arithmetic and its order are those of the separate launches, so both
-// schedules give the same bits.
+// with fewer real nodes reads only its first 1, 2 or 4 words.  With several
+// ranges the chunk's quadruples are paired wave-wide (pair_wave) rather than
+// slot by slot: a lane's position sets the order of its word reads and of
+// each triple product, so the two schedules agree to that rounding, and
+// bit for bit with one range.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -450,6 +452,60 @@ __device__ __forceinline__ int pair_lane(int cls) {
     return ((pair >> 4) << 5) | i | (side ? (second ? 16 : 24) : (second ? 8 : 0));
 }
 
+// Wave-wide pairing of a fused chunk: the wave's 64 NT quadruples (slot t of
+// every lane, t < NT) dealt at once, in pair_lane's order (matched pairs of
+// classes 0 and 3, then of 1 and 2, then the ones left over), pair P going
+// to slot P / 32 at the lanes pair_lane gives pair P mod 32.  Dealt per slot,
+// a wave's 64 quadruples leave about 9 without a complement, which put a
+// conflict cycle on most reads of every slot; dealt over 64 NT, the count
+// left over grows as the square root, and all of them sit in the last
+// slots.  pk[t]: this lane's quadruple of slot t; returns in dest[t] the
+// position (slot 64 + lane) that evaluates it.  The class ballots are taken
+// again in the second sweep rather than kept (registers).
+template <typename PK, int NT>
+__device__ __forceinline__ void pair_wave(const typename PK::T (&pk)[NT], int (&dest)[NT]) {
+    int n1 = 0, n2 = 0, n3 = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = PK::odd(pk[t]);
+        const uint64_t lo = __builtin_amdgcn_ballot_w64(c & 1), hi = __builtin_amdgcn_ballot_w64(c & 2);
+        n3 += __popcll(lo & hi);
+        n1 += __popcll(lo & ~hi);
+        n2 += __popcll(~lo & hi);
+    }
+    const int n0 = 64 * NT - n1 - n2 - n3;
+    const int m03 = min(n0, n3), m12 = min(n1, n2), l03 = n0 + n3 - 2 * m03;
+    int b0 = 0, b1 = 0, b2 = 0, b3 = 0;   // quadruples of each class in the earlier slots
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = PK::odd(pk[t]);
+        const uint64_t lo = __builtin_amdgcn_ballot_w64(c & 1), hi = __builtin_amdgcn_ballot_w64(c & 2);
+        const bool outer = c == 0 || c == 3;
+        const uint32_t m1 = 0u - static_cast<uint32_t>(c & 1), m2 = 0u - static_cast<uint32_t>((c >> 1) & 1);
+        const uint32_t same_lo = ~((static_cast<uint32_t>(lo) ^ m1) | (static_cast<uint32_t>(hi) ^ m2));
+        const uint32_t same_hi = ~((static_cast<uint32_t>(lo >> 32) ^ m1) | (static_cast<uint32_t>(hi >> 32) ^ m2));
+        const int before = c == 0 ? b0 : c == 1 ? b1 : c == 2 ? b2 : b3;
+        const int r = before + __builtin_amdgcn_mbcnt_hi(same_hi, __builtin_amdgcn_mbcnt_lo(same_lo, 0));
+        const int m = outer ? m03 : m12;
+        int pair, side;
+        if (r < m) {
+            pair = (outer ? 0 : m03) + r;
+            side = c >= 2;
+        } else {
+            const int k = (outer ? 0 : l03) + r - m;
+            pair = m03 + m12 + (k >> 1);
+            side = k & 1;
+        }
+        const int p = pair & 31, i = p & 7, second = (p >> 3) & 1;
+        dest[t] = (pair >> 5) * 64 + (((p >> 4) << 5) | i | (side ? (second ? 16 : 24) : (second ? 8 : 0)));
+        const int c3 = __popcll(lo & hi), c1 = __popcll(lo & ~hi), c2 = __popcll(~lo & hi);
+        b0 += 64 - c1 - c2 - c3;
+        b1 += c1;
+        b2 += c2;
+        b3 += c3;
+    }
+}
+
 // One node pass.  LDS: the slab [E][G W] of 16-byte words (nodes q0 ..
 // q0 + c - 1 of every folded entry).  Lane s of group g reads, for each of
 // its R quadruples e = base + r NG + g, its W words of the three rows.
@@ -618,7 +674,8 @@ constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int kCachePolicyNT = 2;
 
 // Quadruples per lane and chunk (NT): as many as fit in registers beside the
-// staged slab words, 8 beside 6 words, 6 beside 8 (10 beside 6 spill).
+// staged slab words, 8 beside 6 words, 6 beside 8 (10 beside 6 spill); the
+// host's fused_chunk_quads gives the same count.
 constexpr int fused_chunk(int spt) { return spt <= 6 ? 8 : 6; }
 
 // An empty register constraint: the compiler must assume the value is read
@@ -677,7 +734,18 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     __shared__ uint4 lds_raw[kLdsMax / 16];
     constexpr int ROWB = 8 * 16;
     const int words = a.E * 8;
-    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw + words);
+    // Several ranges: the slab area doubles as the exchange area of the
+    // wave-wide pairing (8 bytes per quadruple, each wave its own part),
+    // used between a chunk's last range and the next chunk's first stage.
+    constexpr int XWORDS = kThreads * NT * 8 / 16;
+    // This lane's 4-byte (x = 4) or 8-byte (x = 8) entry of slot 0 in the
+    // wave's part, formed where it is used (not held through the loop).
+    auto xslot0 = [&](int x) __attribute__((always_inline)) {
+        uint32_t i = threadIdx.x;
+        opaque(i);
+        return reinterpret_cast<char *>(lds_raw) + (i >> 6) * (64 * NT * 8) + (i & 63) * x;
+    };
+    int32_t *lbasis = reinterpret_cast<int32_t *>(lds_raw + (MULTI ? max(words, XWORDS) : words));
     int16_t *lfold = reinterpret_cast<int16_t *>(lbasis + a.N);
     for (int i = threadIdx.x; i < a.N; i += kThreads) lbasis[i] = a.basis[i];
     for (int i = threadIdx.x; i < a.nd * a.nd; i += kThreads) lfold[i] = static_cast<int16_t>(a.fold[i]);
@@ -780,18 +848,43 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     };
 
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n; base += step) {
-        // Decode and pair: lane dest[t] evaluates this lane's quadruple t.
+        // Decode and pair.  Several ranges: position dest[t] (slot 64 +
+        // lane) of the wave evaluates this lane's quadruple t, and the packed
+        // words go there through the exchange area; one range: lane dest[t]
+        // of slot t does, and the word goes by one permute.
         int dest[NT];
         const int len = chunk_len(base);
+        if constexpr (MULTI) {
+            T pk[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
-            const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
-            const T pk = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
-            dest[t] = pair_lane(PK::odd(pk));
-            ev[t] = PK::send(pk, dest[t]);
-            if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
-            acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
+            for (int t = 0; t < NT; ++t) {
+                const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
+                const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
+                pk[t] = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
+            }
+            pair_wave<PK, NT>(pk, dest);
+            T *xw = reinterpret_cast<T *>(xslot0(4)) - (threadIdx.x & 63);   // the wave's part
+#pragma unroll
+            for (int t = 0; t < NT; ++t) xw[dest[t]] = pk[t];
+            // The wave's own part: its LDS operations complete in order.
+            const T *xmine = reinterpret_cast<const T *>(xslot0(4));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                ev[t] = xmine[t * 64];
+                if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
+                acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
+                const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
+                const T pk = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
+                dest[t] = pair_lane(PK::odd(pk));
+                ev[t] = PK::send(pk, dest[t]);
+                if (threadIdx.x & 16) ev[t] = PK::flip(ev[t]);   // high lane of its pair
+                acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
+            }
         }
         if constexpr (MULTI) {
             for (int p = 0; p + 1 < P; ++p) {
@@ -802,17 +895,32 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
             stage();
             load_quads(base + step);
             last_range();
-            fetch_slab<SPT>(pre, slab_rsrc, row, 0);   // the next chunk's first range
         } else {
             load_quads(base + step);
             last_range();
         }
         double res[NT];
+        if constexpr (MULTI) {
+            // Every wave is done with the slab; the sums go back to their
+            // quadruples' lanes through the exchange area.
+            __syncthreads();
+            double *xmine = reinterpret_cast<double *>(xslot0(8));
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            res[t] = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2hiint(acc[t])),
-                                      __builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2loint(acc[t]))) *
-                     a.pref;
+            for (int t = 0; t < NT; ++t) xmine[t * 64] = acc[t];
+            const double *xd = reinterpret_cast<const double *>(xslot0(8)) - (threadIdx.x & 63);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) res[t] = xd[dest[t]] * a.pref;
+            // Read before the next chunk writes its packed words there (of
+            // another type: the compiler must not move those stores up).
+            __asm__ volatile("" ::: "memory");
+            fetch_slab<SPT>(pre, slab_rsrc, row, 0);   // the next chunk's first range
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                res[t] = __hiloint2double(__builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2hiint(acc[t])),
+                                          __builtin_amdgcn_ds_bpermute(dest[t] << 2, __double2loint(acc[t]))) *
+                         a.pref;
+        }
         store_results(base, res);
     }
 }

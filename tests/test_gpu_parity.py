@@ -178,6 +178,29 @@ def test_reconstruct_plain_all_occupied_quadruples(pw, tables, path):
 
 DIRECT_DEFAULT = 1 << 19
 
+# The two schedules of the node sums against each other, condition-aware:
+# the fused launch deals a chunk's quadruples to lanes wave-wide when it has
+# several node ranges, the separate launches slot by slot.  A lane's
+# position sets the order in which it adds a range's words, and the high
+# lane of a pair reads the quadruple's rows in reverse order, which
+# reassociates each node's triple product (two roundings on either side)
+# and the word sums that follow.  FP64: a few units of 2^-53 of the sum of
+# the terms' magnitudes (1e-14 leaves room); float-float: of 2^-48;
+# single FP32: products and the pairwise word sum, at most 4 roundings of
+# 2^-24 on either side, 8 * 2^-24 = 4.8e-7.  With one range the dealing is
+# the same, and so are the bits.
+SCHEDULE_TOL = {"fp64": 1e-14, "fp32": 4.8e-7, "mixed": 2e-13}
+
+
+def _same_sums(a, b, o, quads, name, ranges, L=1.0):
+    import torch
+    if ranges == 1:
+        assert torch.equal(a, b), name
+        return
+    scale = P.cond_scale(o["tau"], o["W"], o["basis"], quads, L=L)
+    d = (a - b).abs().cpu().numpy()
+    assert np.all(d <= SCHEDULE_TOL[name] * scale), (name, float((d / scale).max()))
+
 
 @pytest.mark.parametrize("path", ["direct", "passes"])
 @pytest.mark.parametrize("n", [1, 2, 255, 1023, 1024, 1025, 2047, 2048, 2049, 4097, 30001])
@@ -228,8 +251,8 @@ def test_reconstruct_profile_matches_and_times_every_launch(pw, tables):
     finally:
         t.set_direct_max(DIRECT_DEFAULT)
     out, ms = t.reconstruct_profile(q)
-    assert torch.equal(out, ref)
     lay = t.layout()
+    _same_sums(out, ref, P.setup(169, 96), q.cpu().numpy(), "fp64", lay["passes"])
     assert lay["passes"] == -(-96 // lay["nodes_per_pass"])
     assert len(ms) == 1 + lay["passes"] and np.all(ms > 0)
 
@@ -316,8 +339,9 @@ SHORT_RANGES = [
 @pytest.mark.parametrize("mesh,Q,expect", SHORT_RANGES)
 def test_fused_short_last_range(pw, mesh, Q, expect):
     """The fused schedule reads only the real words of a short last node
-    range (1, 2 or 4 of 8): bit for bit the separate launches (which read
-    the zero padding too), and within the bar of the oracle, in all three
+    range (1, 2 or 4 of 8): the separate launches' sums (which read the zero
+    padding too) to the rounding of the word order, bit for bit with one
+    range, and within the bar of the oracle, in all three
     arithmetics, on a ragged stream."""
     import torch
     n2max = 25
@@ -337,7 +361,7 @@ def test_fused_short_last_range(pw, mesh, Q, expect):
             a = t.reconstruct(dq, precision=prec)
             b, _ = t.reconstruct_profile(dq, precision=prec)
             t.sync()
-            assert torch.equal(a, b), (mesh, name)
+            _same_sums(a, b, o, quads, name, t.layout(prec)["passes"])
         _check_reconstruct(pw, t, o, quads, label=f"Q={Q} short last range")
         t.set_layout(0, 0)
 
@@ -356,8 +380,9 @@ EIGHT_WORD = {
 @pytest.mark.parametrize("Q", sorted(EIGHT_WORD))
 def test_fused_eight_word_slab(pw, Q):
     """The fused kernels that stage 8 slab words per lane (and hold 6
-    quadruples per lane, not 8): bit for bit the separate launches, and
-    within the bar of the oracle, on a ragged stream."""
+    quadruples per lane, not 8): the separate launches' sums to the rounding
+    of the word order (bit for bit with one range), and within the bar of
+    the oracle, on a ragged stream."""
     import torch
     n2max = 200
     o = P.setup(n2max, Q)
@@ -376,7 +401,7 @@ def test_fused_eight_word_slab(pw, Q):
             a = t.reconstruct(dq, precision=prec)
             b, _ = t.reconstruct_profile(dq, precision=prec)
             t.sync()
-            assert torch.equal(a, b), (Q, name)
+            _same_sums(a, b, o, quads, name, ranges)
         _check_reconstruct(pw, t, o, quads, label=f"n2max=200 Q={Q} eight-word slab")
         t.set_layout(0, 0)
 

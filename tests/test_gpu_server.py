@@ -203,10 +203,15 @@ def test_box_requests_match_the_library(pw):
 def test_bad_request_beside_a_good_one_on_the_same_table(pw):
     """Two node-pass requests (above the largest direct-kernel size) on one
     table run in two slots at once; the one with a bad index fails and the
-    other does not, as each slot raises its own error word."""
+    other does not, as each slot raises its own error word.  The fused node
+    sums pair a wave's 512 quadruples of a chunk together, so the bad one
+    moves the others of its wave to other lanes: those may differ from the
+    good request's by the rounding of their node terms' order, the rest not
+    at all."""
     import torch
     n = 1_100_000
-    good = torch.from_numpy(workloads.uniform_quads(1045, n, seed=21)).cuda()
+    good_h = workloads.uniform_quads(1045, n, seed=21)
+    good = torch.from_numpy(good_h).cuda()
     bad = good.clone()
     bad[n // 2, 0] = -5
     outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
@@ -230,8 +235,11 @@ def test_bad_request_beside_a_good_one_on_the_same_table(pw):
     assert np.array_equal(outs[1].cpu().numpy(), ref) and np.array_equal(outs[3].cpu().numpy(), ref)
     got = outs[0].cpu().numpy()
     assert np.isnan(got[n // 2])
-    keep = np.arange(n) != n // 2
-    assert np.array_equal(got[keep], ref[keep])
+    moved = np.nonzero((got != ref) & (np.arange(n) != n // 2))[0]
+    assert len(moved) < 512
+    o = P.setup(40, 64)
+    scale = P.cond_scale(o["tau"], o["W"], o["basis"], good_h[moved])
+    assert np.all(np.abs(got[moved] - ref[moved]) <= 1e-14 * scale)
     assert np.array_equal(e_good.cpu().numpy(), e_ref)
 
 
