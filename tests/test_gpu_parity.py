@@ -406,6 +406,42 @@ def test_fused_eight_word_slab(pw, Q):
         t.set_layout(0, 0)
 
 
+@pytest.mark.parametrize("kind", ["diagonal", "half_diagonal", "one_quadruple"])
+def test_fused_pairing_with_skewed_classes(pw, tables, kind):
+    """Streams whose classes cannot be paired: every (i, i, i, i) reads the
+    folded row of m = m' = 0 three times, so all its quadruples share one
+    parity class; half the stream such; one quadruple repeated.  The fused
+    node sums then deal many or all of a chunk's quadruples as left over,
+    and each result must still be its own quadruple's: against the oracle,
+    and against the separate launches within the rounding of the order of
+    the node terms, in all three arithmetics, on a ragged stream."""
+    import torch
+    t = tables(169, 96)
+    o = P.setup(169, 96)
+    n = 30001
+    draw = workloads.uniform_quads(t.N, n, seed=61)
+    if kind == "diagonal":
+        quads = np.repeat(draw[:, :1], 4, axis=1)
+    elif kind == "half_diagonal":
+        quads = draw.copy()
+        quads[: n // 2] = np.repeat(draw[: n // 2, :1], 4, axis=1)
+    else:
+        quads = np.repeat(draw[:1], n, axis=0)
+    quads = np.ascontiguousarray(quads, dtype=np.int32)
+    dq = _dev(quads, torch.int32)
+    t.set_direct_max(0)
+    try:
+        for name, prec in (("fp64", pw.FP64), ("mixed", pw.MIXED), ("fp32", pw.FP32)):
+            assert t.fused(prec) and t.layout(prec)["passes"] > 1
+            a = t.reconstruct(dq, precision=prec)
+            b, _ = t.reconstruct_profile(dq, precision=prec)
+            t.sync()
+            _same_sums(a, b, o, quads, name, t.layout(prec)["passes"])
+        _check_reconstruct(pw, t, o, quads, label=f"skewed classes: {kind}")
+    finally:
+        t.set_direct_max(DIRECT_DEFAULT)
+
+
 def test_reconstruct_offset_views_leave_neighbours(pw, tables):
     """Quadruples and outputs handed over as views into larger buffers (a
     ragged last chunk in the fused schedule, whose loads and stores are
