@@ -72,9 +72,11 @@ __global__ __launch_bounds__(kDirectThreads) void k_rec_direct(DirectBatch b) {
 #pragma unroll 2
         for (int w = s; w < words; w += kDirectLanes) {
             const float4 a = x[w], c = y[w], d = z[w];
-            const float p0 = (a.x * c.x) * d.x, p1 = (a.y * c.y) * d.y;
-            const float p2 = (a.z * c.z) * d.z, p3 = (a.w * c.w) * d.w;
-            acc += static_cast<double>((p0 + p1) + (p2 + p3));
+            // the node passes' word sum: two pairs, each a rounded triple
+            // product added into the other by a fused multiply-add
+            const float s01 = fmaf(a.x * c.x, d.x, (a.y * c.y) * d.y);
+            const float s23 = fmaf(a.z * c.z, d.z, (a.w * c.w) * d.w);
+            acc += static_cast<double>(s01 + s23);
         }
         r = acc;
     } else if (!J.mixed) {

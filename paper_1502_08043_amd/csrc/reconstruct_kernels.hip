@@ -164,10 +164,14 @@ struct F32 {
     using V = float4;    // four adjacent nodes
     struct Acc { double v; };
     __device__ static void zero(Acc &a) { a.v = 0.0; }
+    // A word's four node terms summed pairwise in FP32: each pair as one
+    // rounded triple product added into the other by a fused multiply-add
+    // (at most 4 roundings of 2^-24 per term on top of the entries', as
+    // with four products and two additions, in 9 operations instead of 11).
     __device__ static void add2(Acc &a, V x, V y, V z) {
-        const float p0 = (x.x * y.x) * z.x, p1 = (x.y * y.y) * z.y;
-        const float p2 = (x.z * y.z) * z.z, p3 = (x.w * y.w) * z.w;
-        a.v += static_cast<double>((p0 + p1) + (p2 + p3));
+        const float s01 = fmaf(x.x * y.x, z.x, (x.y * y.y) * z.y);
+        const float s23 = fmaf(x.z * y.z, z.z, (x.w * y.w) * z.w);
+        a.v += static_cast<double>(s01 + s23);
     }
     __device__ static double value(const Acc &a) { return a.v; }
 };

@@ -17,9 +17,11 @@ import oracle
 TOL_FP64 = 1e-12          # condition-aware, FP64 path
 TOL_MIXED = 1e-12         # condition-aware, split-FP32 path (float-float)
 # condition-aware, single-FP32 path: each entry W^(1/3) tau rounded once to
-# FP32 (3 roundings per node term), the product (2) and the pairwise sum of a
-# four-node word (2), each at most 2^-24 relative: 7 * 2^-24 = 4.2e-7 of the
-# sum of the node terms' magnitudes; the FP64 accumulation adds ~1e-16.
+# FP32 (3 roundings per node term) and at most 4 in the pairwise sum of a
+# four-node word (the first product; the second product and the fused
+# multiply-add that adds it to its pair; the sum of the two pairs), each at
+# most 2^-24 relative: 7 * 2^-24 = 4.2e-7 of the sum of the node terms'
+# magnitudes; the FP64 accumulation adds ~1e-16.
 TOL_FP32 = 4.2e-7
 TOL_E_FP64 = 1e-12        # relative, energies
 TOL_E_MIXED = 1e-12
