@@ -124,11 +124,6 @@ struct PassArgs {
     int *err;
 };
 
-// Basis vector packed as three signed bytes of an int32.
-__device__ __forceinline__ int bx(int v) { return (v << 24) >> 24; }
-__device__ __forceinline__ int by(int v) { return (v << 16) >> 24; }
-__device__ __forceinline__ int bz(int v) { return (v << 8) >> 24; }
-
 // The folded entries carry W_q^(1/3) (the mesh weights are positive), so a
 // node term is the plain product of the three entries.
 // FP64 arithmetic: one node term is (x * y) * z added with an FMA.
@@ -334,11 +329,19 @@ __device__ __forceinline__ typename PK::T decode_one(const PassArgs &a, const in
         return PK::flagged();
     }
     const int K = a.K, nd = a.nd;
-    const int ni = basis[v.x], nj = basis[v.y], nk = basis[v.z], nl = basis[v.w];
+    const uint32_t ni = basis[v.x], nj = basis[v.y], nk = basis[v.z], nl = basis[v.w];
+    // A planewave's three components are the low three bytes of its packed
+    // word (signed).  With the sign bits flipped each byte is the component
+    // plus 128, so one addition and one subtraction form (n_k - n_i + K) in
+    // all three bytes at once: every byte stays within [0, 2K] (|n| <= 24,
+    // K = 2 nmax), so no carry or borrow crosses into the next.
+    constexpr uint32_t kSign = 0x808080u;
+    const uint32_t kk = static_cast<uint32_t>(K) * 0x010101u;
+    const uint32_t ki = ((nk ^ kSign) + kk) - (ni ^ kSign), lj = ((nl ^ kSign) + kk) - (nj ^ kSign);
     // (difference + K) lies in [0, 2K] and nd = 2K + 1 is small: 24-bit products
-    const int ix = __umul24(bx(nk) - bx(ni) + K, nd) + (bx(nl) - bx(nj) + K);
-    const int iy = __umul24(by(nk) - by(ni) + K, nd) + (by(nl) - by(nj) + K);
-    const int iz = __umul24(bz(nk) - bz(ni) + K, nd) + (bz(nl) - bz(nj) + K);
+    const int ix = __umul24(ki & 255u, nd) + (lj & 255u);
+    const int iy = __umul24((ki >> 8) & 255u, nd) + ((lj >> 8) & 255u);
+    const int iz = __umul24(ki >> 16, nd) + (lj >> 16);
     int fx = lfold ? lfold[ix] : gfold[ix];
     int fy = lfold ? lfold[iy] : gfold[iy];
     int fz = lfold ? lfold[iz] : gfold[iz];
