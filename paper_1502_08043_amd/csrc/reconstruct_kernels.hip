@@ -72,8 +72,9 @@
 // results written once (24 bytes per quadruple instead of 28 + 20 per later
 // pass), no decoded stream is stored, the next range's slab is loaded into
 // registers while the current one is read, and the next chunk's quadruples
-// while the last range is.  Larger chunks spill registers.  A last range
-// with fewer real nodes reads only its first 1, 2 or 4 words.  With several
+// while the last range is (with several ranges, decoded beside its reads).
+// Larger chunks spill registers.  A last range with fewer real nodes reads
+// only its first 1, 2 or 4 words.  With several
 // ranges the chunk's quadruples are paired wave-wide (pair_wave) rather than
 // slot by slot: a lane's position sets the order of its word reads and of
 // each triple product, so the two schedules agree to that rounding, and
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
     double acc[NT];
     // One full range: each quadruple's terms in step order, its twelve reads
     // of a half in a block of their own (more in flight would spill).
-    auto full_range = [&]() __attribute__((always_inline)) {
+    auto full_range = [&](auto after) __attribute__((always_inline)) {
         const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & 7) * 16);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -828,15 +829,17 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
             acc[t] = acc[t] + A::value(s);
             opaque(acc[t]);   // summed here, not where it is stored
             __builtin_amdgcn_sched_barrier(0);
+            after(t);
         }
     };
+    auto none = [](int) __attribute__((always_inline)) {};
     // The last range.  A short one (fewer than 8 words of real nodes) reads
     // its first WL words only, word k ^ (lane mod WL) at step k: the order in
     // which the full range meets those words, the others holding zero-weight
     // padding, so the sum is the full range's.
-    auto last_range = [&]() __attribute__((always_inline)) {
+    auto last_range = [&](auto after) __attribute__((always_inline)) {
         if constexpr (WL == 8) {
-            full_range();
+            full_range(after);
         } else {
             const uint32_t lane_r = static_cast<uint32_t>((threadIdx.x & (WL - 1)) * 16);
 #pragma unroll
@@ -850,9 +853,27 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
                 acc[t] = acc[t] + A::value(s);
                 opaque(acc[t]);
                 __builtin_amdgcn_sched_barrier(0);
+                after(t);
             }
         }
     };
+    // Several ranges: the next chunk's quadruples are decoded during the
+    // last range, quadruple t after the range's quadruple t + kDecodeLag
+    // (their loads, issued just before the range, have landed by then), so
+    // that the VALU work of the decode runs beside the range's LDS reads
+    // instead of after the chunk, when every wave would run it at once.
+    constexpr int kDecodeLag = 3;
+    T pkn[NT];
+    auto decode_one_next = [&](int t, int len) __attribute__((always_inline)) {
+        const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
+        const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
+        pkn[t] = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
+    };
+    if constexpr (MULTI) {
+        const int len0 = chunk_len(static_cast<int64_t>(blockIdx.x) * chunk);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) decode_one_next(t, len0);
+    }
 
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * chunk; base < a.n; base += step) {
         // Decode and pair.  Several ranges: position dest[t] (slot 64 +
@@ -860,19 +881,11 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
         // words go there through the exchange area; one range: lane dest[t]
         // of slot t does, and the word goes by one permute.
         int dest[NT];
-        const int len = chunk_len(base);
         if constexpr (MULTI) {
-            T pk[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
-                const bool real = t * kThreads + static_cast<int>(threadIdx.x) < len;
-                pk[t] = real ? decode_one<PK>(a, lbasis, lfold, nullptr, q) : PK::pack(0, 0, 0);
-            }
-            pair_wave<PK, NT>(pk, dest);
+            pair_wave<PK, NT>(pkn, dest);
             T *xw = reinterpret_cast<T *>(xslot0(4)) - (threadIdx.x & 63);   // the wave's part
 #pragma unroll
-            for (int t = 0; t < NT; ++t) xw[dest[t]] = pk[t];
+            for (int t = 0; t < NT; ++t) xw[dest[t]] = pkn[t];
             // The wave's own part: its LDS operations complete in order.
             const T *xmine = reinterpret_cast<const T *>(xslot0(4));
 #pragma unroll
@@ -882,6 +895,7 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
                 acc[t] = PK::flag(ev[t]) ? NAN : 0.0;   // a bad quadruple is NaN
             }
         } else {
+            const int len = chunk_len(base);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int4 q = make_int4(qn[t].x, qn[t].y, qn[t].z, qn[t].w);
@@ -897,14 +911,19 @@ __global__ __launch_bounds__(kThreads) void k_rec_fused(PassArgs a, int P) {
             for (int p = 0; p + 1 < P; ++p) {
                 stage();
                 fetch_slab<SPT>(pre, slab_rsrc, row, p + 1);   // the next range
-                full_range();
+                full_range(none);
             }
             stage();
             load_quads(base + step);
-            last_range();
+            const int len_next = chunk_len(base + step);
+            last_range([&](int t) __attribute__((always_inline)) {
+                if (t >= kDecodeLag) decode_one_next(t - kDecodeLag, len_next);
+            });
+#pragma unroll
+            for (int t = NT - kDecodeLag; t < NT; ++t) decode_one_next(t, len_next);
         } else {
             load_quads(base + step);
-            last_range();
+            last_range(none);
         }
         double res[NT];
         if constexpr (MULTI) {
